@@ -1,0 +1,486 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix, independent
+of the oracle's own formulas: printed stencils and values, a hand-assembled matrix,
+closed-form discrete solutions, brute-force dense algebra, Galerkin identities,
+invariants of the iteration and finite differences of the objective."""
+from __future__ import annotations
+
+import json
+import math
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2505_10168_amd import inputs as I
+
+GOLD = json.loads((Path(__file__).parent / "golden" / "paper_values.json").read_text())
+
+
+def uniform_level(n_el, n_t, k=1.0, c=1.0, length=1.0, t_final=0.1):
+    return O.Level(n_el, n_t, length / n_el, t_final / n_t, np.full(n_el, k), np.full(n_el, c))
+
+
+def random_level(n_el, n_t, seed, t_final=0.1):
+    rng = np.random.default_rng(seed)
+    return O.Level(n_el, n_t, 1.0 / n_el, t_final / n_t, 10 ** rng.uniform(-3, 0, n_el),
+                   rng.uniform(0.5, 2.0, n_el))
+
+
+def unit(level, n, i):
+    e = np.zeros(level.shape)
+    e[n, i] = 1.0
+    return e
+
+
+# ---------------------------------------------------------------------------------------
+# Stencil and assembly
+# ---------------------------------------------------------------------------------------
+
+def test_interior_row_equals_printed_stencil():
+    """eq. (stencil of J 1): c dx/dt [[0,0,0],[1/6,2/3,1/6],[-1/6,-2/3,-1/6]] + k/dx [[0,0,0],[-1,2,-1],[0,0,0]]
+    with rows t_{n+1}, t_n, t_{n-1} and columns x_{i-1}, x_i, x_{i+1}."""
+    k, c = 3.0, 0.7
+    lv = uniform_level(8, 6, k, c)
+    h, tau = lv.h, lv.tau
+    J = O.dense_J(lv)
+    n, i = 3, 4
+    row = J[n * 9 + i].reshape(lv.shape)
+    cm, kk = c * h / tau, k / h
+    expect = np.zeros(lv.shape)
+    expect[n, i - 1:i + 2] = cm * np.array([1 / 6, 2 / 3, 1 / 6]) + kk * np.array([-1, 2, -1])
+    expect[n - 1, i - 1:i + 2] = cm * np.array([-1 / 6, -2 / 3, -1 / 6])
+    np.testing.assert_allclose(row, expect, rtol=1e-14, atol=1e-12)
+    # the same row through the matrix-free operator
+    for dn in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            y = O.apply_J(lv, unit(lv, n + dn, i + di))
+            assert y[n, i] == pytest.approx(expect[n + dn, i + di], rel=1e-14, abs=1e-12)
+
+
+def hand_matrix_2x2():
+    """J for N_el = N_t = 2, k = (1, 3), c = (2, 5), h = 1/2, dt = 1/4, written out by
+    hand from Section 2.2 and Appendix A (DOF order (n, i), time-major)."""
+    A11, A12, A22 = 38 / 3, -13 / 3, 28 / 3       # C/dt + K on the free nodes 1, 2
+    M11, M12, M22 = 14 / 3, 5 / 3, 10 / 3         # C/dt on the free nodes
+    W = 16.0                                      # 5 * 0.5 / 0.25 + 3 / 0.5
+    J = np.zeros((9, 9))
+    idx = lambda n, i: 3 * n + i  # noqa: E731
+    for n in range(3):
+        J[idx(n, 0), idx(n, 0)] = W
+    for i in (1, 2):
+        J[idx(0, i), idx(0, i)] = W
+    # time level 1: no coupling to level 0 (eliminated Dirichlet columns)
+    J[idx(1, 1), idx(1, 1)], J[idx(1, 1), idx(1, 2)] = A11, A12
+    J[idx(1, 2), idx(1, 1)], J[idx(1, 2), idx(1, 2)] = A12, A22
+    # time level 2
+    J[idx(2, 1), idx(2, 1)], J[idx(2, 1), idx(2, 2)] = A11, A12
+    J[idx(2, 2), idx(2, 1)], J[idx(2, 2), idx(2, 2)] = A12, A22
+    J[idx(2, 1), idx(1, 1)], J[idx(2, 1), idx(1, 2)] = -M11, -M12
+    J[idx(2, 2), idx(1, 1)], J[idx(2, 2), idx(1, 2)] = -M12, -M22
+    return J
+
+
+def test_dense_J_equals_hand_assembly():
+    lv = O.Level(2, 2, 0.5, 0.25, np.array([1.0, 3.0]), np.array([2.0, 5.0]))
+    assert O.w_diri(lv) == 16.0
+    H = hand_matrix_2x2()
+    np.testing.assert_allclose(O.dense_J(lv), H, rtol=1e-14, atol=1e-13)
+    for col in range(9):
+        e = np.zeros(9)
+        e[col] = 1.0
+        np.testing.assert_allclose(O.apply_J(lv, e.reshape(3, 3)).ravel(), H[:, col], atol=1e-13)
+        np.testing.assert_allclose(O.apply_J(lv, e.reshape(3, 3), True).ravel(), H[col, :], atol=1e-13)
+    np.testing.assert_allclose(O.diag_J(lv).ravel(), np.diag(H), rtol=1e-15)
+
+
+def test_load_vector_uniform_source():
+    """q = 1 integrates to h at interior nodes, h/2 at x = L, 0 at Dirichlet DOFs."""
+    lv = uniform_level(16, 5)
+    b = O.load_vector(lv, 1.0)
+    assert np.all(b[0] == 0) and np.all(b[:, 0] == 0)
+    np.testing.assert_allclose(b[1:, 1:-1], lv.h)
+    np.testing.assert_allclose(b[1:, -1], lv.h / 2)
+    # total heat per step: integral of q over [0, L] minus the half cell at x = 0
+    np.testing.assert_allclose(b[1:].sum(axis=1), 1.0 - lv.h / 2, rtol=1e-14)
+
+
+def test_load_vector_elementwise_total():
+    """Hat functions sum to one, so sum_i b_Neu,i = sum_e q_e h; Appendix A then drops
+    node 0, which holds q_0 h / 2."""
+    lv = uniform_level(9, 4)
+    q = np.random.default_rng(2).random((5, 9))
+    b = O.load_vector(lv, q)
+    np.testing.assert_allclose(b[1:].sum(axis=1), (q[1:] * lv.h).sum(axis=1) - q[1:, 0] * lv.h / 2,
+                               rtol=1e-14)
+    np.testing.assert_allclose(b[1:, 3], lv.h / 2 * (q[1:, 2] + q[1:, 3]), rtol=1e-15)
+
+
+def test_jacobi_damping_halves_dirichlet_values():
+    """omega = 1/2 (Section 3.1): at a Dirichlet DOF J = W, so one step with b = 0 maps
+    u_D to (1 - omega) u_D = u_D / 2; eliminated columns do not feed the interior."""
+    lv = uniform_level(6, 5)
+    h = O.Hierarchy([lv], [], [], O.Options())
+    u = 1.0 - O.dirichlet_mask(lv)
+    out = O.jacobi(h, 0, u, np.zeros(lv.shape), 1)
+    np.testing.assert_array_equal(out, 0.5 * u)
+
+
+def test_design_field_averaging_method():
+    mat = O.Material(1e-3, 1.0, 0.2, 1.0, 3.0, 2.0)
+    chi = np.random.default_rng(4).random(8)
+    lv = O.make_fine_level(chi, mat, 4, 1.0, 0.1)
+    co = O.coarsen(lv, "x", O.Options(reassembly="D", material=mat))
+    cm = (chi[0::2] + chi[1::2]) / 2
+    np.testing.assert_allclose(co.k, 1e-3 + (1 - 1e-3) * cm ** 3, rtol=1e-14)
+    np.testing.assert_allclose(co.c, 0.2 + 0.8 * cm ** 2, rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------------------
+# Exact solutions
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_direct_solve_equals_dense_solve(transpose):
+    for seed in range(4):
+        lv = random_level(5 + seed, 4 + seed, seed)
+        b = np.random.default_rng(50 + seed).standard_normal(lv.shape)
+        ref = np.linalg.solve(O.dense_J(lv, transpose), b.ravel()).reshape(lv.shape)
+        np.testing.assert_allclose(O.direct_solve(lv, b, transpose), ref, rtol=1e-11, atol=1e-13)
+
+
+def sine_mode(n_el, m):
+    theta = (m + 0.5) * math.pi / n_el
+    i = np.arange(n_el + 1)
+    v = np.sin(i * theta)
+    H = np.ones(n_el + 1)
+    H[-1] = 0.5
+    return theta, v, H
+
+
+@pytest.mark.parametrize("m", [0, 3, 11])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_sine_mode_closed_form(m, transpose):
+    """Constant k = c = 1: M v = m_th H v, K v = k_th H v for v_i = sin(i th), th = (m+1/2) pi / N,
+    so b_n = beta H v gives u_n = (beta / k_th)(1 - g^n) v with g = 1 / (1 + dt k_th / m_th)
+    (J^T: the same with n counted backwards from N_t)."""
+    n_el, n_t = 24, 17
+    lv = uniform_level(n_el, n_t)
+    h, tau = lv.h, lv.tau
+    th, v, H = sine_mode(n_el, m)
+    m_th, k_th = h / 3 * (2 + math.cos(th)), 2 / h * (1 - math.cos(th))
+    g = 1 / (1 + tau * k_th / m_th)
+    beta = 0.7
+    b = np.zeros(lv.shape)
+    b[1:, :] = beta * H * v
+    b[:, 0] = 0
+    n = np.arange(n_t + 1)
+    steps = n if not transpose else (n_t - n + 1)
+    a = beta / k_th * (1 - g ** steps)
+    a[0] = 0.0
+    exact = a[:, None] * v[None, :]
+    np.testing.assert_allclose(O.direct_solve(lv, b, transpose), exact, rtol=0, atol=1e-13 * np.abs(exact).max())
+
+
+def uniform_q_closed_form(n_el, n_t, t_final=0.1):
+    """Exact discrete solution for k = c = 1, q = 1 by expanding the load in the modes."""
+    lv = uniform_level(n_el, n_t, t_final=t_final)
+    h, tau = lv.h, lv.tau
+    u = np.zeros(lv.shape)
+    ones = np.ones(n_el + 1)
+    ones[0] = 0.0
+    for m in range(n_el):
+        th, v, H = sine_mode(n_el, m)
+        coef = np.sum(v * H * ones) / np.sum(v * H * v)
+        m_th, k_th = h / 3 * (2 + math.cos(th)), 2 / h * (1 - math.cos(th))
+        g = 1 / (1 + tau * k_th / m_th)
+        a = h * coef / k_th * (1 - g ** np.arange(n_t + 1))
+        u += a[:, None] * v[None, :]
+    return lv, u
+
+
+def test_configuration_64x64_closed_form():
+    lv, exact = uniform_q_closed_form(64, 64)
+    b = O.load_vector(lv, 1.0)
+    np.testing.assert_allclose(O.direct_solve(lv, b), exact, rtol=0, atol=1e-13 * exact.max())
+    h = O.build_hierarchy(lv, O.Options())
+    res = O.stmg_solve(h, b)
+    assert res.status == "converged" and res.history[-1] < 1e-10
+    assert np.abs(res.u - exact).max() / exact.max() < 1e-9
+
+
+def test_sine_mode_decays_like_the_pde():
+    """Fine grids: g^n approaches exp(-(m+1/2)^2 pi^2 t) (separation of variables)."""
+    n_el, n_t, tf = 256, 4096, 0.05
+    lv = uniform_level(n_el, n_t, t_final=tf)
+    th, _, _ = sine_mode(n_el, 0)
+    h, tau = lv.h, lv.tau
+    m_th, k_th = h / 3 * (2 + math.cos(th)), 2 / h * (1 - math.cos(th))
+    g = 1 / (1 + tau * k_th / m_th)
+    assert g ** n_t == pytest.approx(math.exp(-(0.5 * math.pi) ** 2 * tf), rel=2e-4)
+
+
+# ---------------------------------------------------------------------------------------
+# Effective anisotropy and coarsening paths (Sections 3.2, 4, 5.2)
+# ---------------------------------------------------------------------------------------
+
+def al_epoxy():
+    m = GOLD["table3_materials"]["value"]
+    return O.Material(m["k_ins"], m["k_con"], m["c_ins"], m["c_con"], 3.0, 2.0)
+
+
+def test_lambda_eff_problem7_and_8():
+    L, N = 0.1, 256
+    chi7 = I.ramp_design(N, L, 5.0 / L, L / 2)
+    lv7 = O.make_fine_level(chi7, al_epoxy(), N, L, 10.0)
+    g7 = GOLD["lambda_eff_problem7"]
+    assert abs(O.lambda_eff(lv7) - g7["value"]) <= g7["abs_tol"]
+    chi8 = I.thin_insulator_design(N, L, 0.03)
+    lv8 = O.make_fine_level(chi8, al_epoxy(), N, L, 100.0)
+    g8 = GOLD["lambda_eff_problem8"]
+    assert abs(O.lambda_eff(lv8) - g8["value"]) <= g8["abs_tol"]
+    # lambda_eff is the geometric mean of the element extremes (eq. lambda eff def 1)
+    lam_e = lv8.k / lv8.c * lv8.tau / lv8.h ** 2
+    assert O.lambda_eff(lv8) == pytest.approx(math.sqrt(lam_e.min() * lam_e.max()), rel=1e-14)
+
+
+def test_uniform_study_lambda_range():
+    lo, hi = GOLD["uniform_lambda_range_log2"]["value"]
+    for tT, expect in ((2.0 ** -18, lo), (4.0, hi)):
+        lv = uniform_level(256, 256, t_final=tT)
+        assert math.log2(O.lambda_eff(lv)) == pytest.approx(expect, abs=1e-12)
+
+
+@pytest.mark.parametrize("prob", ["1", "2", "3", "4", "5", "6"])
+def test_problems_1_to_6_lambda_window(prob):
+    k_ins, c_ins, xoff = GOLD["table1_params"]["value"][prob]
+    e0, e1 = GOLD["table1_tT_range_log2"]["value"][prob]
+    lo, hi = GOLD["problems_1_6_lambda_window_log2"]["value"]
+    mat = O.Material(k_ins, 1.0, c_ins, 1.0, 3.0, 2.0)
+    chi = I.ramp_design(256, 1.0, 10.0, xoff)
+    for e in (e0, e1):
+        lv = O.make_fine_level(chi, mat, 256, 1.0, 2.0 ** e)
+        assert lo < math.log2(O.lambda_eff(lv)) < hi
+
+
+def test_uniform_path_alg2():
+    """Configuration 1: lambda = 6.4, 1.6, 0.4 (all >= 0.25) so Algorithm 2 takes x three
+    times; the 9 x 65 level is below 1024 DOFs."""
+    lv = uniform_level(64, 64)
+    h = O.build_hierarchy(lv, O.Options())
+    assert h.path == "xxx"
+    np.testing.assert_allclose(h.lambdas, [6.4, 1.6, 0.4], rtol=1e-14)
+    assert O.w_diri(lv) == pytest.approx(1 * (1 / 64) / (0.1 / 64) + 64.0)
+    assert O.diag_J(lv)[5, 5] == pytest.approx(2 / 3 * (1 / 64) / (0.1 / 64) + 2 * 64)
+
+
+def test_alg4_guard_forces_t():
+    lv = uniform_level(64, 64)
+    h = O.build_hierarchy(lv, O.Options(M_min_elems=32, max_levels=4))
+    assert h.path == "xtt"
+
+
+def test_resistivity_average_is_harmonic_mean():
+    """Section 5.1: averaging 1/k gives k = 2 k_a k_b / (k_a + k_b); c is averaged."""
+    rng = np.random.default_rng(1)
+    k = 10 ** rng.uniform(-4, 0, 16)
+    c = rng.uniform(0.5, 2, 16)
+    lv = O.Level(16, 4, 1 / 16, 0.025, k, c)
+    co = O.coarsen(lv, "x", O.Options(reassembly="R"))
+    np.testing.assert_allclose(co.k, 2 * k[0::2] * k[1::2] / (k[0::2] + k[1::2]), rtol=1e-14)
+    np.testing.assert_allclose(co.c, (c[0::2] + c[1::2]) / 2, rtol=1e-15)
+    # constant conductivity: R, K and D coincide
+    lv1 = O.Level(16, 4, 1 / 16, 0.025, np.full(16, 0.3), c, np.full(16, 0.5))
+    kk = [O.coarsen(lv1, "x", O.Options(reassembly=m)).k for m in ("R", "K")]
+    np.testing.assert_allclose(kk[0], kk[1], rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------------------
+# Transfers: Galerkin identities of the rediscretised coarse operators
+# ---------------------------------------------------------------------------------------
+
+def coarse_interior(level):
+    m = O.dirichlet_mask(level).astype(bool)
+    return m.ravel()
+
+
+def galerkin(level, d):
+    import scipy.sparse as sp
+    Pt, Px, s = O.transfer_pair(level, d)
+    P = sp.kron(Pt, Px).toarray()
+    return s * P.T @ O.dense_J(level) @ P
+
+
+def test_x_transfer_galerkin_equals_K_rediscretisation():
+    """Nested linear elements: R J P on the coarse interior equals the coarse BE-FE
+    operator with arithmetically averaged k (the K method), s = 1.  (Exact for the
+    stiffness because coarse hat derivatives are constant per coarse element; the mass
+    term is exact only for constant c, which this test uses.)"""
+    lv = random_level(8, 5, 3)
+    lv.c = np.full(lv.n_el, 1.3)
+    co = O.coarsen(lv, "x", O.Options(reassembly="K"))
+    G = galerkin(lv, "x")
+    Jc = O.dense_J(co)
+    m = coarse_interior(co)
+    np.testing.assert_allclose(G[np.ix_(m, m)], Jc[np.ix_(m, m)], rtol=1e-12, atol=1e-10)
+
+
+def test_t_transfer_galerkin_equals_rediscretisation():
+    """Causal P and s = 1/2: R J P equals the coarse operator with dt doubled on the
+    interior rows, except the last coarse time level (no fine partner 2J+1)."""
+    lv = random_level(6, 8, 4)
+    co = O.coarsen(lv, "t", O.Options())
+    G = galerkin(lv, "t")
+    Jc = O.dense_J(co)
+    m = coarse_interior(co).reshape(co.shape)
+    m[-1, :] = False
+    m = m.ravel()
+    np.testing.assert_allclose(G[np.ix_(m, m)], Jc[np.ix_(m, m)], rtol=1e-12, atol=1e-10)
+
+
+def test_prolongation_stencils():
+    lv = uniform_level(8, 6)
+    z = np.zeros((7, 5))
+    z[2, 2] = 1.0
+    px = O.prolong(lv, "x", z)
+    expect = np.zeros(lv.shape)
+    expect[2, 3:6] = [0.5, 1.0, 0.5]
+    np.testing.assert_array_equal(px, expect)
+    zt = np.zeros((4, 9))
+    zt[1, 4] = 1.0
+    pt = O.prolong(lv, "t", zt)
+    expect = np.zeros(lv.shape)
+    expect[2:4, 4] = 1.0          # coarse level J -> fine 2J and 2J+1 (forward in time)
+    np.testing.assert_array_equal(pt, expect)
+
+
+# ---------------------------------------------------------------------------------------
+# Invariants of the smoother and the cycle
+# ---------------------------------------------------------------------------------------
+
+def small_hierarchy(nu=2, transpose=False):
+    rho = I.block_density(32, 4, seed=11)
+    mat = O.Material(1e-3, 1.0, 1.0, 1.0)
+    lv = O.make_fine_level(rho, mat, 40, 1.0, 0.1)
+    return lv, O.build_hierarchy(lv, O.Options(nu=nu, min_coarse_dofs=100))
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_exact_solution_is_fixed_point(transpose):
+    lv, h = small_hierarchy()
+    b = np.random.default_rng(5).standard_normal(lv.shape)
+    u = O.direct_solve(lv, b, transpose)
+    np.testing.assert_allclose(O.jacobi(h, 0, u, b, 3, transpose), u, atol=1e-12 * np.abs(u).max())
+    np.testing.assert_allclose(O.vcycle(h, 0, u, b, transpose), u, atol=1e-12 * np.abs(u).max())
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_cycle_linearity_and_affine_consistency(transpose):
+    lv, h = small_hierarchy()
+    rng = np.random.default_rng(6)
+    b = rng.standard_normal(lv.shape)
+    u = rng.standard_normal(lv.shape)
+    v0 = O.vcycle(h, 0, np.zeros(lv.shape), b, transpose)
+    np.testing.assert_allclose(O.vcycle(h, 0, np.zeros(lv.shape), 3.5 * b, transpose), 3.5 * v0,
+                               rtol=1e-12, atol=1e-12)
+    lhs = O.vcycle(h, 0, u, b, transpose)
+    rhs = u + O.vcycle(h, 0, np.zeros(lv.shape), b - O.apply_J(lv, u, transpose), transpose)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-11)
+
+
+def test_adjoint_identity_every_level():
+    _, h = small_hierarchy()
+    for l, lev in enumerate(h.levels):
+        rng = np.random.default_rng(20 + l)
+        x, y = rng.standard_normal(lev.shape), rng.standard_normal(lev.shape)
+        a = np.sum(y * O.apply_J(lev, x))
+        b = np.sum(O.apply_J(lev, y, True) * x)
+        assert a == pytest.approx(b, rel=1e-12)
+
+
+def test_stmg_reaches_direct_solution_high_contrast():
+    for transpose in (False, True):
+        lv, h = small_hierarchy(nu=5, transpose=transpose)
+        b = O.load_vector(lv, 1.0)
+        res = O.stmg_solve(h, b, transpose=transpose)
+        assert res.status == "converged"
+        exact = O.direct_solve(lv, b, transpose)
+        assert np.abs(res.u - exact).max() / np.abs(exact).max() < 1e-8
+
+
+def test_termination_rule_and_factor():
+    lv, h = small_hierarchy()
+    h.opts.max_cycles = 3
+    res = O.stmg_solve(h, O.load_vector(lv, 1.0))
+    assert res.status == "max_cycles" and res.cycles == 3 and len(res.history) == 4
+    assert res.conv_factor == pytest.approx((res.history[3] / res.history[0]) ** (1 / 3))
+    # a W_Diri near zero makes the smoother blow up at the Dirichlet DOFs (Appendix A)
+    lv2, h2 = small_hierarchy()
+    for l in h2.levels:
+        l.w_override = 1e-12
+    res2 = O.stmg_solve(h2, O.load_vector(lv2, 1.0))
+    assert res2.status == "diverged"
+
+
+# ---------------------------------------------------------------------------------------
+# Objective, adjoint and gradient (Section 7)
+# ---------------------------------------------------------------------------------------
+
+def test_objective_two_ways():
+    lv, _ = small_hierarchy()
+    b = O.load_vector(lv, 1.0)
+    u = O.direct_solve(lv, b)
+    lam = O.direct_solve(lv, O.adjoint_rhs(lv, b), transpose=True)
+    theta = O.objective(lv, b, u)
+    assert theta == pytest.approx(float(np.sum(lam * b)), rel=1e-12)
+    assert theta == pytest.approx(lv.tau * float(np.sum(b * u)), rel=1e-15)
+
+
+@pytest.mark.parametrize("vary_c", [False, True])
+def test_gradient_against_central_differences(vary_c):
+    mat = O.Material(1e-2, 1.0, 0.3 if vary_c else 1.0, 1.0, 3.0, 2.0)
+    chi = np.random.default_rng(8).uniform(0.1, 0.9, 7)
+    n_t, tf = 6, 0.05
+
+    def theta(ch):
+        lv = O.make_fine_level(ch, mat, n_t, 1.0, tf)
+        b = O.load_vector(lv, 1.0)
+        return O.objective(lv, b, O.direct_solve(lv, b))
+
+    lv = O.make_fine_level(chi, mat, n_t, 1.0, tf)
+    b = O.load_vector(lv, 1.0)
+    u = O.direct_solve(lv, b)
+    lam = O.direct_solve(lv, O.adjoint_rhs(lv, b), transpose=True)
+    g = O.gradient(lv, mat, chi, u, lam)
+    fd = np.zeros_like(chi)
+    eps = 1e-6
+    for e in range(chi.size):
+        cp, cm = chi.copy(), chi.copy()
+        cp[e] += eps
+        cm[e] -= eps
+        fd[e] = (theta(cp) - theta(cm)) / (2 * eps)
+    np.testing.assert_allclose(g, fd, rtol=0, atol=1e-7 * np.abs(fd).max())
+
+
+# ---------------------------------------------------------------------------------------
+# Qualitative convergence claims
+# ---------------------------------------------------------------------------------------
+
+def two_grid_factor(lv, path, nu=5, cycles=12):
+    h = O.build_hierarchy(lv, O.Options(nu=nu, force_path=path, tol=1e-300, max_cycles=cycles))
+    b = O.load_vector(lv, 1.0)
+    return O.stmg_solve(h, b).conv_factor
+
+
+def test_two_grid_uniform_x_versus_t():
+    """Section 3.2 (Figure 3): t-coarsening wins for small lambda, x-coarsening for
+    large lambda, with the crossover near lambda = 0.1 (here between 2^-4 and 2^-2 on a
+    64 x 64 grid), and full space-time coarsening is never better than the better
+    semi-coarsening."""
+    n = 64
+    for log2lam, winner in ((-6, "t"), (-4, "t"), (-2, "x"), (0, "x"), (2, "x"), (4, "x")):
+        lv = uniform_level(n, n, t_final=2.0 ** log2lam * n / n ** 2)
+        assert O.lambda_eff(lv) == pytest.approx(2.0 ** log2lam)
+        f = {p: two_grid_factor(lv, p, cycles=8) for p in "xtf"}
+        assert min(f, key=lambda p: f[p]) in (winner, "f") and f[winner] <= f["f"] + 1e-12
+        assert f[winner] < f["t" if winner == "x" else "x"]
