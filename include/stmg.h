@@ -1,0 +1,214 @@
+/*
+ * stmg.h - C ABI of libstmg, a space-time multigrid (STMG) solver for 1D transient
+ * heat conduction on MI355X (gfx950), after Appel & Alexandersen, "Space-Time
+ * Multigrid Methods Suitable for Topology Optimisation of Transient Heat
+ * Conduction" (arXiv 2505.10168).
+ *
+ * Problem (Section 2): c dT/dt - d/dx(k dT/dx) = q on [0,L] x [0,t_T], T = 0 at t = 0
+ * and at x = 0, dT/dx = 0 at x = L.  Linear finite elements in space (N_el elements),
+ * backward Euler in time (N_t steps), element-wise constant k, c, q (Section 2.2),
+ * giving the all-at-once system J u = b with the Dirichlet treatment of Appendix A.
+ * Materials follow the SIMP maps of Section 2.1 applied to element densities rho_e.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Space-time vectors are DEVICE pointers to compact, time-major FP64 arrays of
+ *   shape [(N_t+1)][(N_el+1)] for the grid they belong to: element (n, i) at
+ *   offset n*(N_el+1) + i, time level n = 0..N_t, node i = 0..N_el.
+ * - Per-element arrays (densities, gradients) are DEVICE pointers to N_el FP64 values.
+ * - The caller owns every pointer it passes and keeps it valid until the call
+ *   returns; the library never retains a caller pointer after a call.
+ * - All device work runs on the stream given at creation (a hipStream_t passed as
+ *   void*, NULL = the default stream).  Calls return after their work is complete
+ *   on that stream.
+ * - A handle is not thread-safe; use one handle per host thread.  Distinct handles
+ *   may be used concurrently from different threads on different streams.
+ * - Return values: 0 = OK; > 0 = outcome of an iterative solve (outputs and stats
+ *   are written); < 0 = error (outputs untouched, stmg_last_error() describes it).
+ */
+#ifndef STMG_H
+#define STMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------ */
+#define STMG_OK               0
+#define STMG_NOT_CONVERGED    1   /* cycle cap reached before the tolerance        */
+#define STMG_DIVERGED         2   /* residual above the divergence bound, or NaN   */
+#define STMG_EINVAL          -1   /* invalid argument                               */
+#define STMG_ENOMEM          -2   /* device allocation failed                       */
+#define STMG_EHIP            -3   /* HIP runtime error                              */
+#define STMG_EUNSUPPORTED    -4   /* valid request this build does not implement    */
+
+/* reassembly methods of the coarse levels (Section 5.1) */
+#define STMG_REASSEMBLE_R     0   /* average thermal resistivity 1/k (default)     */
+#define STMG_REASSEMBLE_K     1   /* average conductivity                           */
+#define STMG_REASSEMBLE_D     2   /* average the design field, then apply SIMP      */
+
+/* precision of the solve */
+#define STMG_FP64             0   /* everything in FP64                             */
+#define STMG_MIXED            1   /* FP64 outer defect correction around FP32 cycles */
+
+#define STMG_MAX_HISTORY   1024   /* longest residual history kept in the stats     */
+
+/* Physical problem.  Materials: k(rho) = k_ins + (k_con - k_ins) rho^p_k and
+ * c(rho) = c_ins + (c_con - c_ins) rho^p_c (Section 2.1, eqs. SIMP k / SIMP c).
+ * theta_ref normalises the objective (Section 7.1).  q_uniform is the heat source
+ * used when no element-wise load is given at creation. */
+typedef struct {
+    int32_t n_el;          /* elements, >= 1                                        */
+    int32_t n_t;           /* backward-Euler steps, >= 1                            */
+    double  length;        /* L > 0                                                 */
+    double  t_final;       /* t_T > 0                                               */
+    double  k_ins, k_con;  /* conductivities of insulator / conductor, > 0          */
+    double  c_ins, c_con;  /* heat capacities, > 0                                  */
+    double  p_k, p_c;      /* SIMP penalties (paper: 3 and 2)                       */
+    double  theta_ref;     /* > 0                                                   */
+    double  q_uniform;     /* uniform heat source                                   */
+} stmg_problem;
+
+/* Solver options.  stmg_default_options() fills: nu = 2, omega = 0.5,
+ * lambda_crit = 0.25, max_levels = 0, min_coarse_dofs = 1024, M_min_elems = 0,
+ * reassembly = R, deff_mode = 0, tol = 1e-10, diverge = 1e9, max_cycles = 100,
+ * precision = FP64, w_diri_override = 0, fused = 1, time_kernels = 0. */
+typedef struct {
+    int32_t nu;               /* smoothing steps before and after the coarse correction (Algorithm 1) */
+    double  omega;            /* Jacobi damping (Section 3.1 uses 1/2)                       */
+    double  lambda_crit;      /* threshold of Algorithms 2-4                                 */
+    int32_t max_levels;       /* N_l; 0 = coarsen while a level has > min_coarse_dofs DOFs    */
+    int64_t min_coarse_dofs;  /* used when max_levels == 0                                    */
+    int32_t M_min_elems;      /* Algorithm 4 guard: t-coarsen when N_el/2 < M (0 = off)       */
+    int32_t reassembly;       /* STMG_REASSEMBLE_*                                           */
+    int32_t deff_mode;        /* 0: D_eff from the field (Algorithm 3);
+                                 1: sqrt(D_SIMP(0) D_SIMP(1)) (Section 7.2), path independent of rho */
+    double  tol;              /* stop when r_n < tol (Section 3.1 termination rule)          */
+    double  diverge;          /* stop when r_n > diverge                                      */
+    int32_t max_cycles;       /* stop after this many cycles (<= STMG_MAX_HISTORY)           */
+    int32_t precision;        /* STMG_FP64 or STMG_MIXED                                      */
+    double  w_diri_override;  /* > 0: use this W_Diri on every level; otherwise Appendix A    */
+    int32_t fused;            /* 1: fused streaming kernels; 0: one kernel per method step   */
+    int32_t time_kernels;     /* 1: time the fine-level fused passes with HIP events          */
+} stmg_options;
+
+typedef struct {
+    int32_t status;                  /* same value as the call's return               */
+    int32_t cycles;                  /* V-cycles (FP64) or outer corrections (mixed)  */
+    int32_t n_levels;
+    double  rel_residual;            /* final ||J u - b|| / ||b|| (FP64)               */
+    double  conv_factor;             /* (r_N / r_0)^(1/N) (Section 3.1)               */
+    double  solve_ms;                /* wall time of the solve call                    */
+    double  dof_updates;             /* sum over cycles of sum_{l < N_l} 2 nu n_l      */
+    double  fine_kernel_ms;          /* time_kernels: summed time of fine fused passes */
+    double  fine_kernel_bytes;       /* their algorithmic bytes                         */
+    int64_t fine_kernel_launches;
+    double  history[STMG_MAX_HISTORY + 1];   /* r_0 .. r_cycles                       */
+} stmg_stats;
+
+/* Hierarchy description (read-only copy). */
+typedef struct {
+    int32_t n_levels;
+    int32_t n_el[64], n_t[64];
+    double  h[64], tau[64], w_diri[64];
+    double  lambda_eff[64];          /* value that chose the direction leaving level l */
+    char    path[64];                /* 'x' / 't' per coarsening step, NUL terminated  */
+    size_t  device_bytes;            /* device memory held by the handle               */
+} stmg_info;
+
+typedef struct stmg_ctx* stmg_t;
+
+/* Fill *o with the defaults listed above.  Returns STMG_EINVAL if o is NULL. */
+int stmg_default_options(stmg_options* o);
+
+/* Device bytes a handle for (p, o) will allocate, without allocating.  The figure
+ * is exact for the path that field-independent D_eff (deff_mode = 1) yields and an
+ * upper bound (every step taken in x, the costlier direction) otherwise. */
+int stmg_footprint(const stmg_problem* p, const stmg_options* o, size_t* bytes);
+
+/* Build the level hierarchy (Algorithms 3/4 with the reassembly method of
+ * Section 5.1) and the fine load vector (Section 2.2) on the device.
+ *   d_rho : N_el densities in [0, 1] (device).
+ *   d_q   : optional element load, [(N_t+1)][N_el] FP64 (device), row n = q at t_n,
+ *           row 0 ignored; NULL = q_uniform everywhere.
+ *   stream: hipStream_t used by every call on this handle (NULL = default stream).
+ * N_el and N_t need not be powers of two; a direction that cannot halve is
+ * replaced by the other one and coarsening stops when neither can.
+ * Errors: EINVAL (bad sizes or values), ENOMEM, EHIP. */
+int stmg_create(stmg_t* handle, const stmg_problem* p, const stmg_options* o,
+                const double* d_rho, const double* d_q, void* stream);
+
+/* Re-assemble every level from new densities (Section 7.2: with deff_mode = 1 the
+ * path and memory stay fixed across designs).  With deff_mode = 0 the path is
+ * recomputed; if it changes, EUNSUPPORTED is returned and the handle is unchanged
+ * (create a new handle instead). */
+int stmg_set_design(stmg_t h, const double* d_rho);
+
+/* Solve J u = b by V-cycles (Algorithm 1) from u0, stopping by the rule of
+ * Section 3.1 with the tol / diverge / max_cycles options.
+ *   d_rhs : right-hand side on the fine grid, or NULL for the assembled load b.
+ *   d_u0  : initial guess, or NULL for u = 0 (the paper's choice).
+ *   d_u   : output (may alias d_u0).
+ *   st    : optional statistics.
+ * Returns OK, NOT_CONVERGED or DIVERGED (d_u holds the last iterate in all three). */
+int stmg_solve_forward(stmg_t h, const double* d_rhs, const double* d_u0,
+                       double* d_u, stmg_stats* st);
+
+/* Solve the adjoint J^T Lambda = b dt / Theta_ref (Section 7.2) with (J^(l))^T on
+ * every level and the same forward-causal transfers.  d_rhs = NULL selects
+ * b dt / Theta_ref; otherwise as stmg_solve_forward. */
+int stmg_solve_adjoint(stmg_t h, const double* d_rhs, const double* d_l0,
+                       double* d_lambda, stmg_stats* st);
+
+/* Theta = b^T u dt / Theta_ref (Section 7.1) with the assembled load b, written to
+ * *theta (host). */
+int stmg_objective(stmg_t h, const double* d_u, double* theta);
+
+/* dTheta/drho_e for all elements by the discrete adjoint method (Section 7.2):
+ * g_e = -Lambda^T (dJ/drho_e) u with Dirichlet entries of u and Lambda removed.
+ * d_grad: N_el FP64 (device). */
+int stmg_gradient(stmg_t h, const double* d_u, const double* d_lambda, double* d_grad);
+
+int stmg_get_info(stmg_t h, stmg_info* info);
+int stmg_destroy(stmg_t h);
+
+/* ---- per-level components (each level's own grid, compact layout) -------------
+ * Entry points for testing one step of Algorithm 1 at a time.  `level` is 0-based
+ * (0 = finest); `transpose` selects J^T.  Level vectors have the shape of that
+ * level from stmg_get_info. */
+
+/* y = J x  (Appendix A form of the BE-FE operator of Section 2.2). */
+int stmg_level_apply(stmg_t h, int level, int transpose, const double* d_x, double* d_y);
+
+/* nu damped-Jacobi steps u <- u + omega D^-1 (b - J u) in place (Section 3.1),
+ * through the fused kernels when the handle has fused = 1. */
+int stmg_level_smooth(stmg_t h, int level, int transpose, int nu, const double* d_b, double* d_u);
+
+/* b_c = R (b - J u) after nu pre-smoothing steps, i.e. lines "smooth" and
+ * "restrict" of Algorithm 1 on `level` (level < n_levels - 1).  d_u is updated in
+ * place; d_bc has the shape of level + 1. */
+int stmg_level_presmooth_restrict(stmg_t h, int level, int transpose, int nu,
+                                  const double* d_b, double* d_u, double* d_bc);
+
+/* u <- u + P z, then nu post-smoothing steps (the last two steps of Algorithm 1). */
+int stmg_level_prolong_postsmooth(stmg_t h, int level, int transpose, int nu,
+                                  const double* d_b, const double* d_z, double* d_u);
+
+/* Exact solve of J z = b on the coarsest level (Algorithm 1, first branch). */
+int stmg_level_coarsest_solve(stmg_t h, int transpose, const double* d_b, double* d_z);
+
+/* One V-cycle in place on the fine grid; *rel_res (host, optional) receives
+ * ||J u - b|| / ||b|| after the cycle. */
+int stmg_vcycle(stmg_t h, int transpose, const double* d_b, double* d_u, double* rel_res);
+
+const char* stmg_status_string(int status);
+/* Message of the last error on the calling thread (empty if none). */
+const char* stmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STMG_H */

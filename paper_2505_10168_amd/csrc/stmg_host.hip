@@ -1,0 +1,1063 @@
+// Host side of libstmg: level hierarchy (Algorithms 3/4, Section 5.1), V-cycle
+// driver (Algorithm 1), FP64 and mixed-precision solve loops with the termination
+// rule of Section 3.1, objective and gradient (Section 7), and the C ABI of stmg.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "stmg.h"
+#include "stmg_launch.hpp"
+
+using namespace stmg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                       \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess)                                                           \
+            return fail(STMG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+#define CHK(x)                     \
+    do {                           \
+        int rc_ = (x);             \
+        if (rc_ < 0) return rc_;   \
+    } while (0)
+
+int64_t pitch_for(int N) { return ((int64_t)N + 4 + 31) / 32 * 32; }
+int64_t dofs_of(int N, int Nt) { return (int64_t)(N + 1) * (Nt + 1); }
+
+struct Level {
+    int N = 0, Nt = 0;
+    int64_t P = 0;
+    double h = 0, tau = 0, W = 0;
+    char dir = 0;            // direction that builds the next level ('x' / 't'); 0 = coarsest
+    double lambda = 0;
+    double* k = nullptr;
+    double* c = nullptr;
+    double* chi = nullptr;
+    double* coef = nullptr;  // 7 (N+1)
+    float* coef32 = nullptr;
+    double* thomas = nullptr;  // coarsest: cp, inv, rhs scratch (3 (N+1))
+    double* u = nullptr;
+    double* b = nullptr;
+    double* t = nullptr;
+    float* u32 = nullptr;
+    float* b32 = nullptr;
+    float* t32 = nullptr;
+    int64_t elems() const { return (int64_t)(Nt + 1) * P; }
+    int64_t dofs() const { return dofs_of(N, Nt); }
+};
+
+template <typename T> T*& U(Level& l);
+template <typename T> T*& B(Level& l);
+template <typename T> T*& Tt(Level& l);
+template <> double*& U<double>(Level& l) { return l.u; }
+template <> double*& B<double>(Level& l) { return l.b; }
+template <> double*& Tt<double>(Level& l) { return l.t; }
+template <> float*& U<float>(Level& l) { return l.u32; }
+template <> float*& B<float>(Level& l) { return l.b32; }
+template <> float*& Tt<float>(Level& l) { return l.t32; }
+
+template <typename T>
+LevelView<T> view(const Level& l, double omega);
+
+template <>
+LevelView<double> view<double>(const Level& l, double omega) {
+    LevelView<double> v;
+    const int64_t S = l.N + 1;
+    v.N = l.N; v.Nt = l.Nt; v.P = l.P;
+    v.lo = l.coef; v.di = l.coef + S; v.up = l.coef + 2 * S;
+    v.mlo = l.coef + 3 * S; v.mdi = l.coef + 4 * S; v.mup = l.coef + 5 * S;
+    v.wd = l.coef + 6 * S;
+    v.W = l.W;
+    v.wW = omega / l.W;
+    return v;
+}
+
+template <>
+LevelView<float> view<float>(const Level& l, double omega) {
+    LevelView<float> v;
+    const int64_t S = l.N + 1;
+    v.N = l.N; v.Nt = l.Nt; v.P = l.P;
+    v.lo = l.coef32; v.di = l.coef32 + S; v.up = l.coef32 + 2 * S;
+    v.mlo = l.coef32 + 3 * S; v.mdi = l.coef32 + 4 * S; v.mup = l.coef32 + 5 * S;
+    v.wd = l.coef32 + 6 * S;
+    v.W = (float)l.W;
+    v.wW = (float)(omega / l.W);
+    return v;
+}
+
+// Bytes of the fine-level fused passes that the event timer records (algorithmic:
+// every vector read or written once per pass).
+struct KernelTimer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<double> bytes;
+    size_t used = 0;
+};
+
+}  // namespace
+
+struct stmg_ctx {
+    stmg_problem p{};
+    stmg_options o{};
+    hipStream_t s = nullptr;
+    std::vector<Level> L;
+    double* bload = nullptr;     // fine load vector b (Section 2.2)
+    double* rho = nullptr;       // current densities
+    double* kp = nullptr;        // dk/drho
+    double* cpd = nullptr;       // dc/drho
+    double* simp = nullptr;      // device {k_ins, k_con, p_k, c_ins, c_con, p_c}
+    double* stats = nullptr;     // device scratch for level stats (4 doubles)
+    double* dscal = nullptr;     // device scalars
+    double* hscal = nullptr;     // pinned host scalars
+    double* parts = nullptr;
+    int64_t nparts = 0;
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    KernelTimer timer;
+    bool want_norm = false;      // fuse the residual norm into the fine post pass
+    int norm_parts = 0;          // partial count written by the last fused norm
+
+    ~stmg_ctx() {
+        for (void* q : allocs) (void)hipFree(q);
+        if (hscal) (void)hipHostFree(hscal);
+        for (auto& e : timer.ev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
+
+    template <typename T>
+    int alloc(T** out, int64_t n) {
+        if (n <= 0) n = 1;
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, (size_t)n * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(STMG_ENOMEM, "hipMalloc of " + std::to_string((size_t)n * sizeof(T)) +
+                                         " bytes failed");
+        }
+        allocs.push_back(q);
+        bytes += (size_t)n * sizeof(T);
+        e = hipMemsetAsync(q, 0, (size_t)n * sizeof(T), s);
+        if (e != hipSuccess) return fail(STMG_EHIP, "hipMemsetAsync failed");
+        *out = static_cast<T*>(q);
+        return 0;
+    }
+};
+
+namespace {
+
+// ------------------------------------------------------------------------------------
+// Validation and footprint
+// ------------------------------------------------------------------------------------
+
+int validate(const stmg_problem* p, const stmg_options* o) {
+    if (!p || !o) return fail(STMG_EINVAL, "null problem or options");
+    if (p->n_el < 1 || p->n_t < 1) return fail(STMG_EINVAL, "n_el and n_t must be >= 1");
+    if ((int64_t)p->n_el > (1 << 24) || (int64_t)p->n_t > (1 << 26))
+        return fail(STMG_EINVAL, "grid too large");
+    if (!(p->length > 0) || !(p->t_final > 0)) return fail(STMG_EINVAL, "length and t_final must be > 0");
+    if (!(p->k_ins > 0) || !(p->k_con > 0) || !(p->c_ins > 0) || !(p->c_con > 0))
+        return fail(STMG_EINVAL, "material constants must be > 0");
+    if (!(p->theta_ref > 0)) return fail(STMG_EINVAL, "theta_ref must be > 0");
+    if (!std::isfinite(p->q_uniform)) return fail(STMG_EINVAL, "q_uniform must be finite");
+    if (o->nu < 0 || o->nu > 64) return fail(STMG_EINVAL, "nu must be in [0, 64]");
+    if (!(o->omega > 0)) return fail(STMG_EINVAL, "omega must be > 0");
+    if (o->max_levels < 0 || o->max_levels > 64) return fail(STMG_EINVAL, "max_levels must be in [0, 64]");
+    if (o->min_coarse_dofs < 1) return fail(STMG_EINVAL, "min_coarse_dofs must be >= 1");
+    if (o->max_cycles < 1 || o->max_cycles > STMG_MAX_HISTORY)
+        return fail(STMG_EINVAL, "max_cycles must be in [1, STMG_MAX_HISTORY]");
+    if (o->reassembly < 0 || o->reassembly > 2) return fail(STMG_EINVAL, "unknown reassembly method");
+    if (o->deff_mode < 0 || o->deff_mode > 1) return fail(STMG_EINVAL, "unknown deff_mode");
+    if (o->precision != STMG_FP64 && o->precision != STMG_MIXED)
+        return fail(STMG_EINVAL, "unknown precision");
+    if (!(o->tol > 0) || !(o->diverge > 0)) return fail(STMG_EINVAL, "tol and diverge must be > 0");
+    return 0;
+}
+
+bool can_x(int N) { return N % 2 == 0 && N >= 2; }
+bool can_t(int Nt) { return Nt % 2 == 0 && Nt >= 2; }
+
+// Bytes a level of (N, Nt) holds for the given precision and position.
+size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest) {
+    const int64_t P = pitch_for(N), E = (int64_t)(Nt + 1) * P;
+    size_t b = 3 * (size_t)N * 8 + 7 * (size_t)(N + 1) * 8;
+    if (precision == STMG_MIXED) b += 7 * (size_t)(N + 1) * 4;
+    if (coarsest) b += 3 * (size_t)(N + 1) * 8;
+    if (precision == STMG_FP64 || fine) b += 3 * (size_t)E * 8;
+    if (precision == STMG_MIXED) b += 3 * (size_t)E * 4;
+    return b;
+}
+
+// Footprint of a handle.  Directions are not known without the field (deff_mode 0),
+// so for every level count the largest grid any x/t sequence can produce is used.
+size_t footprint_of(const stmg_problem* p, const stmg_options* o) {
+    const int N0 = p->n_el, T0 = p->n_t;
+    size_t total = 0;
+    const int fine_parts = 1 << 20;
+    total += (size_t)(T0 + 1) * pitch_for(N0) * 8;   // bload
+    total += (size_t)N0 * 8 * 4 + 64 + 4096;          // rho, kp, cpd, scalars
+    total += (size_t)fine_parts * 8;
+    if (o->deff_mode == 1) {
+        const double deff = std::sqrt((p->k_ins / p->c_ins) * (p->k_con / p->c_con));
+        int N = N0, Nt = T0, lev = 1;
+        double h = p->length / N0, tau = p->t_final / T0;
+        while (true) {
+            bool last;
+            char want = 0;
+            if (o->max_levels) last = (lev == o->max_levels);
+            else last = dofs_of(N, Nt) <= o->min_coarse_dofs;
+            if (!last) {
+                double lam = deff * tau / (h * h);
+                want = lam < o->lambda_crit ? 't' : 'x';
+                if (o->M_min_elems && N / 2.0 < o->M_min_elems) want = 't';
+                if (want == 'x' && !can_x(N)) want = can_t(Nt) ? 't' : 0;
+                else if (want == 't' && !can_t(Nt)) want = can_x(N) ? 'x' : 0;
+                if (!want) last = true;
+            }
+            total += level_bytes(N, Nt, o->precision, lev == 1, last);
+            if (last) break;
+            if (want == 'x') { N /= 2; h *= 2; } else { Nt /= 2; tau *= 2; }
+            ++lev;
+        }
+        return total;
+    }
+    // field-dependent path: bound each level by the largest (N, Nt) of any path
+    struct S { int N, Nt; };
+    std::vector<S> frontier{{N0, T0}};
+    int lev = 1;
+    while (!frontier.empty() && lev <= 64) {
+        size_t worst = 0;
+        std::vector<S> next;
+        bool any_continue = false;
+        for (auto& f : frontier) {
+            bool last = o->max_levels ? (lev == o->max_levels) : (dofs_of(f.N, f.Nt) <= o->min_coarse_dofs);
+            if (!last && !can_x(f.N) && !can_t(f.Nt)) last = true;
+            worst = std::max(worst, level_bytes(f.N, f.Nt, o->precision, lev == 1, true));
+            if (!last) {
+                any_continue = true;
+                if (can_x(f.N)) next.push_back({f.N / 2, f.Nt});
+                if (can_t(f.Nt)) next.push_back({f.N, f.Nt / 2});
+            }
+        }
+        total += worst;
+        if (!any_continue) break;
+        // keep the frontier small: distinct (N, Nt) pairs only
+        std::vector<S> uniq;
+        for (auto& q : next) {
+            bool seen = false;
+            for (auto& w : uniq) seen |= (w.N == q.N && w.Nt == q.Nt);
+            if (!seen) uniq.push_back(q);
+        }
+        frontier.swap(uniq);
+        ++lev;
+    }
+    return total;
+}
+
+// ------------------------------------------------------------------------------------
+// Setup
+// ------------------------------------------------------------------------------------
+
+int fetch_stats(stmg_ctx* h, const Level& l, double out[4]) {
+    launch_level_stats(l.k, l.c, l.N, h->stats, h->s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->hscal, h->stats, 4 * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    for (int i = 0; i < 4; ++i) out[i] = h->hscal[i];
+    return 0;
+}
+
+double level_w(const stmg_options& o, const Level& l, const double st[4]) {
+    if (o.w_diri_override > 0) return o.w_diri_override;
+    // W_Diri = max_e c_e dx/dt + max_e k_e / dx  (Appendix A)
+    return st[2] * l.h / l.tau + st[3] / l.h;
+}
+
+// Fills k, c, chi of level 0 from rho (SIMP, Section 2.1).
+int level0_material(stmg_ctx* h) {
+    Level& f = h->L[0];
+    const stmg_problem& p = h->p;
+    HIPCHK(hipMemcpyAsync(f.chi, h->rho, (size_t)f.N * 8, hipMemcpyDeviceToDevice, h->s));
+    launch_simp(h->rho, f.N, p.k_ins, p.k_con, p.p_k, f.k, h->s);
+    launch_simp(h->rho, f.N, p.c_ins, p.c_con, p.p_c, f.c, h->s);
+    launch_simp_derivative(h->rho, f.N, p.k_ins, p.k_con, p.p_k, h->kp, h->s);
+    launch_simp_derivative(h->rho, f.N, p.c_ins, p.c_con, p.p_c, h->cpd, h->s);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+// Direction leaving level `cur` (Algorithm 3; Algorithm 4 guard; Section 7.2 D_eff).
+char choose_direction(const stmg_ctx* h, const Level& cur, const double st[4], double* lam_out) {
+    const stmg_options& o = h->o;
+    const stmg_problem& p = h->p;
+    double lam;
+    if (o.deff_mode == 1) {
+        const double deff = std::sqrt((p.k_ins / p.c_ins) * (p.k_con / p.c_con));
+        lam = deff * cur.tau / (cur.h * cur.h);
+    } else {
+        lam = std::sqrt(st[0] * st[1]) * cur.tau / (cur.h * cur.h);
+    }
+    *lam_out = lam;
+    char want = lam < o.lambda_crit ? 't' : 'x';
+    if (o.M_min_elems && cur.N / 2.0 < o.M_min_elems) want = 't';
+    if (want == 'x' && !can_x(cur.N)) want = can_t(cur.Nt) ? 't' : 0;
+    else if (want == 't' && !can_t(cur.Nt)) want = can_x(cur.N) ? 'x' : 0;
+    return want;
+}
+
+bool is_last(const stmg_ctx* h, size_t nlev, const Level& cur) {
+    if (h->o.max_levels) return (int)nlev == h->o.max_levels;
+    return cur.dofs() <= h->o.min_coarse_dofs;
+}
+
+int coarse_coefficients(stmg_ctx* h, const Level& f, char dir, Level& c) {
+    if (dir == 't') {
+        HIPCHK(hipMemcpyAsync(c.k, f.k, (size_t)f.N * 8, hipMemcpyDeviceToDevice, h->s));
+        HIPCHK(hipMemcpyAsync(c.c, f.c, (size_t)f.N * 8, hipMemcpyDeviceToDevice, h->s));
+        HIPCHK(hipMemcpyAsync(c.chi, f.chi, (size_t)f.N * 8, hipMemcpyDeviceToDevice, h->s));
+        return 0;
+    }
+    const int method = h->o.reassembly == STMG_REASSEMBLE_R ? 0 : (h->o.reassembly == STMG_REASSEMBLE_K ? 1 : 2);
+    launch_coarsen_x(f.k, f.c, f.chi, c.N, method, h->simp, c.k, c.c, c.chi, h->s);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int finish_level(stmg_ctx* h, Level& l, bool coarsest) {
+    launch_stencil_coef(l.k, l.c, l.N, l.h, l.tau, h->o.omega, l.coef, l.coef32, h->s);
+    if (coarsest) launch_thomas_factors(l.coef, l.N, l.thomas, l.thomas + (l.N + 1), h->s);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int build(stmg_ctx* h, const double* d_q) {
+    const stmg_problem& p = h->p;
+    Level f;
+    f.N = p.n_el;
+    f.Nt = p.n_t;
+    f.P = pitch_for(f.N);
+    f.h = p.length / p.n_el;
+    f.tau = p.t_final / p.n_t;
+    h->L.push_back(f);
+    // directions first (needs only k, c); vectors are allocated once the path is known
+    CHK(h->alloc(&h->L[0].k, f.N));
+    CHK(h->alloc(&h->L[0].c, f.N));
+    CHK(h->alloc(&h->L[0].chi, f.N));
+    CHK(level0_material(h));
+    while (true) {
+        Level& cur = h->L.back();
+        double st[4];
+        CHK(fetch_stats(h, cur, st));
+        cur.W = level_w(h->o, cur, st);
+        if (is_last(h, h->L.size(), cur)) break;
+        double lam;
+        char d = choose_direction(h, cur, st, &lam);
+        if (!d) break;
+        cur.dir = d;
+        cur.lambda = lam;
+        Level c;
+        c.N = d == 'x' ? cur.N / 2 : cur.N;
+        c.Nt = d == 't' ? cur.Nt / 2 : cur.Nt;
+        c.P = pitch_for(c.N);
+        c.h = d == 'x' ? 2.0 * cur.h : cur.h;
+        c.tau = d == 't' ? 2.0 * cur.tau : cur.tau;
+        CHK(h->alloc(&c.k, c.N));
+        CHK(h->alloc(&c.c, c.N));
+        CHK(h->alloc(&c.chi, c.N));
+        CHK(coarse_coefficients(h, cur, d, c));
+        h->L.push_back(c);
+        if (h->L.size() >= 64) break;
+    }
+    const size_t nl = h->L.size();
+    for (size_t i = 0; i < nl; ++i) {
+        Level& l = h->L[i];
+        // k, c, chi already allocated: allocate the rest
+        const bool fine = i == 0, last = i + 1 == nl;
+        CHK(h->alloc(&l.coef, 7 * (int64_t)(l.N + 1)));
+        if (h->o.precision == STMG_MIXED) CHK(h->alloc(&l.coef32, 7 * (int64_t)(l.N + 1)));
+        if (last) CHK(h->alloc(&l.thomas, 3 * (int64_t)(l.N + 1)));
+        if (h->o.precision == STMG_FP64 || fine) {
+            CHK(h->alloc(&l.u, l.elems()));
+            CHK(h->alloc(&l.b, l.elems()));
+            CHK(h->alloc(&l.t, l.elems()));
+        }
+        if (h->o.precision == STMG_MIXED) {
+            CHK(h->alloc(&l.u32, l.elems()));
+            CHK(h->alloc(&l.b32, l.elems()));
+            CHK(h->alloc(&l.t32, l.elems()));
+        }
+        CHK(finish_level(h, l, last));
+    }
+    Level& fl = h->L[0];
+    CHK(h->alloc(&h->bload, fl.elems()));
+    launch_load_vector(d_q, p.q_uniform, fl.N, fl.Nt, fl.h, h->bload, fl.P, h->s);
+    HIPCHK(hipGetLastError());
+    // partial-sum buffer: largest fused pass on the fine level, reductions, gradient
+    int64_t need = 1024;
+    for (int S = 0; S <= 4; ++S) need = std::max<int64_t>(need, fused_parts(fl.N, fl.Nt, S));
+    need = std::max<int64_t>(need, (int64_t)gradient_chunks(fl.Nt) * fl.N);
+    CHK(h->alloc(&h->parts, need));
+    h->nparts = need;
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+// ------------------------------------------------------------------------------------
+// V-cycle (Algorithm 1)
+// ------------------------------------------------------------------------------------
+
+double level_pass_bytes(const Level& l, int sizeofT, bool read_u) {
+    return (double)l.dofs() * sizeofT * (read_u ? 3.0 : 2.0);
+}
+
+void timer_begin(stmg_ctx* h, bool on) {
+    if (!on) return;
+    KernelTimer& T = h->timer;
+    if (T.used == T.ev.size()) {
+        hipEvent_t a, b;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        T.ev.push_back({a, b});
+        T.bytes.push_back(0);
+    }
+    (void)hipEventRecord(T.ev[T.used].first, h->s);
+}
+
+void timer_end(stmg_ctx* h, bool on, double bytes) {
+    if (!on) return;
+    KernelTimer& T = h->timer;
+    (void)hipEventRecord(T.ev[T.used].second, h->s);
+    T.bytes[T.used] = bytes;
+    ++T.used;
+}
+
+// Sweep chunk sizes for nu steps: ceil(nu/4) fused passes of near-equal size.
+std::vector<int> chunks_of(int nu) {
+    const int n = nu <= 4 ? 1 : (nu + 3) / 4;
+    std::vector<int> c;
+    for (int k = 0; k < n; ++k) c.push_back(nu / n + (k < nu % n ? 1 : 0));
+    return c;
+}
+
+template <typename T>
+int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) {
+    Level& lv = h->L[l];
+    Level& cl = h->L[l + 1];
+    const auto V = view<T>(lv, h->o.omega);
+    T*& u = U<T>(lv);
+    T* b = B<T>(lv);
+    T*& t = Tt<T>(lv);
+    const bool timed = h->o.time_kernels && l == 0;
+    if (h->o.fused) {
+        std::vector<int> ch = chunks_of(nu);
+        bool zero = zero_start;
+        for (size_t k = 0; k < ch.size(); ++k) {
+            FusedPass fp{};
+            fp.trans = trans;
+            fp.sweeps = ch[k];
+            fp.zero_in = zero;
+            const bool lastc = k + 1 == ch.size();
+            fp.tail = lastc ? lv.dir : 0;
+            fp.bc = B<T>(cl);
+            fp.Pbc = cl.P;
+            fp.Nc = cl.N;
+            fp.Ntc = cl.Nt;
+            timer_begin(h, timed);
+            launch_fused<T>(V, fp, u, b, t, h->s);
+            timer_end(h, timed, level_pass_bytes(lv, sizeof(T), !zero) + (lastc ? (double)cl.dofs() * sizeof(T) : 0.0));
+            std::swap(u, t);
+            zero = false;
+        }
+    } else {
+        for (int k = 0; k < nu; ++k) {
+            launch_apply<T>(V, trans, APPLY_JACOBI, u, b, t, zero_start && k == 0, h->s);
+            std::swap(u, t);
+        }
+        if (nu == 0 && zero_start) launch_fill<T>(u, lv.elems(), T(0), h->s);
+        launch_apply<T>(V, trans, APPLY_RESIDUAL, u, b, t, false, h->s);
+        launch_restrict<T>(lv.dir, V, t, B<T>(cl), cl.P, h->s);
+    }
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+template <typename T>
+int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
+    Level& lv = h->L[l];
+    Level& cl = h->L[l + 1];
+    const auto V = view<T>(lv, h->o.omega);
+    T*& u = U<T>(lv);
+    T* b = B<T>(lv);
+    T*& t = Tt<T>(lv);
+    const T* z = U<T>(cl);
+    const bool timed = h->o.time_kernels && l == 0;
+    if (h->o.fused) {
+        std::vector<int> ch = chunks_of(nu);
+        for (size_t k = 0; k < ch.size(); ++k) {
+            FusedPass fp{};
+            fp.trans = trans;
+            fp.sweeps = ch[k];
+            fp.prolong = k == 0 ? lv.dir : 0;
+            fp.z = z;
+            fp.Pz = cl.P;
+            fp.Nc = cl.N;
+            fp.Ntc = cl.Nt;
+            const bool lastc = k + 1 == ch.size();
+            fp.tail = (lastc && norm) ? 'n' : 0;
+            fp.parts = h->parts;
+            timer_begin(h, timed);
+            int nw = launch_fused<T>(V, fp, u, b, t, h->s);
+            timer_end(h, timed, level_pass_bytes(lv, sizeof(T), true) + (k == 0 ? (double)cl.dofs() * sizeof(T) : 0.0));
+            if (lastc && norm) h->norm_parts = nw;
+            std::swap(u, t);
+        }
+    } else {
+        launch_prolong_add<T>(lv.dir, V, z, cl.P, u, h->s);
+        for (int k = 0; k < nu; ++k) {
+            launch_apply<T>(V, trans, APPLY_JACOBI, u, b, t, false, h->s);
+            std::swap(u, t);
+        }
+        if (norm) {
+            launch_residual_sumsq_partial<T>(V, trans, u, b, h->parts, h->s);
+            h->norm_parts = reduce_parts(lv.Nt + 1);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+template <typename T>
+int coarsest_solve(stmg_ctx* h, int l, int trans) {
+    Level& lv = h->L[l];
+    const auto V = view<double>(lv, h->o.omega);
+    launch_coarsest<T>(V, lv.thomas, lv.thomas + (lv.N + 1), B<T>(lv), U<T>(lv), trans, h->s);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+template <typename T>
+int vcycle(stmg_ctx* h, int l, int trans, bool zero_start, bool norm) {
+    const int last = (int)h->L.size() - 1;
+    if (l == last) return coarsest_solve<T>(h, l, trans);
+    CHK(pre_smooth_restrict<T>(h, l, trans, zero_start, h->o.nu));
+    CHK(vcycle<T>(h, l + 1, trans, true, false));
+    CHK(prolong_post_smooth<T>(h, l, trans, h->o.nu, norm));
+    return 0;
+}
+
+// sqrt(sum of the norm partials) -> host
+int finish_norm(stmg_ctx* h, int nparts, double* out) {
+    launch_reduce_final(h->parts, nparts, 1.0, h->dscal, h->s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->hscal, h->dscal, sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    *out = std::sqrt(h->hscal[0]);
+    return 0;
+}
+
+int residual_norm64(stmg_ctx* h, int trans, double* out) {
+    Level& f = h->L[0];
+    launch_residual_sumsq_partial<double>(view<double>(f, h->o.omega), trans, f.u, f.b, h->parts, h->s);
+    HIPCHK(hipGetLastError());
+    return finish_norm(h, reduce_parts(f.Nt + 1), out);
+}
+
+int norm64(stmg_ctx* h, const double* x, const Level& l, double* out) {
+    launch_sumsq_partial<double>(x, l.Nt + 1, l.N + 1, l.P, h->parts, h->s);
+    HIPCHK(hipGetLastError());
+    return finish_norm(h, reduce_parts(l.Nt + 1), out);
+}
+
+double cycle_dof_updates(const stmg_ctx* h) {
+    double s = 0;
+    for (size_t i = 0; i + 1 < h->L.size(); ++i) s += 2.0 * h->o.nu * (double)h->L[i].dofs();
+    return s;
+}
+
+void collect_timer(stmg_ctx* h, stmg_stats* st) {
+    KernelTimer& T = h->timer;
+    if (st) {
+        for (size_t i = 0; i < T.used; ++i) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, T.ev[i].first, T.ev[i].second) == hipSuccess) {
+                st->fine_kernel_ms += ms;
+                st->fine_kernel_bytes += T.bytes[i];
+                st->fine_kernel_launches += 1;
+            }
+        }
+    }
+    T.used = 0;
+}
+
+// ------------------------------------------------------------------------------------
+// Solve loops
+// ------------------------------------------------------------------------------------
+
+int set_rhs(stmg_ctx* h, int trans, const double* d_rhs) {
+    Level& f = h->L[0];
+    if (d_rhs) {
+        launch_copy2d<double, double>(d_rhs, f.N + 1, f.b, f.P, f.Nt + 1, f.N + 1, 1.0, h->s);
+    } else {
+        const double scale = trans ? f.tau / h->p.theta_ref : 1.0;
+        launch_copy2d<double, double>(h->bload, f.P, f.b, f.P, f.Nt + 1, f.N + 1, scale, h->s);
+    }
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int set_u0(stmg_ctx* h, const double* d_u0) {
+    Level& f = h->L[0];
+    if (d_u0)
+        launch_copy2d<double, double>(d_u0, f.N + 1, f.u, f.P, f.Nt + 1, f.N + 1, 1.0, h->s);
+    else
+        launch_fill<double>(f.u, f.elems(), 0.0, h->s);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int classify(const stmg_options& o, double r, bool* stop) {
+    if (!std::isfinite(r) || r > o.diverge) { *stop = true; return STMG_DIVERGED; }
+    if (r < o.tol) { *stop = true; return STMG_OK; }
+    *stop = false;
+    return STMG_NOT_CONVERGED;
+}
+
+int solve_fp64(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
+    Level& f = h->L[0];
+    double nb;
+    CHK(norm64(h, f.b, f, &nb));
+    if (!(nb > 0)) return fail(STMG_EINVAL, "right-hand side is zero");
+    double r;
+    CHK(residual_norm64(h, trans, &r));
+    r /= nb;
+    if (st) st->history[0] = r;
+    const double r0 = r;
+    int cyc = 0, code = STMG_NOT_CONVERGED;
+    bool stop = false;
+    const bool timed = h->o.time_kernels != 0;
+    const bool single = h->L.size() == 1;
+    for (cyc = 1; cyc <= h->o.max_cycles; ++cyc) {
+        CHK(vcycle<double>(h, 0, trans, false, true));
+        double ss;
+        if (single)
+            CHK(residual_norm64(h, trans, &ss));
+        else
+            CHK(finish_norm(h, h->norm_parts, &ss));
+        r = ss / nb;
+        if (timed) collect_timer(h, st);
+        if (st) st->history[cyc] = r;
+        code = classify(h->o, r, &stop);
+        if (stop) break;
+    }
+    if (cyc > h->o.max_cycles) cyc = h->o.max_cycles;
+    if (st) {
+        st->cycles = cyc;
+        st->rel_residual = r;
+        st->conv_factor = (r0 > 0 && cyc > 0) ? std::pow(r / r0, 1.0 / cyc) : NAN;
+        st->dof_updates = cyc * cycle_dof_updates(h);
+    }
+    *status = code;
+    return 0;
+}
+
+// Mixed precision: FP64 defect correction around FP32 V-cycles.  Each outer step
+// forms r = b - J u in FP64, scales it by s (RMS of the previous residual) into the
+// FP32 right-hand side, runs one FP32 V-cycle from zero (FP64 coarsest solve) and
+// applies u += s e in FP64.
+int solve_mixed(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
+    Level& f = h->L[0];
+    const auto V64 = view<double>(f, h->o.omega);
+    double nb;
+    CHK(norm64(h, f.b, f, &nb));
+    if (!(nb > 0)) return fail(STMG_EINVAL, "right-hand side is zero");
+    const double rms_den = std::sqrt((double)f.dofs());
+    launch_apply<double>(V64, trans, APPLY_RESIDUAL, f.u, f.b, f.t, false, h->s);
+    double r;
+    CHK(norm64(h, f.t, f, &r));
+    r /= nb;
+    if (st) st->history[0] = r;
+    const double r0 = r;
+    int cyc = 0, code = STMG_NOT_CONVERGED;
+    bool stop = false;
+    double scale = r * nb / rms_den;
+    for (cyc = 1; cyc <= h->o.max_cycles; ++cyc) {
+        if (!(scale > 0)) scale = 1.0;
+        launch_copy2d<double, float>(f.t, f.P, f.b32, f.P, f.Nt + 1, f.N + 1, 1.0 / scale, h->s);
+        CHK(vcycle<float>(h, 0, trans, true, false));
+        launch_axpy2d<float>(f.u32, f.P, f.u, f.P, f.Nt + 1, f.N + 1, scale, h->s);
+        launch_apply<double>(V64, trans, APPLY_RESIDUAL, f.u, f.b, f.t, false, h->s);
+        HIPCHK(hipGetLastError());
+        double rn;
+        CHK(norm64(h, f.t, f, &rn));
+        r = rn / nb;
+        scale = rn / rms_den;
+        if (st) st->history[cyc] = r;
+        code = classify(h->o, r, &stop);
+        if (stop) break;
+    }
+    if (cyc > h->o.max_cycles) cyc = h->o.max_cycles;
+    if (st) {
+        st->cycles = cyc;
+        st->rel_residual = r;
+        st->conv_factor = (r0 > 0 && cyc > 0) ? std::pow(r / r0, 1.0 / cyc) : NAN;
+        st->dof_updates = cyc * cycle_dof_updates(h);
+    }
+    *status = code;
+    return 0;
+}
+
+int solve(stmg_ctx* h, int trans, const double* d_rhs, const double* d_u0, double* d_u,
+          stmg_stats* st) {
+    if (!h) return fail(STMG_EINVAL, "null handle");
+    if (!d_u) return fail(STMG_EINVAL, "null output");
+    auto t0 = std::chrono::steady_clock::now();
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->n_levels = (int)h->L.size();
+    }
+    h->timer.used = 0;
+    CHK(set_rhs(h, trans, d_rhs));
+    CHK(set_u0(h, d_u0));
+    int status = STMG_NOT_CONVERGED;
+    if (h->o.precision == STMG_FP64)
+        CHK(solve_fp64(h, trans, st, &status));
+    else
+        CHK(solve_mixed(h, trans, st, &status));
+    Level& f = h->L[0];
+    launch_copy2d<double, double>(f.u, f.P, d_u, f.N + 1, f.Nt + 1, f.N + 1, 1.0, h->s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->s));
+    if (st) {
+        st->status = status;
+        st->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    g_err.clear();
+    return status;
+}
+
+int check_level(stmg_ctx* h, int level) {
+    if (!h) return fail(STMG_EINVAL, "null handle");
+    if (level < 0 || level >= (int)h->L.size()) return fail(STMG_EINVAL, "level out of range");
+    if (h->o.precision != STMG_FP64)
+        return fail(STMG_EUNSUPPORTED, "per-level entry points need an FP64 handle");
+    return 0;
+}
+
+int copy_in(stmg_ctx* h, const Level& l, const double* src, double* dst) {
+    launch_copy2d<double, double>(src, l.N + 1, dst, l.P, l.Nt + 1, l.N + 1, 1.0, h->s);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+int copy_out(stmg_ctx* h, const Level& l, const double* src, double* dst) {
+    launch_copy2d<double, double>(src, l.P, dst, l.N + 1, l.Nt + 1, l.N + 1, 1.0, h->s);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int reassemble(stmg_ctx* h, bool check_path) {
+    CHK(level0_material(h));
+    for (size_t i = 0; i < h->L.size(); ++i) {
+        Level& l = h->L[i];
+        double st[4];
+        CHK(fetch_stats(h, l, st));
+        if (i + 1 < h->L.size()) {
+            double lam;
+            char d = choose_direction(h, l, st, &lam);
+            if (check_path && d != l.dir) return fail(STMG_EUNSUPPORTED, "coarsening path changed with the new design");
+            l.lambda = lam;
+            CHK(coarse_coefficients(h, l, l.dir, h->L[i + 1]));
+        }
+        l.W = level_w(h->o, l, st);
+        CHK(finish_level(h, l, i + 1 == h->L.size()));
+    }
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+}  // namespace
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+
+extern "C" {
+
+int stmg_default_options(stmg_options* o) {
+    if (!o) return fail(STMG_EINVAL, "null options");
+    std::memset(o, 0, sizeof(*o));
+    o->nu = 2;
+    o->omega = 0.5;
+    o->lambda_crit = 0.25;
+    o->max_levels = 0;
+    o->min_coarse_dofs = 1024;
+    o->M_min_elems = 0;
+    o->reassembly = STMG_REASSEMBLE_R;
+    o->deff_mode = 0;
+    o->tol = 1e-10;
+    o->diverge = 1e9;
+    o->max_cycles = 100;
+    o->precision = STMG_FP64;
+    o->w_diri_override = 0.0;
+    o->fused = 1;
+    o->time_kernels = 0;
+    return 0;
+}
+
+int stmg_footprint(const stmg_problem* p, const stmg_options* o, size_t* bytes) {
+    CHK(validate(p, o));
+    if (!bytes) return fail(STMG_EINVAL, "null output");
+    *bytes = footprint_of(p, o);
+    return 0;
+}
+
+int stmg_create(stmg_t* handle, const stmg_problem* p, const stmg_options* o,
+                const double* d_rho, const double* d_q, void* stream) {
+    if (!handle) return fail(STMG_EINVAL, "null handle pointer");
+    *handle = nullptr;
+    CHK(validate(p, o));
+    if (!d_rho) return fail(STMG_EINVAL, "null density");
+    auto* h = new stmg_ctx();
+    h->p = *p;
+    h->o = *o;
+    h->s = static_cast<hipStream_t>(stream);
+    int rc = 0;
+    do {
+        if (hipHostMalloc(&h->hscal, 64 * sizeof(double)) != hipSuccess) {
+            rc = fail(STMG_ENOMEM, "hipHostMalloc failed");
+            break;
+        }
+        if ((rc = h->alloc(&h->rho, p->n_el)) < 0) break;
+        if ((rc = h->alloc(&h->kp, p->n_el)) < 0) break;
+        if ((rc = h->alloc(&h->cpd, p->n_el)) < 0) break;
+        if ((rc = h->alloc(&h->simp, 8)) < 0) break;
+        if ((rc = h->alloc(&h->stats, 8)) < 0) break;
+        if ((rc = h->alloc(&h->dscal, 8)) < 0) break;
+        double sp[6] = {p->k_ins, p->k_con, p->p_k, p->c_ins, p->c_con, p->p_c};
+        if (hipMemcpyAsync(h->simp, sp, sizeof(sp), hipMemcpyHostToDevice, h->s) != hipSuccess ||
+            hipMemcpyAsync(h->rho, d_rho, (size_t)p->n_el * 8, hipMemcpyDeviceToDevice, h->s) != hipSuccess) {
+            rc = fail(STMG_EHIP, "copy of the design failed");
+            break;
+        }
+        rc = build(h, d_q);
+    } while (0);
+    if (rc < 0) {
+        (void)hipStreamSynchronize(h->s);
+        delete h;
+        return rc;
+    }
+    *handle = h;
+    g_err.clear();
+    return 0;
+}
+
+int stmg_set_design(stmg_t h, const double* d_rho) {
+    if (!h || !d_rho) return fail(STMG_EINVAL, "null argument");
+    // keep the old design to restore the handle if the path would change
+    std::vector<double> old((size_t)h->p.n_el);
+    HIPCHK(hipMemcpyAsync(old.data(), h->rho, old.size() * 8, hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipMemcpyAsync(h->rho, d_rho, old.size() * 8, hipMemcpyDeviceToDevice, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    int rc = reassemble(h, h->o.deff_mode == 0);
+    if (rc == STMG_EUNSUPPORTED) {
+        std::string msg = g_err;
+        HIPCHK(hipMemcpyAsync(h->rho, old.data(), old.size() * 8, hipMemcpyHostToDevice, h->s));
+        HIPCHK(hipStreamSynchronize(h->s));
+        CHK(reassemble(h, false));
+        return fail(STMG_EUNSUPPORTED, msg);
+    }
+    return rc;
+}
+
+int stmg_solve_forward(stmg_t h, const double* d_rhs, const double* d_u0, double* d_u,
+                       stmg_stats* st) {
+    return solve(h, 0, d_rhs, d_u0, d_u, st);
+}
+
+int stmg_solve_adjoint(stmg_t h, const double* d_rhs, const double* d_l0, double* d_lambda,
+                       stmg_stats* st) {
+    return solve(h, 1, d_rhs, d_l0, d_lambda, st);
+}
+
+int stmg_objective(stmg_t h, const double* d_u, double* theta) {
+    if (!h || !d_u || !theta) return fail(STMG_EINVAL, "null argument");
+    Level& f = h->L[0];
+    launch_dot_partial(h->bload, d_u, f.Nt + 1, f.N + 1, f.P, f.N + 1, h->parts, h->s);
+    // Theta = b^T u dt / Theta_ref  (Section 7.1)
+    launch_reduce_final(h->parts, reduce_parts(f.Nt + 1), f.tau / h->p.theta_ref, h->dscal, h->s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->hscal, h->dscal, sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    *theta = h->hscal[0];
+    return 0;
+}
+
+int stmg_gradient(stmg_t h, const double* d_u, const double* d_lambda, double* d_grad) {
+    if (!h || !d_u || !d_lambda || !d_grad) return fail(STMG_EINVAL, "null argument");
+    Level& f = h->L[0];
+    const int chunks = gradient_chunks(f.Nt);
+    launch_gradient_partial(d_u, d_lambda, f.N, f.Nt, f.N + 1, f.N + 1, h->kp, h->cpd, f.h, f.tau,
+                            h->parts, h->s);
+    launch_gradient_final(h->parts, f.N, chunks, d_grad, h->s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+int stmg_get_info(stmg_t h, stmg_info* info) {
+    if (!h || !info) return fail(STMG_EINVAL, "null argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_levels = (int)h->L.size();
+    for (size_t i = 0; i < h->L.size() && i < 64; ++i) {
+        const Level& l = h->L[i];
+        info->n_el[i] = l.N;
+        info->n_t[i] = l.Nt;
+        info->h[i] = l.h;
+        info->tau[i] = l.tau;
+        info->w_diri[i] = l.W;
+        info->lambda_eff[i] = l.lambda;
+        if (i + 1 < h->L.size() && i < 63) info->path[i] = l.dir;
+    }
+    info->device_bytes = h->bytes;
+    return 0;
+}
+
+int stmg_destroy(stmg_t h) {
+    if (!h) return 0;
+    (void)hipStreamSynchronize(h->s);
+    delete h;
+    return 0;
+}
+
+int stmg_level_apply(stmg_t h, int level, int transpose, const double* d_x, double* d_y) {
+    CHK(check_level(h, level));
+    if (!d_x || !d_y) return fail(STMG_EINVAL, "null vector");
+    Level& l = h->L[level];
+    CHK(copy_in(h, l, d_x, l.u));
+    launch_apply<double>(view<double>(l, h->o.omega), transpose, APPLY_J, l.u, l.b, l.t, false, h->s);
+    CHK(copy_out(h, l, l.t, d_y));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+int stmg_level_smooth(stmg_t h, int level, int transpose, int nu, const double* d_b, double* d_u) {
+    CHK(check_level(h, level));
+    if (!d_b || !d_u || nu < 0) return fail(STMG_EINVAL, "bad argument");
+    Level& l = h->L[level];
+    CHK(copy_in(h, l, d_b, l.b));
+    CHK(copy_in(h, l, d_u, l.u));
+    const auto V = view<double>(l, h->o.omega);
+    if (h->o.fused) {
+        for (int S : chunks_of(nu)) {
+            FusedPass fp{};
+            fp.trans = transpose;
+            fp.sweeps = S;
+            launch_fused<double>(V, fp, l.u, l.b, l.t, h->s);
+            std::swap(l.u, l.t);
+        }
+    } else {
+        for (int k = 0; k < nu; ++k) {
+            launch_apply<double>(V, transpose, APPLY_JACOBI, l.u, l.b, l.t, false, h->s);
+            std::swap(l.u, l.t);
+        }
+    }
+    CHK(copy_out(h, l, l.u, d_u));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+int stmg_level_presmooth_restrict(stmg_t h, int level, int transpose, int nu, const double* d_b,
+                                  double* d_u, double* d_bc) {
+    CHK(check_level(h, level));
+    if (level + 1 >= (int)h->L.size()) return fail(STMG_EINVAL, "coarsest level has no restriction");
+    if (!d_b || !d_u || !d_bc || nu < 0) return fail(STMG_EINVAL, "bad argument");
+    Level& l = h->L[level];
+    Level& c = h->L[level + 1];
+    CHK(copy_in(h, l, d_b, l.b));
+    CHK(copy_in(h, l, d_u, l.u));
+    CHK(pre_smooth_restrict<double>(h, level, transpose, false, nu));
+    CHK(copy_out(h, l, l.u, d_u));
+    CHK(copy_out(h, c, c.b, d_bc));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+int stmg_level_prolong_postsmooth(stmg_t h, int level, int transpose, int nu, const double* d_b,
+                                  const double* d_z, double* d_u) {
+    CHK(check_level(h, level));
+    if (level + 1 >= (int)h->L.size()) return fail(STMG_EINVAL, "coarsest level has no prolongation");
+    if (!d_b || !d_u || !d_z || nu < 0) return fail(STMG_EINVAL, "bad argument");
+    Level& l = h->L[level];
+    Level& c = h->L[level + 1];
+    CHK(copy_in(h, l, d_b, l.b));
+    CHK(copy_in(h, l, d_u, l.u));
+    CHK(copy_in(h, c, d_z, c.u));
+    CHK(prolong_post_smooth<double>(h, level, transpose, nu, false));
+    CHK(copy_out(h, l, l.u, d_u));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+int stmg_level_coarsest_solve(stmg_t h, int transpose, const double* d_b, double* d_z) {
+    if (!h) return fail(STMG_EINVAL, "null handle");
+    const int last = (int)h->L.size() - 1;
+    CHK(check_level(h, last));
+    if (!d_b || !d_z) return fail(STMG_EINVAL, "null vector");
+    Level& l = h->L[last];
+    CHK(copy_in(h, l, d_b, l.b));
+    CHK(coarsest_solve<double>(h, last, transpose));
+    CHK(copy_out(h, l, l.u, d_z));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+int stmg_vcycle(stmg_t h, int transpose, const double* d_b, double* d_u, double* rel_res) {
+    CHK(check_level(h, 0));
+    if (!d_b || !d_u) return fail(STMG_EINVAL, "null vector");
+    Level& f = h->L[0];
+    CHK(copy_in(h, f, d_b, f.b));
+    CHK(copy_in(h, f, d_u, f.u));
+    CHK(vcycle<double>(h, 0, transpose, false, false));
+    if (rel_res) {
+        double nb, r;
+        CHK(norm64(h, f.b, f, &nb));
+        CHK(residual_norm64(h, transpose, &r));
+        *rel_res = r / nb;
+    }
+    CHK(copy_out(h, f, f.u, d_u));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+const char* stmg_status_string(int status) {
+    switch (status) {
+        case STMG_OK: return "ok";
+        case STMG_NOT_CONVERGED: return "not converged (cycle cap reached)";
+        case STMG_DIVERGED: return "diverged";
+        case STMG_EINVAL: return "invalid argument";
+        case STMG_ENOMEM: return "out of device memory";
+        case STMG_EHIP: return "HIP runtime error";
+        case STMG_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char* stmg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

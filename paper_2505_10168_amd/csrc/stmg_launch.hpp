@@ -1,0 +1,102 @@
+// Host-side launch wrappers of the STMG kernels (internal to libstmg).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "stmg_device.hpp"
+
+namespace stmg {
+
+// Operator modes of the one-thread-per-DOF kernel.
+enum ApplyMode { APPLY_J = 0, APPLY_RESIDUAL = 1, APPLY_JACOBI = 2 };
+
+// ---- setup (Section 2.1, Section 5.1, Appendix A) ---------------------------------
+void launch_simp(const double* rho, int n, double v_ins, double v_con, double p, double* out,
+                 hipStream_t s);
+void launch_simp_derivative(const double* rho, int n, double v_ins, double v_con, double p,
+                            double* out, hipStream_t s);
+// method: 0 = R (resistivity), 1 = K (conductivity), 2 = D (design field + SIMP)
+void launch_coarsen_x(const double* k, const double* c, const double* chi, int n_coarse,
+                      int method, const double* simp_params, double* kc, double* cc,
+                      double* chic, hipStream_t s);
+// out[0] = min_e k_e/c_e, out[1] = max_e k_e/c_e, out[2] = max_e c_e, out[3] = max_e k_e
+void launch_level_stats(const double* k, const double* c, int n, double* out, hipStream_t s);
+// coef: 7 arrays of N+1 doubles (lo, di, up, mlo, mdi, mup, wd); coef32 optional FP32 copy
+void launch_stencil_coef(const double* k, const double* c, int N, double h, double tau,
+                         double omega, double* coef, float* coef32, hipStream_t s);
+void launch_thomas_factors(const double* coef, int N, double* cp, double* inv, hipStream_t s);
+void launch_load_vector(const double* q, double q0, int N, int Nt, double h, double* b,
+                        int64_t P, hipStream_t s);
+
+// ---- data movement ------------------------------------------------------------------
+template <typename T>
+void launch_fill(T* x, int64_t n, T v, hipStream_t s);
+// dst[r*dp + c] = (Tout)(scale * src[r*sp + c]) for r < rows, c < cols
+template <typename Tin, typename Tout>
+void launch_copy2d(const Tin* src, int64_t sp, Tout* dst, int64_t dp, int rows, int cols,
+                   double scale, hipStream_t s);
+// dst += scale * src (2-D, FP64 destination)
+template <typename Tin>
+void launch_axpy2d(const Tin* src, int64_t sp, double* dst, int64_t dp, int rows, int cols,
+                   double scale, hipStream_t s);
+
+// ---- reference (one thread per DOF) kernels -----------------------------------------
+template <typename T>
+void launch_apply(const LevelView<T>& L, int trans, int mode, const T* x, const T* b, T* y,
+                  bool zero_in, hipStream_t s);
+template <typename T>
+void launch_restrict(char dir, const LevelView<T>& F, const T* r, T* bc, int64_t Pc,
+                     hipStream_t s);
+template <typename T>
+void launch_prolong_add(char dir, const LevelView<T>& F, const T* z, int64_t Pc, T* u,
+                        hipStream_t s);
+// Exact coarsest solve (time stepping + Thomas) in FP64 on vectors of type TV.
+template <typename TV>
+void launch_coarsest(const LevelView<double>& L, const double* cp, const double* inv,
+                     const TV* b, TV* u, int trans, hipStream_t s);
+
+// ---- reductions (deterministic: fixed partition, fixed tree) ------------------------
+int reduce_parts(int rows);
+template <typename T>
+void launch_sumsq_partial(const T* x, int rows, int cols, int64_t P, double* parts,
+                          hipStream_t s);
+void launch_dot_partial(const double* a, const double* b, int rows, int cols, int64_t Pa,
+                        int64_t Pb, double* parts, hipStream_t s);
+// out[0] = scale * sum(parts[0..n))
+void launch_reduce_final(const double* parts, int n, double scale, double* out, hipStream_t s);
+// residual norm^2 of the fine level, one-thread-per-DOF: parts from b - J u
+template <typename T>
+void launch_residual_sumsq_partial(const LevelView<T>& L, int trans, const T* u, const T* b,
+                                   double* parts, hipStream_t s);
+
+// ---- sensitivities (Section 7) -------------------------------------------------------
+int gradient_chunks(int Nt);
+void launch_gradient_partial(const double* u, const double* lam, int N, int Nt, int64_t Pu,
+                             int64_t Pl, const double* kp, const double* cp, double h,
+                             double tau, double* parts, hipStream_t s);
+void launch_gradient_final(const double* parts, int N, int chunks, double* grad,
+                           hipStream_t s);
+
+// ---- fused streaming kernels ----------------------------------------------------------
+// Pass descriptor of one fused streaming launch on a level.
+struct FusedPass {
+    int trans;          // 0: J, 1: J^T (streams backwards in time)
+    int sweeps;         // Jacobi steps fused in this pass (0..4)
+    int zero_in;        // input u is identically zero (not read)
+    char prolong;       // 0, 'x' or 't': add P z to the input first
+    const void* z;      // coarse correction (type T), pitch Pz
+    int64_t Pz;
+    int Nc;             // coarse elements (prolong/restrict)
+    int Ntc;            // coarse steps
+    char tail;          // 0: none, 'x'/'t': residual + restriction, 'n': residual norm
+    void* bc;           // restricted residual output (type T), pitch Pbc
+    int64_t Pbc;
+    double* parts;      // norm partials ('n')
+};
+template <typename T>
+int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T* b, T* out,
+                 hipStream_t s);
+int fused_parts(int N, int Nt, int sweeps);
+
+}  // namespace stmg

@@ -1,0 +1,89 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the header
+declares, fills defaults, sizes footprints and rejects bad arguments before any
+device work (no GPU needed)."""
+from __future__ import annotations
+
+import ctypes as C
+import re
+from pathlib import Path
+
+import pytest
+
+from paper_2505_10168_amd import binding as B
+
+HEADER = Path(__file__).resolve().parent.parent / "include" / "stmg.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(stmg_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_and_library_exports_every_entry_point():
+    names = declared_functions()
+    assert len(names) >= 18
+    assert sorted(B.EXPORTED) == names
+    lib = C.CDLL(str(B.LIB_PATH))
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layouts_match_header_sizes():
+    # field counts of the ctypes mirrors equal the header's struct members
+    text = HEADER.read_text()
+    for cname, cls in (("stmg_problem", B.stmg_problem), ("stmg_options", B.stmg_options)):
+        body = re.search(r"typedef struct \{([^}]*)\}\s*" + cname + ";", text).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        members = [m.strip() for decl in body.split(";") if decl.strip()
+                   for m in decl.strip().split(None, 1)[1].split(",")]
+        assert [f[0] for f in cls._fields_] == members
+
+
+def test_default_options():
+    o = B.stmg_default_options()
+    assert (o.nu, o.omega, o.lambda_crit, o.min_coarse_dofs, o.max_cycles) == (2, 0.5, 0.25, 1024, 100)
+    assert (o.tol, o.diverge, o.reassembly, o.precision, o.fused) == (1e-10, 1e9, 0, 0, 1)
+
+
+def test_footprint_grows_with_grid_and_precision():
+    o = B.make_options()
+    small = B.stmg_footprint(B.Problem(64, 64).c_struct(), o)
+    big = B.stmg_footprint(B.Problem(1024, 4096).c_struct(), o)
+    assert big > 20 * small > 0
+    # FP64 vectors: at least u, b, t and the load on the fine grid
+    assert big >= 4 * 4097 * 1056 * 8
+    mixed = B.stmg_footprint(B.Problem(1024, 4096).c_struct(), B.make_options(precision=B.STMG_MIXED))
+    assert mixed < big
+    fixed = B.stmg_footprint(B.Problem(1024, 4096).c_struct(), B.make_options(deff_mode=1))
+    assert fixed <= big
+
+
+@pytest.mark.parametrize("field,value", [("n_el", 0), ("n_t", -1), ("length", 0.0),
+                                         ("k_ins", -1.0), ("theta_ref", 0.0)])
+def test_create_rejects_bad_problem_without_device_work(field, value):
+    p = B.Problem(8, 8).c_struct()
+    setattr(p, field, value)
+    o = B.make_options()
+    h = C.c_void_p()
+    rc = B.lib.stmg_create(C.byref(h), C.byref(p), C.byref(o), C.c_void_p(1), None, None)
+    assert rc == B.STMG_EINVAL and not h.value
+    assert B.lib.stmg_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("nu", -1), ("omega", 0.0), ("max_cycles", 0),
+                                         ("max_cycles", 5000), ("precision", 7), ("reassembly", 9),
+                                         ("min_coarse_dofs", 0), ("tol", -1.0)])
+def test_create_rejects_bad_options(field, value):
+    p = B.Problem(8, 8).c_struct()
+    o = B.make_options(**{field: value})
+    h = C.c_void_p()
+    rc = B.lib.stmg_create(C.byref(h), C.byref(p), C.byref(o), C.c_void_p(1), None, None)
+    assert rc == B.STMG_EINVAL
+
+
+def test_null_arguments():
+    assert B.lib.stmg_default_options(None) == B.STMG_EINVAL
+    assert B.lib.stmg_solve_forward(None, None, None, None, None) == B.STMG_EINVAL
+    assert B.lib.stmg_objective(None, None, None) == B.STMG_EINVAL
+    assert B.lib.stmg_destroy(None) == 0
+    assert B.lib.stmg_status_string(B.STMG_DIVERGED) == b"diverged"
