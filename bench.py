@@ -1,0 +1,201 @@
+"""Benchmark of the STMG hot path on one MI355X.
+
+One step = one pass of the whole path on a device-resident design field:
+re-assemble every level from rho (SIMP, Algorithm 3 decision, R-averaged coarse
+operators), forward STMG solve to the relative-residual tolerance, adjoint STMG solve,
+objective and gradient.  Reported value: DOF-updates/s = (sum over both solves of
+cycles * sum_{l < N_l} 2 nu n_l) / wall time of the K timed steps.
+
+Prints ONE JSON line (rank 0).  --gpus above 1 is rejected: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+if str(ROOT) not in sys.path:
+    sys.path.insert(0, str(ROOT))
+
+METRIC = "STMG DOF-updates/s + % HBM roofline; p50/p99 solve latency at 1e-10 resid"
+HBM_PEAK_GBS = 8000.0
+
+# Workloads: name -> (nu, precision).  nu = 2 unless V(2,2) fails to converge within
+# the cycle cap, then the paper's default nu = 5.
+WORKLOADS = {
+    "uniform_64x64": 2,
+    "block_1024x4096": 5,
+    "block_2048x8192": 5,
+    "boxfilt_8192x65536": 2,
+}
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else float("nan")
+
+
+def cpu_baseline(workload: str, nu: int, budget_s: float) -> dict:
+    """Time the oracle's forward V-cycles on the same input in a single-threaded child
+    process, for about budget_s seconds."""
+    code = f"""
+import os, sys, time, json
+sys.path.insert(0, {str(ROOT)!r})
+import numpy as np
+import oracle as O
+from paper_2505_10168_amd import inputs as I
+w = I.workload({workload!r})
+mat = O.Material(w.kappa_min, 1.0, 1.0, 1.0)
+lv = O.make_fine_level(w.rho, mat, w.n_t, w.length, w.t_final)
+t0 = time.perf_counter()
+h = O.build_hierarchy(lv, O.Options(nu={nu}))
+b = O.load_vector(lv, 1.0)
+setup = time.perf_counter() - t0
+u = np.zeros(lv.shape)
+per_cycle = sum(2 * {nu} * O.dofs(l) for l in h.levels[:-1])
+t0 = time.perf_counter(); n = 0
+while True:
+    u = O.vcycle(h, 0, u, b)
+    n += 1
+    el = time.perf_counter() - t0
+    if el > {budget_s} or n >= 200:
+        break
+print(json.dumps({{"cycles": n, "seconds": el, "dof_updates": n * per_cycle, "setup_s": setup}}))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=max(600, 20 * budget_s))
+    if out.returncode != 0:
+        return {"value": None, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+                "sample": f"failed: {out.stderr[-300:]}"}
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": r["dof_updates"] / r["seconds"], "unit": "DOF-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{r['cycles']} forward V-cycles (nu={nu}) of the NumPy FP64 oracle on "
+                      f"{workload}, {r['seconds']:.1f} s, single thread; hierarchy setup "
+                      f"{r['setup_s']:.1f} s excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="block_1024x4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--nu", type=int, default=None)
+    ap.add_argument("--fused", type=int, default=1)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs the STMG path on one GPU only; "
+              "--gpus above 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2505_10168_amd import binding as B
+    from paper_2505_10168_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    w = I.workload(args.workload)
+    nu = args.nu if args.nu is not None else WORKLOADS[args.workload]
+    precision = B.STMG_MIXED if args.precision == "mixed" else B.STMG_FP64
+    prob = B.Problem(w.n_el, w.n_t, w.length, w.t_final, k_ins=w.kappa_min)
+    rho = torch.from_numpy(w.rho).to(dev)
+    solver = B.Solver(prob, rho, nu=nu, precision=precision, fused=args.fused, time_kernels=1)
+    info = solver.info()
+    u = solver._new()
+    lam = solver._new()
+    grad = torch.empty(w.n_el, dtype=torch.float64, device=dev)
+
+    def step(record):
+        solver.set_design(rho)
+        _, st = solver.solve_forward(out=u)
+        rec = {"fwd": st}
+        if not args.no_adjoint:
+            _, sa = solver.solve_adjoint(out=lam)
+            rec["adj"] = sa
+            B.stmg_gradient(solver.handle, u, lam, grad)
+        rec["theta"] = solver.objective(u)
+        record.append(rec)
+
+    warm = []
+    for _ in range(args.warmup):
+        step(warm)
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    solves = [r[k] for r in recs for k in ("fwd", "adj") if k in r]
+    dof_updates = sum(s.dof_updates for s in solves)
+    lat = [s.solve_ms for s in solves]
+    kern_ms = sum(s.fine_kernel_ms for s in solves)
+    kern_bytes = sum(s.fine_kernel_bytes for s in solves)
+    launches = sum(s.fine_kernel_launches for s in solves)
+    achieved = kern_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    bad = [s.status for s in solves if s.status != 0]
+
+    out = {
+        "metric": METRIC,
+        "value": dof_updates / elapsed,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == B.STMG_FP64 else "f64+f32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload, "n_el": w.n_el, "n_t": w.n_t, "dofs": w.dofs,
+            "kappa_min": w.kappa_min, "nu": nu, "tol": 1e-10, "precision": args.precision,
+            "path": info["path"], "levels": info["n_levels"],
+            "step": "reassemble + forward solve" + ("" if args.no_adjoint else
+                                                  " + adjoint solve + gradient") + " + objective",
+        },
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                       "solves": len(lat)},
+        "solve": {
+            "fwd_cycles": recs[-1]["fwd"].cycles,
+            "adj_cycles": recs[-1]["adj"].cycles if "adj" in recs[-1] else None,
+            "fwd_rel_residual": recs[-1]["fwd"].rel_residual,
+            "adj_rel_residual": recs[-1]["adj"].rel_residual if "adj" in recs[-1] else None,
+            "theta": recs[-1]["theta"], "non_converged": len(bad),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_fused_fine (fine-level fused smoother passes)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": None,
+            "launches": launches,
+            "avg_launch_us": 1e3 * kern_ms / launches if launches else None,
+            "bytes_per_launch": kern_bytes / launches if launches else None,
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.workload, nu, args.cpu_budget)
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

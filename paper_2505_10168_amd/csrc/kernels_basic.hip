@@ -141,8 +141,10 @@ __global__ void k_stencil_coef(const double* __restrict__ k, const double* __res
         }
         wd = omega / di;
     }
-    double v[7] = {lo, di, up, mlo, mdi, mup, wd};
-    for (int a = 0; a < 7; ++a) {
+    const double kl = (i >= 1) ? k[i - 1] / h : 0.0;
+    const double kr = (i >= 1 && i < N) ? k[i] / h : 0.0;
+    double v[9] = {lo, di, up, mlo, mdi, mup, wd, kl, kr};
+    for (int a = 0; a < 9; ++a) {
         coef[a * S + i] = v[a];
         if (coef32) coef32[a * S + i] = (float)v[a];
     }
@@ -279,18 +281,18 @@ __global__ void k_apply(LevelView<T> L, int mode, const T* __restrict__ x,
             Jx = L.W * x0;
             scale = L.wW;
         } else {
-            T xm = zero_in ? T(0) : x[o - 1];
+            T xm = (zero_in || i == 1) ? T(0) : x[o - 1];
             T xp = (zero_in || i == L.N) ? T(0) : x[o + 1];
             bool coupled = TR ? (n < L.Nt) : (n >= 2);
             T ym = 0, y0 = 0, yp = 0;
             if (coupled && !zero_in) {
                 const int64_t q = TR ? o + P : o - P;
-                ym = x[q - 1];
+                ym = (i == 1) ? T(0) : x[q - 1];
                 y0 = x[q];
                 yp = (i == L.N) ? T(0) : x[q + 1];
             }
-            Jx = stencil_interior<T>(L.lo[i], L.di[i], L.up[i], L.mlo[i], L.mdi[i], L.mup[i], xm,
-                                     x0, xp, coupled, ym, y0, yp);
+            Jx = stencil_interior<T>(L.mlo[i], L.mdi[i], L.mup[i], L.kl[i], L.kr[i], xm, x0, xp,
+                                     coupled, ym, y0, yp);
             scale = L.wd[i];
         }
         if (mode == APPLY_J) {
@@ -451,6 +453,94 @@ void launch_coarsest(const LevelView<double>& L, const double* cp, const double*
     hipLaunchKernelGGL((k_coarsest<TV>), dim3(1), dim3(256), 0, s, L, cp, inv, b, u, trans, rhs);
 }
 
+// Columns of A^{-1} for a small coarsest level (N <= 64): thread j solves A x = e_j
+// with the Thomas factors.  ainv is row-major N x N (row i = node i+1).
+__global__ void k_dense_inverse(const double* __restrict__ coef, int N, const double* __restrict__ cp,
+                                const double* __restrict__ inv, double* __restrict__ ainv) {
+    const int j = threadIdx.x;
+    if (j >= N) return;
+    const double* lo = coef;
+    double d = 0.0;
+    for (int i = 1; i <= N; ++i) {
+        const double e = (i - 1 == j) ? 1.0 : 0.0;
+        d = (i == 1) ? e * inv[1] : (e - lo[i] * d) * inv[i];
+        ainv[(int64_t)(i - 1) * N + j] = d;
+    }
+    double x = 0.0;
+    for (int i = N; i >= 1; --i) {
+        x = (i == N) ? ainv[(int64_t)(i - 1) * N + j] : ainv[(int64_t)(i - 1) * N + j] - cp[i] * x;
+        ainv[(int64_t)(i - 1) * N + j] = x;
+    }
+}
+
+void launch_dense_inverse(const double* coef, int N, const double* cp, const double* inv,
+                          double* ainv, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(64), 0, s, coef, N, cp, inv, ainv);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Exact coarsest solve with a register-resident inverse (one wave, node i+1 in lane
+// i): each time step forms b_n + (C/dt) z_{n-1} (z_{n+1} for J^T) in parallel and
+// multiplies by A^{-1}, broadcasting the right-hand side lane by lane.
+template <typename TV, int NMAX>
+__global__ __launch_bounds__(64) void k_coarsest_dense(LevelView<double> L,
+                                                       const double* __restrict__ ainv,
+                                                       const TV* __restrict__ b,
+                                                       TV* __restrict__ u, int trans) {
+    const int lane = threadIdx.x;
+    const int N = L.N, Nt = L.Nt;
+    const int64_t P = L.P;
+    for (int i = lane; i <= N; i += 64) u[i] = (TV)((double)b[i] / L.W);
+    for (int n = 1 + lane; n <= Nt; n += 64) u[(int64_t)n * P] = (TV)((double)b[(int64_t)n * P] / L.W);
+    const int node = lane + 1;
+    const bool act = node <= N;
+    double a[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) a[j] = (act && j < N) ? ainv[(int64_t)lane * N + j] : 0.0;
+    const double mlo = act ? L.mlo[node] : 0.0;
+    const double mdi = act ? L.mdi[node] : 0.0;
+    const double mup = act ? L.mup[node] : 0.0;
+    double zprev = 0.0;
+    for (int s = 0; s < Nt; ++s) {
+        const int n = trans ? Nt - s : 1 + s;
+        const bool coupled = trans ? (n < Nt) : (n >= 2);
+        double rhs = act ? (double)b[(int64_t)n * P + node] : 0.0;
+        const double zl = __shfl_up(zprev, 1, 64);
+        const double zr = __shfl_down(zprev, 1, 64);
+        if (coupled) {
+            double w = mdi * zprev;
+            w = __builtin_fma(mlo, lane == 0 ? 0.0 : zl, w);
+            w = __builtin_fma(mup, zr, w);
+            rhs = rhs + w;
+        }
+        double z = 0.0;
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j)
+            if (j < N) z = __builtin_fma(a[j], readlane_f64(rhs, j), z);
+        if (act) u[(int64_t)n * P + node] = (TV)z;
+        zprev = act ? z : 0.0;
+    }
+}
+
+template <typename TV>
+void launch_coarsest_dense(const LevelView<double>& L, const double* ainv, const TV* b, TV* u,
+                           int trans, hipStream_t s) {
+    if (L.N <= 8)
+        hipLaunchKernelGGL((k_coarsest_dense<TV, 8>), dim3(1), dim3(64), 0, s, L, ainv, b, u, trans);
+    else if (L.N <= 16)
+        hipLaunchKernelGGL((k_coarsest_dense<TV, 16>), dim3(1), dim3(64), 0, s, L, ainv, b, u, trans);
+    else if (L.N <= 32)
+        hipLaunchKernelGGL((k_coarsest_dense<TV, 32>), dim3(1), dim3(64), 0, s, L, ainv, b, u, trans);
+    else
+        hipLaunchKernelGGL((k_coarsest_dense<TV, 64>), dim3(1), dim3(64), 0, s, L, ainv, b, u, trans);
+}
+
 // =====================================================================================
 // Deterministic reductions
 // =====================================================================================
@@ -537,13 +627,13 @@ __global__ void k_residual_sumsq(LevelView<T> L, const T* __restrict__ u, const 
                 T ym = 0, y0 = 0, yp = 0;
                 if (coupled) {
                     const int64_t q = TR ? o + P : o - P;
-                    ym = u[q - 1];
+                    ym = (i == 1) ? T(0) : u[q - 1];
                     y0 = u[q];
                     yp = (i == L.N) ? T(0) : u[q + 1];
                 }
-                Jx = stencil_interior<T>(L.lo[i], L.di[i], L.up[i], L.mlo[i], L.mdi[i], L.mup[i],
-                                         u[o - 1], u[o], (i == L.N) ? T(0) : u[o + 1], coupled, ym,
-                                         y0, yp);
+                Jx = stencil_interior<T>(L.mlo[i], L.mdi[i], L.mup[i], L.kl[i], L.kr[i],
+                                         (i == 1) ? T(0) : u[o - 1], u[o],
+                                         (i == L.N) ? T(0) : u[o + 1], coupled, ym, y0, yp);
             }
             double r = (double)(b[o] - Jx);
             acc = __builtin_fma(r, r, acc);
@@ -655,6 +745,10 @@ template void launch_coarsest<double>(const LevelView<double>&, const double*, c
                                       const double*, double*, int, hipStream_t);
 template void launch_coarsest<float>(const LevelView<double>&, const double*, const double*,
                                      const float*, float*, int, hipStream_t);
+template void launch_coarsest_dense<double>(const LevelView<double>&, const double*,
+                                            const double*, double*, int, hipStream_t);
+template void launch_coarsest_dense<float>(const LevelView<double>&, const double*,
+                                           const float*, float*, int, hipStream_t);
 template void launch_sumsq_partial<double>(const double*, int, int, int64_t, double*,
                                            hipStream_t);
 template void launch_sumsq_partial<float>(const float*, int, int, int64_t, double*, hipStream_t);

@@ -3,17 +3,19 @@
 // The BE-FE operator J (Section 2.2) couples time level n only to level n-1 (J^T:
 // only to n+1), so S damped-Jacobi steps (Section 3.1) can be evaluated in ONE pass
 // that streams through time: at row n, step k needs step k-1 at rows n and n-1,
-// both already available.  Every wavefront owns a strip of 256 contiguous columns
-// (4 per lane) and a segment of time levels; the S+1 sweep states of the previous
-// row stay in registers, neighbouring columns are exchanged between lanes, so each
-// DOF is read and written once per pass instead of once per sweep.
+// both already available.  Every wavefront owns a strip of 64*K contiguous columns
+// (K = 16 bytes / element size per lane: one dwordx4 access per vector and row) and
+// a segment of time levels; the S+1 sweep states of the previous row stay in
+// registers, neighbouring columns are exchanged between lanes, and the next row is
+// prefetched while the current one is computed.  Each DOF is read and written once
+// per pass instead of once per sweep.
 //
 // A pass optionally starts with the prolongation u += P z (the post-smoothing side
 // of Algorithm 1) and optionally ends with the residual r = b - J u followed by the
 // restriction R r (x or t, the pre-smoothing side) or by the squared residual norm
 // (termination test of Section 3.1).
 //
-// Redundant work: 4*HL halo columns per strip side (HL = ceil((S+2)/4) lanes) and
+// Redundant work: K*HL halo columns per strip side (HL = ceil((S+2)/K) lanes) and
 // S(+1) warm-up rows per time segment, both recomputed rather than exchanged.
 // The arithmetic of each DOF goes through stencil_interior/jacobi_update in the
 // same order as the reference kernels, so both paths give identical bits.
@@ -27,7 +29,9 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
-constexpr int kCols = 4;   // contiguous columns per lane
+constexpr int PF = 3;        // rows in flight per wave (register prefetch ring)
+constexpr int kXcds = 8;     // accelerator complex dies of an MI355X
+constexpr int kMaxFused = 6; // Jacobi steps one pass can fuse
 
 enum Tail { TAIL_NONE = 0, TAIL_RX = 1, TAIL_RT = 2, TAIL_NORM = 3 };
 
@@ -50,60 +54,78 @@ struct FusedArgs {
     int nwaves;
 };
 
-__device__ __forceinline__ double shfl_up1(double v) { return __shfl_up(v, 1, kWave); }
-__device__ __forceinline__ double shfl_dn1(double v) { return __shfl_down(v, 1, kWave); }
-__device__ __forceinline__ float shfl_up1(float v) { return __shfl_up(v, 1, kWave); }
-__device__ __forceinline__ float shfl_dn1(float v) { return __shfl_down(v, 1, kWave); }
+template <typename T> struct Lanes;
+template <> struct Lanes<double> { static constexpr int K = 2; };
+template <> struct Lanes<float> { static constexpr int K = 4; };
 
-__device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
-    const double2* q = reinterpret_cast<const double2*>(p);
-    double2 a = q[0], b = q[1];
-    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+// Neighbour exchange across the whole wave with DPP wave shifts (ALU latency, no LDS
+// round trip): shfl_up1 gives lane i the value of lane i-1, shfl_dn1 the value of
+// lane i+1; the edge lane keeps its own value.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp32(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
 }
-__device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)dpp32<CTRL>((int)(unsigned)b);
+    const unsigned hi = (unsigned)dpp32<CTRL>((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double shfl_up1(double v) { return dpp64<kDppWaveShr1>(v); }
+__device__ __forceinline__ double shfl_dn1(double v) { return dpp64<kDppWaveShl1>(v); }
+__device__ __forceinline__ float shfl_up1(float v) {
+    return __int_as_float(dpp32<kDppWaveShr1>(__float_as_int(v)));
+}
+__device__ __forceinline__ float shfl_dn1(float v) {
+    return __int_as_float(dpp32<kDppWaveShl1>(__float_as_int(v)));
+}
+
+// 16-byte row accesses of one lane.
+__device__ __forceinline__ void ld(const double* p, double (&v)[2]) {
+    double2 a = *reinterpret_cast<const double2*>(p);
+    v[0] = a.x; v[1] = a.y;
+}
+__device__ __forceinline__ void ld(const float* p, float (&v)[4]) {
     float4 a = *reinterpret_cast<const float4*>(p);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
-__device__ __forceinline__ void store4(double* p, const double (&v)[4]) {
-    double2* q = reinterpret_cast<double2*>(p);
-    q[0] = make_double2(v[0], v[1]);
-    q[1] = make_double2(v[2], v[3]);
+__device__ __forceinline__ void st(double* p, const double (&v)[2]) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
 }
-__device__ __forceinline__ void store4(float* p, const float (&v)[4]) {
+__device__ __forceinline__ void st(float* p, const float (&v)[4]) {
     *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
 }
-__device__ __forceinline__ void load2(const double* p, double& a, double& b) {
-    double2 v = *reinterpret_cast<const double2*>(p);
-    a = v.x; b = v.y;
+// coarse x-prolongation / x-restriction touch K/2 coarse values per lane
+__device__ __forceinline__ void ldh(const double* p, double (&v)[1]) { v[0] = p[0]; }
+__device__ __forceinline__ void ldh(const float* p, float (&v)[2]) {
+    float2 a = *reinterpret_cast<const float2*>(p);
+    v[0] = a.x; v[1] = a.y;
 }
-__device__ __forceinline__ void load2(const float* p, float& a, float& b) {
-    float2 v = *reinterpret_cast<const float2*>(p);
-    a = v.x; b = v.y;
-}
-__device__ __forceinline__ void store2(double* p, double a, double b) {
-    *reinterpret_cast<double2*>(p) = make_double2(a, b);
-}
-__device__ __forceinline__ void store2(float* p, float a, float b) {
-    *reinterpret_cast<float2*>(p) = make_float2(a, b);
+__device__ __forceinline__ void sth(double* p, const double (&v)[1]) { p[0] = v[0]; }
+__device__ __forceinline__ void sth(float* p, const float (&v)[2]) {
+    *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
 }
 
-// Per-lane stencil coefficients of its 4 columns.
-template <typename T>
+template <typename T, int K>
 struct LaneCoef {
-    T lo[4], di[4], up[4], mlo[4], mdi[4], mup[4], wd[4];
+    T mlo[K], mdi[K], mup[K], kl[K], kr[K], wd[K];
 };
 
-// One Jacobi step (or, with JAC = false, the residual) of the lane's 4 columns at
-// row n.  x: current state, xl/xr: left/right neighbour column values; p/pl/pr: the
-// same at the coupled row.  Invalid columns produce 0.
-template <typename T, bool JAC>
-__device__ __forceinline__ void row_step(const LevelView<T>& L, const LaneCoef<T>& C,
-                                         const bool (&valid)[4], bool dir_col0, bool dir_row,
-                                         bool coupled, const T (&x)[4], T xl, T xr,
-                                         const T (&p)[4], T pl, T pr, const T (&bb)[4],
-                                         T (&y)[4]) {
+// One Jacobi step (JAC) or the residual (!JAC) of the lane's K columns at one row.
+// x: state at this row, xl/xr: neighbour columns; p/pl/pr: the same at the coupled
+// row.  Invalid columns yield 0.
+template <typename T, int K, bool JAC>
+__device__ __forceinline__ void row_step(const LevelView<T>& L, const LaneCoef<T, K>& C,
+                                         const bool (&valid)[K], const bool (&col1)[K],
+                                         bool dir_col0, bool dir_row, bool coupled,
+                                         const T (&x)[K], T xl, T xr, const T (&p)[K], T pl,
+                                         T pr, const T (&bb)[K], T (&y)[K]) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < K; ++j) {
         if (!valid[j]) {
             y[j] = T(0);
             continue;
@@ -113,12 +135,16 @@ __device__ __forceinline__ void row_step(const LevelView<T>& L, const LaneCoef<T
             Jx = L.W * x[j];
             scale = L.wW;
         } else {
-            const T xm = (j > 0) ? x[j - 1] : xl;
-            const T xp = (j < 3) ? x[j + 1] : xr;
-            const T pm = (j > 0) ? p[j - 1] : pl;
-            const T pp = (j < 3) ? p[j + 1] : pr;
-            Jx = stencil_interior<T>(C.lo[j], C.di[j], C.up[j], C.mlo[j], C.mdi[j], C.mup[j], xm,
-                                     x[j], xp, coupled, pm, p[j], pp);
+            T xm = (j > 0) ? x[j - 1] : xl;
+            T pm = (j > 0) ? p[j - 1] : pl;
+            if (col1[j]) {
+                xm = T(0);
+                pm = T(0);
+            }
+            const T xp = (j < K - 1) ? x[j + 1] : xr;
+            const T pp = (j < K - 1) ? p[j + 1] : pr;
+            Jx = stencil_interior<T>(C.mlo[j], C.mdi[j], C.mup[j], C.kl[j], C.kr[j], xm, x[j], xp,
+                                     coupled, pm, p[j], pp);
             scale = C.wd[j];
         }
         const T r = bb[j] - Jx;
@@ -127,36 +153,46 @@ __device__ __forceinline__ void row_step(const LevelView<T>& L, const LaneCoef<T
 }
 
 template <typename T, int TR, int S, int TAIL>
-__global__ __launch_bounds__(256) void k_fused(LevelView<T> L, FusedArgs<T> a) {
+__device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArgs<T>& a) {
+    constexpr int K = Lanes<T>::K;
+    constexpr int KH = K / 2;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    // Workgroups are dealt to the 8 XCDs round robin; renumber them so that each XCD
+    // gets a contiguous range of strips and time segments, whose shared halo columns
+    // and warm-up rows then hit the same L2.
+    const int nb = gridDim.x, q = nb / kXcds, r = nb % kXcds;
+    const int xcd = blockIdx.x % kXcds, idx = blockIdx.x / kXcds;
+    const int lb = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+    const int wave = lb * kWavesPerBlock + (threadIdx.x >> 6);
     if (wave >= a.nwaves) return;
     const int HL = a.HL;
-    const int U = (kWave - 2 * HL) * kCols;
+    const int U = (kWave - 2 * HL) * K;
     const int wx = wave % a.xw;
     const int wt = wave / a.xw;
-    const int g = wx * U - kCols * HL + kCols * lane;   // first column of this lane
+    const int g = wx * U - K * HL + K * lane;   // first column of this lane
     const bool useful = (lane >= HL) && (lane < kWave - HL);
     const bool lane_in = (g >= 0) && (g <= L.N);
     const int N = L.N, Nt = L.Nt;
     const int64_t P = L.P;
 
-    bool valid[4];
+    bool valid[K], col1[K];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) valid[j] = lane_in && (g + j <= N);
+    for (int j = 0; j < K; ++j) {
+        valid[j] = lane_in && (g + j <= N);
+        col1[j] = (g + j == 1);
+    }
     const bool dir_col0 = (g == 0);
 
-    LaneCoef<T> C;
+    LaneCoef<T, K> C;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < K; ++j) {
         const int c = g + j;
         const bool v = valid[j];
-        C.lo[j] = v ? L.lo[c] : T(0);
-        C.di[j] = v ? L.di[c] : T(0);
-        C.up[j] = v ? L.up[c] : T(0);
         C.mlo[j] = v ? L.mlo[c] : T(0);
         C.mdi[j] = v ? L.mdi[c] : T(0);
         C.mup[j] = v ? L.mup[c] : T(0);
+        C.kl[j] = v ? L.kl[c] : T(0);
+        C.kr[j] = v ? L.kr[c] : T(0);
         C.wd[j] = v ? L.wd[c] : T(0);
     }
 
@@ -167,123 +203,182 @@ __global__ __launch_bounds__(256) void k_fused(LevelView<T> L, FusedArgs<T> a) {
     constexpr int WARM = S + (TAIL != TAIL_NONE ? 1 : 0);
     const int first = TR ? min(Nt, n1 - 1 + WARM) : max(0, n0 - WARM);
     const int count = TR ? (first - n0 + 1) : (n1 - first);
+    constexpr bool need_b = (S > 0 || TAIL != TAIL_NONE);
 
     // Sweep states of the previous streamed row: level k = 0..S.
-    T prev[S + 1][4];
+    T prev[S + 1][K];
     T prevl[S + 1], prevr[S + 1];
 #pragma unroll
     for (int k = 0; k <= S; ++k) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) prev[k][j] = T(0);
+        for (int j = 0; j < K; ++j) prev[k][j] = T(0);
         prevl[k] = T(0);
         prevr[k] = T(0);
     }
-    T r_pair[4] = {T(0), T(0), T(0), T(0)};   // t-restriction: residual of the partner row
-    double acc = 0.0;                         // norm tail
+    T r_pair[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) r_pair[j] = T(0);
+    double acc = 0.0;
 
-    for (int it = 0; it < count; ++it) {
-        const int n = TR ? first - it : first + it;
+    // Row buffers: rows are fetched PF steps ahead of use (a register ring that the
+    // unrolled inner loop indexes statically).
+    T ru[PF][K], rb[PF][K], rz[PF][K];
+    auto fetch = [&](int n, T (&fu)[K], T (&fb)[K], T (&fz)[K]) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            fu[j] = T(0);
+            fb[j] = T(0);
+            fz[j] = T(0);
+        }
+        if (!lane_in) return;
+        const int64_t ro = (int64_t)n * P + g;
+        if (!a.zero_in) ld(a.u + ro, fu);
+        if (need_b) ld(a.b + ro, fb);
+        if (a.head == 1) {
+            T zh[KH];
+            ldh(a.z + (int64_t)n * a.Pz + (g >> 1), zh);
+#pragma unroll
+            for (int j = 0; j < KH; ++j) fz[j] = zh[j];
+        } else if (a.head == 2) {
+            ld(a.z + (int64_t)(n >> 1) * a.Pz + g, fz);
+        }
+    };
+    auto row_of = [&](int it) { return TR ? first - it : first + it; };
+#pragma unroll
+    for (int d = 0; d < PF; ++d)
+        if (d < count) fetch(row_of(d), ru[d], rb[d], rz[d]);
+
+    for (int it0 = 0; it0 < count; it0 += PF) {
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+        const int it = it0 + d;
+        if (it >= count) break;
+        const int n = row_of(it);
+        T x[K], bb[K], zz[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            x[j] = ru[d][j];
+            bb[j] = rb[d][j];
+            zz[j] = rz[d][j];
+        }
+        if (it + PF < count) fetch(row_of(it + PF), ru[d], rb[d], rz[d]);
         const bool out_row = (n >= n0) && (n < n1);
         const bool dir_row = (n == 0);
         const bool coupled = TR ? (n < Nt) : (n >= 2);
-        const int64_t ro = (int64_t)n * P + g;
 
-        T x[4] = {T(0), T(0), T(0), T(0)};
-        T bb[4] = {T(0), T(0), T(0), T(0)};
-        if (lane_in) {
-            if (!a.zero_in) load4(a.u + ro, x);
-            if (S > 0 || TAIL != TAIL_NONE) load4(a.b + ro, bb);
-        }
         // Prolongation head: x += P z.
         if (a.head == 1) {
-            T z0 = T(0), z1 = T(0);
-            if (lane_in) load2(a.z + (int64_t)n * a.Pz + (g >> 1), z0, z1);
-            const T z2 = shfl_dn1(z0);
-            if (valid[0]) x[0] += z0;
-            if (valid[1]) x[1] = fmaT(T(0.5), z0 + z1, x[1]);
-            if (valid[2]) x[2] += z1;
-            if (valid[3]) x[3] = fmaT(T(0.5), z1 + z2, x[3]);
-        } else if (a.head == 2) {
-            if (lane_in) {
-                T zz[4];
-                load4(a.z + (int64_t)(n >> 1) * a.Pz + g, zz);
+            const T znext = shfl_dn1(zz[0]);   // first coarse value of the next lane
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (valid[j]) x[j] += zz[j];
+            for (int j = 0; j < K; ++j) {
+                if (!valid[j]) continue;
+                const T za = zz[j >> 1];
+                if ((j & 1) == 0) {
+                    x[j] += za;
+                } else {
+                    const T zb = ((j >> 1) + 1 < KH) ? zz[(j >> 1) + 1] : znext;
+                    x[j] = fmaT(T(0.5), za + zb, x[j]);
+                }
             }
+        } else if (a.head == 2) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (valid[j]) x[j] += zz[j];
         }
-        T xl = shfl_up1(x[3]);
+        T xl = shfl_up1(x[K - 1]);
         T xr = shfl_dn1(x[0]);
 
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-            T y[4];
-            row_step<T, true>(L, C, valid, dir_col0, dir_row, coupled, x, xl, xr, prev[k],
-                              prevl[k], prevr[k], bb, y);
+            T y[K];
+            row_step<T, K, true>(L, C, valid, col1, dir_col0, dir_row, coupled, x, xl, xr,
+                                 prev[k], prevl[k], prevr[k], bb, y);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) prev[k][j] = x[j];
+            for (int j = 0; j < K; ++j) {
+                prev[k][j] = x[j];
+                x[j] = y[j];
+            }
             prevl[k] = xl;
             prevr[k] = xr;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) x[j] = y[j];
-            xl = shfl_up1(x[3]);
+            xl = shfl_up1(x[K - 1]);
             xr = shfl_dn1(x[0]);
         }
 
-        if (out_row && useful && lane_in) store4(a.out + ro, x);
+        if (out_row && useful && lane_in) st(a.out + (int64_t)n * P + g, x);
 
         if constexpr (TAIL != TAIL_NONE) {
-            T r[4];
-            row_step<T, false>(L, C, valid, dir_col0, dir_row, coupled, x, xl, xr, prev[S],
-                               prevl[S], prevr[S], bb, r);
+            T r[K];
+            row_step<T, K, false>(L, C, valid, col1, dir_col0, dir_row, coupled, x, xl, xr,
+                                  prev[S], prevl[S], prevr[S], bb, r);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) prev[S][j] = x[j];
+            for (int j = 0; j < K; ++j) prev[S][j] = x[j];
             prevl[S] = xl;
             prevr[S] = xr;
             if constexpr (TAIL == TAIL_RX) {
-                const T rl = shfl_up1(r[3]);
+                // coarse node I = (g + j)/2 for even j: r_{2I} + 1/2 (r_{2I-1} + r_{2I+1})
+                const T rl = shfl_up1(r[K - 1]);
                 if (out_row && useful && lane_in) {
                     const int I0 = g >> 1;
-                    const T c0 = fmaT(T(0.5), rl + r[1], r[0]);
-                    const T c1 = fmaT(T(0.5), r[1] + r[3], r[2]);
+                    T c[KH];
+#pragma unroll
+                    for (int q = 0; q < KH; ++q) {
+                        const T left = (q == 0) ? rl : r[2 * q - 1];
+                        c[q] = fmaT(T(0.5), left + r[2 * q + 1], r[2 * q]);
+                    }
                     T* dst = a.bc + (int64_t)n * a.Pbc + I0;
-                    if (I0 + 1 <= a.Nc)
-                        store2(dst, c0, c1);
-                    else if (I0 <= a.Nc)
-                        dst[0] = c0;
+                    if (I0 + KH - 1 <= a.Nc) {
+                        sth(dst, c);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < KH; ++q)
+                            if (I0 + q <= a.Nc) dst[q] = c[q];
+                    }
                 }
             } else if constexpr (TAIL == TAIL_RT) {
                 if (out_row && useful && lane_in) {
-                    // pairs (2J, 2J+1) -> J; in the transposed stream 2J+1 comes first
-                    const bool second = TR ? ((n & 1) == 0) : ((n & 1) == 1);
-                    const bool lone = TR ? false : ((n & 1) == 0 && n == Nt);
-                    const bool lone_tr = TR ? (n == Nt && (n & 1) == 0) : false;
-                    if (second && !lone_tr) {
-                        T v[4];
+                    // pairs (2J, 2J+1) -> J; the transposed stream meets 2J+1 first
+                    const bool odd = (n & 1) != 0;
+                    T v[K];
+                    T* dst = a.bc + (int64_t)(n >> 1) * a.Pbc + g;
+                    if (!TR) {
+                        if (odd) {
 #pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            v[j] = T(0.5) * (TR ? (r[j] + r_pair[j]) : (r_pair[j] + r[j]));
-                        store4(a.bc + (int64_t)(n >> 1) * a.Pbc + g, v);
-                    } else if (lone || lone_tr) {
-                        T v[4];
+                            for (int j = 0; j < K; ++j) v[j] = T(0.5) * (r_pair[j] + r[j]);
+                            st(dst, v);
+                        } else if (n == Nt) {
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) v[j] = T(0.5) * r[j];
-                        store4(a.bc + (int64_t)(n >> 1) * a.Pbc + g, v);
+                            for (int j = 0; j < K; ++j) v[j] = T(0.5) * r[j];
+                            st(dst, v);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < K; ++j) r_pair[j] = r[j];
+                        }
                     } else {
+                        if (odd) {
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) r_pair[j] = r[j];
+                            for (int j = 0; j < K; ++j) r_pair[j] = r[j];
+                        } else if (n == Nt) {
+#pragma unroll
+                            for (int j = 0; j < K; ++j) v[j] = T(0.5) * r[j];
+                            st(dst, v);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < K; ++j) v[j] = T(0.5) * (r[j] + r_pair[j]);
+                            st(dst, v);
+                        }
                     }
                 }
             } else if constexpr (TAIL == TAIL_NORM) {
                 if (out_row && useful) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                    for (int j = 0; j < K; ++j) {
                         const double rv = (double)r[j];
                         acc = __builtin_fma(rv, rv, acc);
                     }
                 }
             }
         }
+    }
     }
 
     if constexpr (TAIL == TAIL_NORM) {
@@ -293,66 +388,96 @@ __global__ __launch_bounds__(256) void k_fused(LevelView<T> L, FusedArgs<T> a) {
     }
 }
 
+// Two entry points with the same body: the finest level gets its own symbol so that
+// profiles attribute the dominant passes separately from the coarse levels.
+template <typename T, int TR, int S, int TAIL>
+__global__ __launch_bounds__(256) void k_fused(LevelView<T> L, FusedArgs<T> a) {
+    fused_body<T, TR, S, TAIL>(L, a);
+}
+template <typename T, int TR, int S, int TAIL>
+__global__ __launch_bounds__(256) void k_fused_fine(LevelView<T> L, FusedArgs<T> a) {
+    fused_body<T, TR, S, TAIL>(L, a);
+}
+
 struct Geometry {
     int HL, U, xw, seg, nwaves;
 };
 
+template <typename T>
 Geometry geometry(int N, int Nt, int sweeps) {
+    constexpr int K = Lanes<T>::K;
     Geometry G;
-    G.HL = (sweeps + 2 + kCols - 1) / kCols;
-    if (G.HL < 1) G.HL = 1;
-    G.U = (kWave - 2 * G.HL) * kCols;
+    // Halo lanes: ceil((S+2)/K), rounded up so that the useful strip of every wave is
+    // a whole number of 128-byte lines; then no two waves write the same line.
+    constexpr int lanes_per_line = 128 / (K * (int)sizeof(T));
+    const int align = lanes_per_line / 2 > 0 ? lanes_per_line / 2 : 1;
+    G.HL = (sweeps + 2 + K - 1) / K;
+    G.HL = (G.HL + align - 1) / align * align;
+    G.U = (kWave - 2 * G.HL) * K;
     G.xw = (N + 1 + G.U - 1) / G.U;
-    const int rows = Nt + 1;
-    const int64_t target = 8192;
-    int64_t seg = ((int64_t)rows * G.xw + target - 1) / target;
-    const int64_t min_seg = 32;
+    const int64_t rows = Nt + 1;
+    // enough waves to keep every SIMD busy several times over
+    const int64_t target = 16384;
+    int64_t seg = (rows * G.xw + target - 1) / target;
+    const int64_t min_seg = 4;
     if (seg < min_seg) seg = min_seg;
-    if (seg > 512) seg = 512;
+    if (seg > 1024) seg = 1024;
     if (seg & 1) ++seg;
     G.seg = (int)seg;
-    G.nwaves = G.xw * ((rows + G.seg - 1) / G.seg);
+    G.nwaves = (int)(G.xw * ((rows + G.seg - 1) / G.seg));
     return G;
 }
 
 template <typename T, int TR, int S, int TAIL>
-void launch_one(const LevelView<T>& L, const FusedArgs<T>& a, hipStream_t s) {
+void launch_one(const LevelView<T>& L, const FusedArgs<T>& a, bool fine, hipStream_t s) {
     const int blocks = (a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL((k_fused<T, TR, S, TAIL>), dim3(blocks), dim3(kWave * kWavesPerBlock), 0,
-                       s, L, a);
+    if (fine)
+        hipLaunchKernelGGL((k_fused_fine<T, TR, S, TAIL>), dim3(blocks),
+                           dim3(kWave * kWavesPerBlock), 0, s, L, a);
+    else
+        hipLaunchKernelGGL((k_fused<T, TR, S, TAIL>), dim3(blocks), dim3(kWave * kWavesPerBlock),
+                           0, s, L, a);
 }
 
 template <typename T, int TR, int S>
-void dispatch_tail(int tail, const LevelView<T>& L, const FusedArgs<T>& a, hipStream_t s) {
+void dispatch_tail(int tail, const LevelView<T>& L, const FusedArgs<T>& a, bool fine,
+                   hipStream_t s) {
     switch (tail) {
-        case TAIL_NONE: launch_one<T, TR, S, TAIL_NONE>(L, a, s); break;
-        case TAIL_RX: launch_one<T, TR, S, TAIL_RX>(L, a, s); break;
-        case TAIL_RT: launch_one<T, TR, S, TAIL_RT>(L, a, s); break;
-        default: launch_one<T, TR, S, TAIL_NORM>(L, a, s); break;
+        case TAIL_NONE: launch_one<T, TR, S, TAIL_NONE>(L, a, fine, s); break;
+        case TAIL_RX: launch_one<T, TR, S, TAIL_RX>(L, a, fine, s); break;
+        case TAIL_RT: launch_one<T, TR, S, TAIL_RT>(L, a, fine, s); break;
+        default: launch_one<T, TR, S, TAIL_NORM>(L, a, fine, s); break;
     }
 }
 
 template <typename T, int TR>
-void dispatch_sweeps(int S, int tail, const LevelView<T>& L, const FusedArgs<T>& a,
+void dispatch_sweeps(int S, int tail, const LevelView<T>& L, const FusedArgs<T>& a, bool fine,
                      hipStream_t s) {
     switch (S) {
-        case 0: dispatch_tail<T, TR, 0>(tail, L, a, s); break;
-        case 1: dispatch_tail<T, TR, 1>(tail, L, a, s); break;
-        case 2: dispatch_tail<T, TR, 2>(tail, L, a, s); break;
-        case 3: dispatch_tail<T, TR, 3>(tail, L, a, s); break;
-        default: dispatch_tail<T, TR, 4>(tail, L, a, s); break;
+        case 0: dispatch_tail<T, TR, 0>(tail, L, a, fine, s); break;
+        case 1: dispatch_tail<T, TR, 1>(tail, L, a, fine, s); break;
+        case 2: dispatch_tail<T, TR, 2>(tail, L, a, fine, s); break;
+        case 3: dispatch_tail<T, TR, 3>(tail, L, a, fine, s); break;
+        case 4: dispatch_tail<T, TR, 4>(tail, L, a, fine, s); break;
+        case 5: dispatch_tail<T, TR, 5>(tail, L, a, fine, s); break;
+        default: dispatch_tail<T, TR, 6>(tail, L, a, fine, s); break;
     }
 }
 
 }  // namespace
 
-int fused_parts(int N, int Nt, int sweeps) { return geometry(N, Nt, sweeps).nwaves; }
+int fused_max_sweeps() { return kMaxFused; }
+
+int fused_parts(int N, int Nt, int sweeps) {
+    // the FP32 geometry (wider lanes) never needs more waves than the FP64 one
+    return geometry<double>(N, Nt, sweeps).nwaves;
+}
 
 template <typename T>
 int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T* b, T* out,
                  hipStream_t s) {
-    if (fp.sweeps < 0 || fp.sweeps > 4) return -1;
-    Geometry G = geometry(L.N, L.Nt, fp.sweeps);
+    if (fp.sweeps < 0 || fp.sweeps > kMaxFused) return -1;
+    Geometry G = geometry<T>(L.N, L.Nt, fp.sweeps);
     FusedArgs<T> a;
     a.u = u;
     a.b = b;
@@ -369,11 +494,12 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
     a.xw = G.xw;
     a.seg = G.seg;
     a.nwaves = G.nwaves;
-    const int tail = fp.tail == 'x' ? TAIL_RX : (fp.tail == 't' ? TAIL_RT : (fp.tail == 'n' ? TAIL_NORM : TAIL_NONE));
+    const int tail = fp.tail == 'x' ? TAIL_RX
+                     : (fp.tail == 't' ? TAIL_RT : (fp.tail == 'n' ? TAIL_NORM : TAIL_NONE));
     if (fp.trans)
-        dispatch_sweeps<T, 1>(fp.sweeps, tail, L, a, s);
+        dispatch_sweeps<T, 1>(fp.sweeps, tail, L, a, fp.fine != 0, s);
     else
-        dispatch_sweeps<T, 0>(fp.sweeps, tail, L, a, s);
+        dispatch_sweeps<T, 0>(fp.sweeps, tail, L, a, fp.fine != 0, s);
     return G.nwaves;
 }
 

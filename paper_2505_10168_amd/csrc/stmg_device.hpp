@@ -13,13 +13,14 @@
 namespace stmg {
 
 // Per-node stencil coefficients of one level (arrays of length N+1, node i):
-//   lo[i] = A_{i,i-1}, di[i] = A_{i,i}, up[i] = A_{i,i+1}  with A = C/dt + K
-//   mlo/mdi/mup          = the same entries of C/dt
+//   lo[i] = A_{i,i-1}, di[i] = A_{i,i}, up[i] = A_{i,i+1}   with A = C/dt + K
+//   mlo/mdi/mup[i]       = the same entries of C/dt
+//   kl[i] = k_{i-1}/h, kr[i] = k_i/h  (conductances of the elements left/right of node i)
 //   wd[i] = omega / A_{i,i}
-// Entries that couple to the Dirichlet node 0 (lo[1], mlo[1]) and entries beyond
-// the last node (up[N], mup[N]) are stored as 0, which removes the eliminated
-// columns of Appendix A.  Node 0 itself is a Dirichlet row handled separately
-// (J u = W u there, as on time level 0).
+// Entries that couple to the Dirichlet node 0 (lo[1], mlo[1]) and entries beyond the
+// last node (up[N], mup[N], kr[N]) are 0: this removes the eliminated columns of
+// Appendix A.  Node 0 itself is a Dirichlet row handled separately (J u = W u there,
+// as on time level 0).
 template <typename T>
 struct LevelView {
     int N;          // elements; nodes 0..N
@@ -32,6 +33,8 @@ struct LevelView {
     const T* mdi;
     const T* mup;
     const T* wd;
+    const T* kl;
+    const T* kr;
     T W;            // W_Diri of this level (Appendix A)
     T wW;           // omega / W_Diri
 };
@@ -39,22 +42,24 @@ struct LevelView {
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-// (J x) at an interior DOF (i >= 1, n >= 1):
-//   sum_j A_ij x_{j,n} - [coupled] sum_j (C/dt)_ij x_{j,m}
-// with m = n-1 for J (coupled iff n >= 2) and m = n+1 for J^T (coupled iff n < Nt).
+// (J x) at an interior DOF (i >= 1, n >= 1), evaluated in difference form
+//   sum_j (C/dt)_ij (x_{j,n} - x_{j,m}) + k_{i-1}/h (x_i - x_{i-1}) + k_i/h (x_i - x_{i+1})
+// which equals sum_j A_ij x_{j,n} - sum_j (C/dt)_ij x_{j,m} but keeps the large,
+// cancelling terms out of the rounding.  m = n-1 for J (coupled iff n >= 2) and
+// m = n+1 for J^T (coupled iff n < Nt); uncoupled rows use y = 0.  The caller passes
+// xm = ym = 0 at i = 1 (the column of node 0 is eliminated).
 template <typename T>
-__device__ __forceinline__ T stencil_interior(T lo, T di, T up, T mlo, T mdi, T mup,
+__device__ __forceinline__ T stencil_interior(T mlo, T mdi, T mup, T kl, T kr,
                                               T xm, T x0, T xp, bool coupled,
                                               T ym, T y0, T yp) {
-    T s = di * x0;
-    s = fmaT(lo, xm, s);
-    s = fmaT(up, xp, s);
-    if (coupled) {
-        T t = mdi * y0;
-        t = fmaT(mlo, ym, t);
-        t = fmaT(mup, yp, t);
-        s = s - t;
-    }
+    const T dm = coupled ? xm - ym : xm;
+    const T d0 = coupled ? x0 - y0 : x0;
+    const T dp = coupled ? xp - yp : xp;
+    T s = mdi * d0;
+    s = fmaT(mlo, dm, s);
+    s = fmaT(mup, dp, s);
+    s = fmaT(kl, x0 - xm, s);
+    s = fmaT(kr, x0 - xp, s);
     return s;
 }
 

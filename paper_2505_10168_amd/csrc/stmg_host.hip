@@ -38,6 +38,8 @@ int fail(int code, const std::string& msg) {
         if (rc_ < 0) return rc_;   \
     } while (0)
 
+constexpr int kCoefArrays = 9;   // lo, di, up, mlo, mdi, mup, wd, kl, kr
+
 int64_t pitch_for(int N) { return ((int64_t)N + 4 + 31) / 32 * 32; }
 int64_t dofs_of(int N, int Nt) { return (int64_t)(N + 1) * (Nt + 1); }
 
@@ -50,9 +52,10 @@ struct Level {
     double* k = nullptr;
     double* c = nullptr;
     double* chi = nullptr;
-    double* coef = nullptr;  // 7 (N+1)
+    double* coef = nullptr;  // kCoefArrays (N+1)
     float* coef32 = nullptr;
     double* thomas = nullptr;  // coarsest: cp, inv, rhs scratch (3 (N+1))
+    double* ainv = nullptr;    // coarsest with N <= kDenseCoarsestMax: A^{-1}, N x N
     double* u = nullptr;
     double* b = nullptr;
     double* t = nullptr;
@@ -84,6 +87,7 @@ LevelView<double> view<double>(const Level& l, double omega) {
     v.lo = l.coef; v.di = l.coef + S; v.up = l.coef + 2 * S;
     v.mlo = l.coef + 3 * S; v.mdi = l.coef + 4 * S; v.mup = l.coef + 5 * S;
     v.wd = l.coef + 6 * S;
+    v.kl = l.coef + 7 * S; v.kr = l.coef + 8 * S;
     v.W = l.W;
     v.wW = omega / l.W;
     return v;
@@ -97,6 +101,7 @@ LevelView<float> view<float>(const Level& l, double omega) {
     v.lo = l.coef32; v.di = l.coef32 + S; v.up = l.coef32 + 2 * S;
     v.mlo = l.coef32 + 3 * S; v.mdi = l.coef32 + 4 * S; v.mup = l.coef32 + 5 * S;
     v.wd = l.coef32 + 6 * S;
+    v.kl = l.coef32 + 7 * S; v.kr = l.coef32 + 8 * S;
     v.W = (float)l.W;
     v.wW = (float)(omega / l.W);
     return v;
@@ -197,9 +202,9 @@ bool can_t(int Nt) { return Nt % 2 == 0 && Nt >= 2; }
 // Bytes a level of (N, Nt) holds for the given precision and position.
 size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest) {
     const int64_t P = pitch_for(N), E = (int64_t)(Nt + 1) * P;
-    size_t b = 3 * (size_t)N * 8 + 7 * (size_t)(N + 1) * 8;
-    if (precision == STMG_MIXED) b += 7 * (size_t)(N + 1) * 4;
-    if (coarsest) b += 3 * (size_t)(N + 1) * 8;
+    size_t b = 3 * (size_t)N * 8 + kCoefArrays * (size_t)(N + 1) * 8;
+    if (precision == STMG_MIXED) b += kCoefArrays * (size_t)(N + 1) * 4;
+    if (coarsest) b += 3 * (size_t)(N + 1) * 8 + (N <= kDenseCoarsestMax ? (size_t)N * N * 8 : 0);
     if (precision == STMG_FP64 || fine) b += 3 * (size_t)E * 8;
     if (precision == STMG_MIXED) b += 3 * (size_t)E * 4;
     return b;
@@ -342,7 +347,11 @@ int coarse_coefficients(stmg_ctx* h, const Level& f, char dir, Level& c) {
 
 int finish_level(stmg_ctx* h, Level& l, bool coarsest) {
     launch_stencil_coef(l.k, l.c, l.N, l.h, l.tau, h->o.omega, l.coef, l.coef32, h->s);
-    if (coarsest) launch_thomas_factors(l.coef, l.N, l.thomas, l.thomas + (l.N + 1), h->s);
+    if (coarsest) {
+        launch_thomas_factors(l.coef, l.N, l.thomas, l.thomas + (l.N + 1), h->s);
+        if (l.ainv)
+            launch_dense_inverse(l.coef, l.N, l.thomas, l.thomas + (l.N + 1), l.ainv, h->s);
+    }
     HIPCHK(hipGetLastError());
     return 0;
 }
@@ -390,9 +399,10 @@ int build(stmg_ctx* h, const double* d_q) {
         Level& l = h->L[i];
         // k, c, chi already allocated: allocate the rest
         const bool fine = i == 0, last = i + 1 == nl;
-        CHK(h->alloc(&l.coef, 7 * (int64_t)(l.N + 1)));
-        if (h->o.precision == STMG_MIXED) CHK(h->alloc(&l.coef32, 7 * (int64_t)(l.N + 1)));
+        CHK(h->alloc(&l.coef, kCoefArrays * (int64_t)(l.N + 1)));
+        if (h->o.precision == STMG_MIXED) CHK(h->alloc(&l.coef32, kCoefArrays * (int64_t)(l.N + 1)));
         if (last) CHK(h->alloc(&l.thomas, 3 * (int64_t)(l.N + 1)));
+        if (last && l.N <= kDenseCoarsestMax) CHK(h->alloc(&l.ainv, (int64_t)l.N * l.N));
         if (h->o.precision == STMG_FP64 || fine) {
             CHK(h->alloc(&l.u, l.elems()));
             CHK(h->alloc(&l.b, l.elems()));
@@ -411,7 +421,7 @@ int build(stmg_ctx* h, const double* d_q) {
     HIPCHK(hipGetLastError());
     // partial-sum buffer: largest fused pass on the fine level, reductions, gradient
     int64_t need = 1024;
-    for (int S = 0; S <= 4; ++S) need = std::max<int64_t>(need, fused_parts(fl.N, fl.Nt, S));
+    for (int S = 0; S <= fused_max_sweeps(); ++S) need = std::max<int64_t>(need, fused_parts(fl.N, fl.Nt, S));
     need = std::max<int64_t>(need, (int64_t)gradient_chunks(fl.Nt) * fl.N);
     CHK(h->alloc(&h->parts, need));
     h->nparts = need;
@@ -448,9 +458,10 @@ void timer_end(stmg_ctx* h, bool on, double bytes) {
     ++T.used;
 }
 
-// Sweep chunk sizes for nu steps: ceil(nu/4) fused passes of near-equal size.
+// Sweep chunk sizes for nu steps: the fewest fused passes, of near-equal size.
 std::vector<int> chunks_of(int nu) {
-    const int n = nu <= 4 ? 1 : (nu + 3) / 4;
+    const int m = fused_max_sweeps();
+    const int n = nu <= m ? 1 : (nu + m - 1) / m;
     std::vector<int> c;
     for (int k = 0; k < n; ++k) c.push_back(nu / n + (k < nu % n ? 1 : 0));
     return c;
@@ -479,6 +490,7 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
             fp.Pbc = cl.P;
             fp.Nc = cl.N;
             fp.Ntc = cl.Nt;
+            fp.fine = l == 0;
             timer_begin(h, timed);
             launch_fused<T>(V, fp, u, b, t, h->s);
             timer_end(h, timed, level_pass_bytes(lv, sizeof(T), !zero) + (lastc ? (double)cl.dofs() * sizeof(T) : 0.0));
@@ -522,6 +534,7 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
             const bool lastc = k + 1 == ch.size();
             fp.tail = (lastc && norm) ? 'n' : 0;
             fp.parts = h->parts;
+            fp.fine = l == 0;
             timer_begin(h, timed);
             int nw = launch_fused<T>(V, fp, u, b, t, h->s);
             timer_end(h, timed, level_pass_bytes(lv, sizeof(T), true) + (k == 0 ? (double)cl.dofs() * sizeof(T) : 0.0));
@@ -547,7 +560,10 @@ template <typename T>
 int coarsest_solve(stmg_ctx* h, int l, int trans) {
     Level& lv = h->L[l];
     const auto V = view<double>(lv, h->o.omega);
-    launch_coarsest<T>(V, lv.thomas, lv.thomas + (lv.N + 1), B<T>(lv), U<T>(lv), trans, h->s);
+    if (lv.ainv)
+        launch_coarsest_dense<T>(V, lv.ainv, B<T>(lv), U<T>(lv), trans, h->s);
+    else
+        launch_coarsest<T>(V, lv.thomas, lv.thomas + (lv.N + 1), B<T>(lv), U<T>(lv), trans, h->s);
     HIPCHK(hipGetLastError());
     return 0;
 }

@@ -22,7 +22,7 @@ void launch_coarsen_x(const double* k, const double* c, const double* chi, int n
                       double* chic, hipStream_t s);
 // out[0] = min_e k_e/c_e, out[1] = max_e k_e/c_e, out[2] = max_e c_e, out[3] = max_e k_e
 void launch_level_stats(const double* k, const double* c, int n, double* out, hipStream_t s);
-// coef: 7 arrays of N+1 doubles (lo, di, up, mlo, mdi, mup, wd); coef32 optional FP32 copy
+// coef: 9 arrays of N+1 doubles (lo, di, up, mlo, mdi, mup, wd, kl, kr); coef32: FP32 copy
 void launch_stencil_coef(const double* k, const double* c, int N, double h, double tau,
                          double omega, double* coef, float* coef32, hipStream_t s);
 void launch_thomas_factors(const double* coef, int N, double* cp, double* inv, hipStream_t s);
@@ -56,6 +56,14 @@ template <typename TV>
 void launch_coarsest(const LevelView<double>& L, const double* cp, const double* inv,
                      const TV* b, TV* u, int trans, hipStream_t s);
 
+// Coarsest levels with N <= kDenseCoarsestMax: A^{-1} built once, applied per step.
+constexpr int kDenseCoarsestMax = 64;
+void launch_dense_inverse(const double* coef, int N, const double* cp, const double* inv,
+                          double* ainv, hipStream_t s);
+template <typename TV>
+void launch_coarsest_dense(const LevelView<double>& L, const double* ainv, const TV* b, TV* u,
+                           int trans, hipStream_t s);
+
 // ---- reductions (deterministic: fixed partition, fixed tree) ------------------------
 int reduce_parts(int rows);
 template <typename T>
@@ -82,7 +90,7 @@ void launch_gradient_final(const double* parts, int N, int chunks, double* grad,
 // Pass descriptor of one fused streaming launch on a level.
 struct FusedPass {
     int trans;          // 0: J, 1: J^T (streams backwards in time)
-    int sweeps;         // Jacobi steps fused in this pass (0..4)
+    int sweeps;         // Jacobi steps fused in this pass (0..fused_max_sweeps())
     int zero_in;        // input u is identically zero (not read)
     char prolong;       // 0, 'x' or 't': add P z to the input first
     const void* z;      // coarse correction (type T), pitch Pz
@@ -93,10 +101,12 @@ struct FusedPass {
     void* bc;           // restricted residual output (type T), pitch Pbc
     int64_t Pbc;
     double* parts;      // norm partials ('n')
+    int fine;           // finest level: launched under its own kernel symbol
 };
 template <typename T>
 int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T* b, T* out,
                  hipStream_t s);
 int fused_parts(int N, int Nt, int sweeps);
+int fused_max_sweeps();
 
 }  // namespace stmg
