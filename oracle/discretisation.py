@@ -23,7 +23,7 @@ from scipy.linalg import solve_banded
 __all__ = [
     "Material", "Level", "simp", "simp_derivative", "make_fine_level",
     "mass_matrix_diagonals", "stiffness_matrix_diagonals", "w_diri",
-    "tridiag_apply", "dirichlet_mask", "apply_J", "diag_J", "load_vector",
+    "tridiag_apply", "stiffness_apply", "dirichlet_mask", "apply_J", "diag_J", "load_vector",
     "dense_J", "direct_solve", "relative_residual", "dofs",
 ]
 
@@ -158,26 +158,37 @@ def dirichlet_mask(level: Level) -> np.ndarray:
     return b
 
 
+def stiffness_apply(level: Level, x: np.ndarray) -> np.ndarray:
+    """K x assembled element by element: element e adds the flux (k_e / h)(x_e - x_{e+1})
+    to node e and subtracts it from node e+1 (linear elements, Section 2.2)."""
+    flux = (level.k / level.h) * (x[..., :-1] - x[..., 1:])
+    y = np.zeros_like(x)
+    y[..., :-1] += flux
+    y[..., 1:] -= flux
+    return y
+
+
 def apply_J(level: Level, u: np.ndarray, transpose: bool = False) -> np.ndarray:
     """y = J u (or J^T u) for J = B J_Neu B + W_Diri (I - B)  (Appendix A).
 
-    J_Neu is the all-at-once BE-FE matrix of Section 2.2: block row n >= 1 is
-    [-C/dt , C/dt + K] on time levels (n-1, n).  Its block row 0 is irrelevant since
-    B removes it.  J_Neu^T has blocks (C/dt + K) on the diagonal and -C/dt on
-    (n, n+1).
+    J_Neu is the all-at-once BE-FE matrix of Section 2.2: time level n >= 1 carries the
+    backward-Euler step C (T_n - T_{n-1}) / dt + K T_n; its block row 0 is irrelevant
+    since B removes it.  J_Neu^T carries C (T_n - T_{n+1}) / dt + K T_n, with no
+    T_{n+1} on the last level.  The step is evaluated in this difference form, as the
+    paper writes it, with K applied element by element.
     """
     mm, mo = mass_matrix_diagonals(level)
-    km, ko = stiffness_matrix_diagonals(level)
     tau = level.tau
     B = dirichlet_mask(level)
     ub = B * u
     y = np.zeros(level.shape)
     if not transpose:
-        y[1:] = tridiag_apply(mm / tau + km, mo / tau + ko, ub[1:]) \
-            - tridiag_apply(mm / tau, mo / tau, ub[:-1])
+        d = ub[1:] - ub[:-1]
+        y[1:] = tridiag_apply(mm / tau, mo / tau, d) + stiffness_apply(level, ub[1:])
     else:
-        y[:] = tridiag_apply(mm / tau + km, mo / tau + ko, ub)
-        y[:-1] -= tridiag_apply(mm / tau, mo / tau, ub[1:])
+        d = ub.copy()
+        d[:-1] -= ub[1:]
+        y[:] = tridiag_apply(mm / tau, mo / tau, d) + stiffness_apply(level, ub)
     return B * y + level.W * (1.0 - B) * u
 
 
