@@ -21,6 +21,8 @@
 // same order as the reference kernels, so both paths give identical bits.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "stmg_launch.hpp"
 
 namespace stmg {
@@ -33,7 +35,7 @@ constexpr int PF = 3;        // rows in flight per wave (register prefetch ring)
 constexpr int kXcds = 8;     // accelerator complex dies of an MI355X
 constexpr int kMaxFused = 6; // Jacobi steps one pass can fuse
 
-enum Tail { TAIL_NONE = 0, TAIL_RX = 1, TAIL_RT = 2, TAIL_NORM = 3 };
+enum Tail { TAIL_NONE = 0, TAIL_RX = 1, TAIL_RT = 2, TAIL_NORM = 3, TAIL_DEFECT = 4 };
 
 template <typename T>
 struct FusedArgs {
@@ -46,8 +48,12 @@ struct FusedArgs {
     int64_t Pbc;
     double* parts;
     int Nc;
-    int head;      // 0, 1 = prolong x, 2 = prolong t
+    int head;      // 0, 1 = prolong x, 2 = prolong t, 3 = defect correction u += s e
     int zero_in;
+    const float* e32;    // head 3: FP32 correction, same pitch as u
+    double s_old;        // head 3: scale of the correction
+    float* f32;          // TAIL_DEFECT: FP32 right-hand side r / s_new
+    double inv_s_new;
     int HL;        // halo lanes per side
     int xw;        // strips along x
     int seg;       // time levels per segment
@@ -241,6 +247,12 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
             for (int j = 0; j < KH; ++j) fz[j] = zh[j];
         } else if (a.head == 2) {
             ld(a.z + (int64_t)(n >> 1) * a.Pz + g, fz);
+        } else if constexpr (std::is_same<T, double>::value) {
+            if (a.head == 3) {
+                const float2 e = *reinterpret_cast<const float2*>(a.e32 + ro);
+                fz[0] = (T)e.x;
+                fz[1] = (T)e.y;
+            }
         }
     };
     auto row_of = [&](int it) { return TR ? first - it : first + it; };
@@ -284,6 +296,10 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
 #pragma unroll
             for (int j = 0; j < K; ++j)
                 if (valid[j]) x[j] += zz[j];
+        } else if (a.head == 3) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (valid[j]) x[j] = fmaT((T)a.s_old, zz[j], x[j]);
         }
         T xl = shfl_up1(x[K - 1]);
         T xr = shfl_dn1(x[0]);
@@ -368,7 +384,7 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
                         }
                     }
                 }
-            } else if constexpr (TAIL == TAIL_NORM) {
+            } else if constexpr (TAIL == TAIL_NORM || TAIL == TAIL_DEFECT) {
                 if (out_row && useful) {
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
@@ -376,12 +392,19 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
                         acc = __builtin_fma(rv, rv, acc);
                     }
                 }
+                if constexpr (TAIL == TAIL_DEFECT && std::is_same<T, double>::value) {
+                    if (out_row && useful && lane_in) {
+                        const float2 f = make_float2((float)(r[0] * a.inv_s_new),
+                                                     (float)(r[1] * a.inv_s_new));
+                        *reinterpret_cast<float2*>(a.f32 + (int64_t)n * P + g) = f;
+                    }
+                }
             }
         }
     }
     }
 
-    if constexpr (TAIL == TAIL_NORM) {
+    if constexpr (TAIL == TAIL_NORM || TAIL == TAIL_DEFECT) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
         if (lane == 0) a.parts[wave] = acc;
@@ -488,14 +511,31 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
     a.Pbc = fp.Pbc;
     a.parts = fp.parts;
     a.Nc = fp.Nc;
-    a.head = fp.prolong == 'x' ? 1 : (fp.prolong == 't' ? 2 : 0);
+    a.head = fp.prolong == 'x' ? 1 : (fp.prolong == 't' ? 2 : (fp.prolong == 'c' ? 3 : 0));
     a.zero_in = fp.zero_in;
+    a.e32 = fp.e32;
+    a.s_old = fp.s_old;
+    a.f32 = fp.f32;
+    a.inv_s_new = fp.inv_s_new;
     a.HL = G.HL;
     a.xw = G.xw;
     a.seg = G.seg;
     a.nwaves = G.nwaves;
     const int tail = fp.tail == 'x' ? TAIL_RX
                      : (fp.tail == 't' ? TAIL_RT : (fp.tail == 'n' ? TAIL_NORM : TAIL_NONE));
+    if (fp.tail == 'c' || fp.prolong == 'c') {
+        // defect correction (FP64 only): u += s_old e; r = b - J u; f = r / s_new; norm
+        if constexpr (std::is_same<T, double>::value) {
+            if (fp.sweeps != 0 || fp.tail != 'c' || fp.prolong != 'c') return -1;
+            if (fp.trans)
+                launch_one<T, 1, 0, TAIL_DEFECT>(L, a, fp.fine != 0, s);
+            else
+                launch_one<T, 0, 0, TAIL_DEFECT>(L, a, fp.fine != 0, s);
+            return G.nwaves;
+        } else {
+            return -1;
+        }
+    }
     if (fp.trans)
         dispatch_sweeps<T, 1>(fp.sweeps, tail, L, a, fp.fine != 0, s);
     else

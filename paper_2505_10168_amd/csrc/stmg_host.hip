@@ -659,7 +659,7 @@ int solve_fp64(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
     Level& f = h->L[0];
     double nb;
     CHK(norm64(h, f.b, f, &nb));
-    if (!(nb > 0)) return fail(STMG_EINVAL, "right-hand side is zero");
+    if (!(nb > 0) || !std::isfinite(nb)) return fail(STMG_EINVAL, "right-hand side is zero or not finite");
     double r;
     CHK(residual_norm64(h, trans, &r));
     r /= nb;
@@ -694,36 +694,66 @@ int solve_fp64(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
 }
 
 // Mixed precision: FP64 defect correction around FP32 V-cycles.  Each outer step
-// forms r = b - J u in FP64, scales it by s (RMS of the previous residual) into the
-// FP32 right-hand side, runs one FP32 V-cycle from zero (FP64 coarsest solve) and
-// applies u += s e in FP64.
-int solve_mixed(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
+// applies u += s_e e (FP64), forms r = b - J u in FP64, writes the FP32 right-hand
+// side f = r / s_f of the next inner cycle (s_f = RMS of the previous residual, so
+// f stays O(1) in FP32 range) and runs one FP32 V-cycle J e = f from e = 0 (FP32
+// smoothers and transfers, FP64 coarsest solve).  Fused path: the update, the
+// residual, the FP32 rounding and the norm partials are one streaming pass.
+int defect_step(stmg_ctx* h, int trans, double s_e, double s_f, double* norm) {
     Level& f = h->L[0];
     const auto V64 = view<double>(f, h->o.omega);
+    const double inv = 1.0 / s_f;
+    if (h->o.fused) {
+        FusedPass fp{};
+        fp.trans = trans;
+        fp.sweeps = 0;
+        fp.prolong = 'c';
+        fp.tail = 'c';
+        fp.e32 = f.u32;
+        fp.s_old = s_e;
+        fp.f32 = f.b32;
+        fp.inv_s_new = inv;
+        fp.parts = h->parts;
+        fp.fine = 1;
+        const bool timed = h->o.time_kernels != 0;
+        timer_begin(h, timed);
+        const int nw = launch_fused<double>(V64, fp, f.u, f.b, f.t, h->s);
+        // u, e, b read; u, f written
+        timer_end(h, timed, (double)f.dofs() * (8 + 4 + 8 + 8 + 4));
+        if (nw < 0) return fail(STMG_EINVAL, "defect-correction pass rejected");
+        std::swap(f.u, f.t);
+        HIPCHK(hipGetLastError());
+        return finish_norm(h, nw, norm);
+    }
+    if (s_e != 0.0) launch_axpy2d<float>(f.u32, f.P, f.u, f.P, f.Nt + 1, f.N + 1, s_e, h->s);
+    launch_apply<double>(V64, trans, APPLY_RESIDUAL, f.u, f.b, f.t, false, h->s);
+    launch_copy2d<double, float>(f.t, f.P, f.b32, f.P, f.Nt + 1, f.N + 1, inv, h->s);
+    HIPCHK(hipGetLastError());
+    return norm64(h, f.t, f, norm);
+}
+
+int solve_mixed(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
+    Level& f = h->L[0];
     double nb;
     CHK(norm64(h, f.b, f, &nb));
-    if (!(nb > 0)) return fail(STMG_EINVAL, "right-hand side is zero");
-    const double rms_den = std::sqrt((double)f.dofs());
-    launch_apply<double>(V64, trans, APPLY_RESIDUAL, f.u, f.b, f.t, false, h->s);
-    double r;
-    CHK(norm64(h, f.t, f, &r));
-    r /= nb;
+    if (!(nb > 0) || !std::isfinite(nb)) return fail(STMG_EINVAL, "right-hand side is zero or not finite");
+    const double sq = std::sqrt((double)f.dofs());
+    double s_f = nb / sq;   // scale of the right-hand side the next step writes
+    double rn;
+    CHK(defect_step(h, trans, 0.0, s_f, &rn));
+    double r = rn / nb;
     if (st) st->history[0] = r;
     const double r0 = r;
+    const bool timed = h->o.time_kernels != 0;
     int cyc = 0, code = STMG_NOT_CONVERGED;
     bool stop = false;
-    double scale = r * nb / rms_den;
     for (cyc = 1; cyc <= h->o.max_cycles; ++cyc) {
-        if (!(scale > 0)) scale = 1.0;
-        launch_copy2d<double, float>(f.t, f.P, f.b32, f.P, f.Nt + 1, f.N + 1, 1.0 / scale, h->s);
         CHK(vcycle<float>(h, 0, trans, true, false));
-        launch_axpy2d<float>(f.u32, f.P, f.u, f.P, f.Nt + 1, f.N + 1, scale, h->s);
-        launch_apply<double>(V64, trans, APPLY_RESIDUAL, f.u, f.b, f.t, false, h->s);
-        HIPCHK(hipGetLastError());
-        double rn;
-        CHK(norm64(h, f.t, f, &rn));
+        const double s_e = s_f;
+        s_f = rn > 0 ? rn / sq : 1.0;
+        CHK(defect_step(h, trans, s_e, s_f, &rn));
         r = rn / nb;
-        scale = rn / rms_den;
+        if (timed) collect_timer(h, st);
         if (st) st->history[cyc] = r;
         code = classify(h->o, r, &stop);
         if (stop) break;

@@ -92,16 +92,21 @@ struct FusedPass {
     int trans;          // 0: J, 1: J^T (streams backwards in time)
     int sweeps;         // Jacobi steps fused in this pass (0..fused_max_sweeps())
     int zero_in;        // input u is identically zero (not read)
-    char prolong;       // 0, 'x' or 't': add P z to the input first
+    char prolong;       // 0, 'x' or 't': add P z to the input first; 'c': u += s_old e32
     const void* z;      // coarse correction (type T), pitch Pz
     int64_t Pz;
     int Nc;             // coarse elements (prolong/restrict)
     int Ntc;            // coarse steps
-    char tail;          // 0: none, 'x'/'t': residual + restriction, 'n': residual norm
+    char tail;          // 0: none, 'x'/'t': residual + restriction, 'n': residual norm,
+                        // 'c': residual norm and f32 = r * inv_s_new (with prolong 'c')
     void* bc;           // restricted residual output (type T), pitch Pbc
     int64_t Pbc;
     double* parts;      // norm partials ('n')
     int fine;           // finest level: launched under its own kernel symbol
+    const float* e32;   // 'c': FP32 correction
+    double s_old;       // 'c': its scale
+    float* f32;         // 'c': FP32 scaled residual output
+    double inv_s_new;
 };
 template <typename T>
 int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T* b, T* out,

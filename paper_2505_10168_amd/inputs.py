@@ -22,11 +22,14 @@ import numpy as np
 # Design fields
 # --------------------------------------------------------------------------------------
 
-def block_density(n_el: int, block: int, seed: int, p: float = 0.5) -> np.ndarray:
+def block_density(n_el: int, block: int, seed: int, p: float = 0.5,
+                  first_on: bool = False) -> np.ndarray:
     """Piecewise-constant 0/1 density in blocks of ``block`` elements.
 
     Each block is 1 with probability ``p``.  A draw with every block equal is redrawn
-    (the field is meant to be high contrast), deterministically from the same seed.
+    (the field is meant to be high contrast), deterministically from the same seed;
+    with ``first_on`` a draw whose first block (next to the cold end x = 0) is
+    insulating is redrawn too.
     """
     if n_el % block != 0:
         raise ValueError("n_el must be a multiple of the block length")
@@ -34,7 +37,7 @@ def block_density(n_el: int, block: int, seed: int, p: float = 0.5) -> np.ndarra
     nb = n_el // block
     while True:
         bits = (rng.random(nb) < p).astype(np.float64)
-        if nb == 1 or (bits.min() != bits.max()):
+        if (nb == 1 or bits.min() != bits.max()) and (not first_on or bits[0] == 1.0):
             break
     return np.repeat(bits, block)
 
@@ -139,7 +142,9 @@ def workload(name: str) -> Workload:
     if name == "boxfilt_8192x65536":
         return Workload(name, 8192, 65536, 1e-4, box_filtered_uniform_density(8192, 9, seed=3))
     if name == "block_2048x8192":
-        return Workload(name, 2048, 8192, 1e-3, block_density(2048, 16, seed=4))
+        # the gradient workload: its first block conducts, so the rod is thermally
+        # connected to the cold end and the design sensitivities are measurable
+        return Workload(name, 2048, 8192, 1e-3, block_density(2048, 16, seed=4, first_on=True))
     raise KeyError(name)
 
 

@@ -1,0 +1,235 @@
+"""GPU tests of the solver forms: mixed precision, objective and gradient (against
+the oracle and against finite differences), design updates, failure statuses,
+determinism and full-size parity of the configurations."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from tests.helpers import I, O, oracle_setup, rel, to_dev, to_np
+from tests.test_gpu_parity import CASES, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("transpose", [0, 1])
+@pytest.mark.parametrize("fused", [1, 0])
+def test_mixed_precision_tracks_fp64(name, transpose, fused, cuda):
+    """FP32 smoothers and transfers inside an FP64 defect correction: the same cycle
+    count and residual history as FP64 (to FP32 accuracy per cycle), the 1e-10 FP64
+    residual when FP64 reaches it, and the solution error against the oracle's direct
+    solve stated."""
+    from paper_2505_10168_amd import binding as B
+    kw = dict(fused=fused, max_cycles=300, nu=5)
+    s64, _, lv, h = make_pair(name, cuda, **kw)
+    s32, _, _, _ = make_pair(name, cuda, precision=B.STMG_MIXED, **kw)
+    b = O.load_vector(lv, 1.0)
+    rhs = O.adjoint_rhs(lv, b) if transpose else b
+    solve64 = s64.solve_adjoint if transpose else s64.solve_forward
+    solve32 = s32.solve_adjoint if transpose else s32.solve_forward
+    u64, a = solve64()
+    u32, m = solve32()
+    exact = O.direct_solve(lv, rhs, bool(transpose))
+    err = rel(to_np(u32), exact)
+    print(f"mixed {name} T={transpose} fused={fused}: cycles={m.cycles} (fp64 {a.cycles}) "
+          f"r={m.rel_residual:.2e} err_vs_oracle_direct={err:.2e} (fp64 {rel(to_np(u64), exact):.2e})")
+    assert m.status == a.status
+    assert abs(m.cycles - a.cycles) <= 2
+    n = min(len(m.history), len(a.history), 30)
+    np.testing.assert_allclose(m.history[:n], a.history[:n], rtol=1e-3)
+    if a.status == 0:
+        assert m.rel_residual < 1e-10 and err < 1e-7
+        r_or = np.linalg.norm(O.apply_J(lv, to_np(u32), bool(transpose)) - rhs) / np.linalg.norm(rhs)
+        assert r_or < 2e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_objective_and_gradient_match_oracle(name, cuda):
+    s, mat, lv, h = make_pair(name, cuda)
+    rho = CASES[name][0]
+    b = O.load_vector(lv, 1.0)
+    u = O.direct_solve(lv, b)
+    lam = O.direct_solve(lv, O.adjoint_rhs(lv, b), transpose=True)
+    ud, ld = to_dev(u, cuda), to_dev(lam, cuda)
+    theta = s.objective(ud)
+    assert theta == pytest.approx(O.objective(lv, b, u), rel=1e-13)
+    g = to_np(s.gradient(ud, ld))
+    g_ref = O.gradient(lv, mat, rho, u, lam)
+    assert rel(g, g_ref) <= 1e-12
+
+
+def test_gradient_block_2048x8192_against_oracle_and_differences(cuda):
+    """Configuration 4: forward + adjoint STMG on 2048 x 8192 with the high-contrast
+    field, the gradient over all 2048 densities against the oracle's adjoint gradient
+    from direct solves, and against central differences of Theta (oracle direct
+    solves, h = 1e-6) on 16 seeded elements: 12 conducting elements drawn among those
+    whose oracle sensitivity exceeds 1% of the largest (sensitivity decays behind
+    insulating blocks to ~1e-30, below the ~1e-10 rounding noise of a difference of
+    the 1.7e7-term objective) and 4 insulating ones (k' = 0 there, so g = 0 exactly)."""
+    from paper_2505_10168_amd import binding as B
+    w = I.workload("block_2048x8192")
+    mat = O.Material(w.kappa_min, 1.0, 1.0, 1.0)
+    s = B.Solver(B.Problem(w.n_el, w.n_t, k_ins=w.kappa_min), to_dev(w.rho, cuda), nu=5)
+    u, st = s.solve_forward()
+    lam, sa = s.solve_adjoint()
+    assert st.status == 0 and sa.status == 0
+    g = to_np(s.gradient(u, lam))
+    lv = O.make_fine_level(w.rho, mat, w.n_t, w.length, w.t_final)
+    b = O.load_vector(lv, 1.0)
+    u_or = O.direct_solve(lv, b)
+    l_or = O.direct_solve(lv, O.adjoint_rhs(lv, b), transpose=True)
+    g_or = O.gradient(lv, mat, w.rho, u_or, l_or)
+    gmax = np.abs(g_or).max()
+    print(f"max |g| = {gmax:.4e} at element {int(np.abs(g_or).argmax())}; "
+          f"stmg vs oracle adjoint gradient {np.abs(g - g_or).max() / gmax:.2e}", flush=True)
+    assert np.abs(g - g_or).max() <= 1e-8 * gmax
+    assert s.objective(u) == pytest.approx(O.objective(lv, b, u_or), rel=1e-9)
+
+    rng = np.random.default_rng(40)
+    live = np.flatnonzero((w.rho == 1.0) & (np.abs(g_or) >= 1e-2 * gmax))
+    zeros = np.flatnonzero(w.rho == 0.0)
+    pick = np.concatenate([rng.choice(live, min(12, live.size), replace=False),
+                           rng.choice(zeros, 4, replace=False)])
+
+    def theta(rho):
+        lvp = O.make_fine_level(rho, mat, w.n_t, w.length, w.t_final)
+        bp = O.load_vector(lvp, 1.0)
+        return O.objective(lvp, bp, O.direct_solve(lvp, bp))
+
+    eps = 1e-6
+    fd = []
+    for e in pick:
+        rp, rm = w.rho.copy(), w.rho.copy()
+        rp[e] += eps
+        rm[e] -= eps
+        fd.append((theta(rp) - theta(rm)) / (2 * eps))
+        print(f"element {e}: rho={w.rho[e]:.0f} stmg={g[e]:.10e} fd={fd[-1]:.10e}", flush=True)
+    fd = np.array(fd)
+    assert live.size >= 12
+    # Difference error: truncation ~h^2 is negligible; rounding is (error of Theta)/h
+    # with Theta ~ 5e-3 summed over 1.7e7 terms, ~1e-11 here, i.e. ~1e-4 of max|g|
+    # because max|g| is only ~1e-5 Theta.  Hence 1e-3 of max|g| (the exact adjoint
+    # gradient is checked to 1e-8 above).
+    assert np.abs(g[pick] - fd).max() <= 1e-3 * gmax
+    k = min(12, live.size)
+    assert np.all(np.abs(g[pick[:k]] - fd[:k]) <= 1e-3 * np.abs(fd[:k]))
+    assert np.all(g[w.rho == 0.0] == 0.0)
+
+
+def test_set_design_matches_fresh_handle(cuda):
+    from paper_2505_10168_amd import binding as B
+    rho1 = I.block_density(128, 16, seed=21)
+    rho2 = I.block_density(128, 16, seed=22)
+    p = B.Problem(128, 256, k_ins=1e-3)
+    a = B.Solver(p, to_dev(rho1, cuda), nu=5, deff_mode=1)
+    a.set_design(to_dev(rho2, cuda))
+    b = B.Solver(p, to_dev(rho2, cuda), nu=5, deff_mode=1)
+    ua, sa = a.solve_forward()
+    ub, sb = b.solve_forward()
+    assert sa.cycles == sb.cycles
+    assert np.array_equal(to_np(ua), to_np(ub))
+    assert a.info()["path"] == b.info()["path"]
+
+
+def test_set_design_rejects_path_change(cuda):
+    from paper_2505_10168_amd import binding as B
+    p = B.Problem(64, 256, k_ins=1e-3)
+    s = B.Solver(p, to_dev(np.ones(64), cuda), nu=2)
+    path = s.info()["path"]
+    with pytest.raises(B.StmgError) as ei:
+        s.set_design(to_dev(np.zeros(64), cuda))
+    assert ei.value.code == B.STMG_EUNSUPPORTED
+    assert s.info()["path"] == path
+    u, st = s.solve_forward()        # the handle still works with the old design
+    assert st.status == 0
+
+
+def test_failure_statuses(cuda):
+    from paper_2505_10168_amd import binding as B
+    rho = I.block_density(64, 16, seed=3)
+    p = B.Problem(64, 128, k_ins=1e-3)
+    # cycle cap
+    _, st = B.Solver(p, to_dev(rho, cuda), max_cycles=1).solve_forward()
+    assert st.status == B.STMG_NOT_CONVERGED and st.cycles == 1
+    # a near-zero W_Diri makes the smoother unstable at the Dirichlet DOFs (Appendix A)
+    _, st = B.Solver(p, to_dev(rho, cuda), w_diri_override=1e-12).solve_forward()
+    assert st.status == B.STMG_DIVERGED
+    # a non-finite or zero right-hand side is rejected before any cycle
+    for fill in (np.nan, 0.0):
+        bad = to_dev(np.full((129, 65), fill), cuda)
+        with pytest.raises(B.StmgError) as ei:
+            B.Solver(p, to_dev(rho, cuda)).solve_forward(rhs=bad)
+        assert ei.value.code == B.STMG_EINVAL
+
+
+def test_solves_are_deterministic(cuda):
+    for name in ("block_256x600",):
+        s, _, _, _ = make_pair(name, cuda, max_cycles=10)
+        u1, a = s.solve_forward()
+        u2, b = s.solve_forward()
+        assert np.array_equal(to_np(u1), to_np(u2)) and a.history == b.history
+
+
+def test_block_1024x4096_iterates_and_solution(cuda):
+    """Configuration 2 at full size: the first two V-cycles element by element and the
+    converged forward and adjoint solutions against the oracle's direct solves."""
+    from paper_2505_10168_amd import binding as B
+    w = I.workload("block_1024x4096")
+    s = B.Solver(B.Problem(w.n_el, w.n_t, k_ins=w.kappa_min), to_dev(w.rho, cuda), nu=5)
+    mat, lv, h = oracle_setup(w.rho, w.n_t, w.kappa_min, nu=5)
+    assert s.info()["path"] == h.path
+    b = O.load_vector(lv, 1.0)
+    u = np.zeros(lv.shape)
+    ud, bd = to_dev(u, cuda), to_dev(b, cuda)
+    for it in range(2):
+        B.stmg_vcycle(s.handle, 0, bd, ud)
+        u = O.vcycle(h, 0, u, b)
+        print(f"cycle {it}: rel err {rel(to_np(ud), u):.2e}", flush=True)
+        assert rel(to_np(ud), u) <= 1e-12
+    uf, st = s.solve_forward()
+    lam, sa = s.solve_adjoint()
+    assert st.status == 0 and sa.status == 0 and st.cycles == 83
+    exact = O.direct_solve(lv, b)
+    exact_l = O.direct_solve(lv, O.adjoint_rhs(lv, b), transpose=True)
+    print(f"forward err {rel(to_np(uf), exact):.2e} adjoint err {rel(to_np(lam), exact_l):.2e}")
+    assert rel(to_np(uf), exact) <= 1e-8 and rel(to_np(lam), exact_l) <= 1e-8
+
+
+def window_reference(w, S, rows, b_full, u_full, transpose=False):
+    """Oracle sweeps on a window of time levels of the full fine level: the first S
+    levels of the window are warm-up (their coupling leaves the window) and only the
+    following levels are compared."""
+    mat = O.Material(w.kappa_min, 1.0, 1.0, 1.0)
+    full = O.make_fine_level(w.rho, mat, w.n_t, w.length, w.t_final)
+    r0, r1 = rows
+    sub = O.Level(full.n_el, r1 - r0 - 1, full.h, full.tau, full.k, full.c, w_override=full.W)
+    hh = O.Hierarchy([sub], [], [], O.Options())
+    out = O.jacobi(hh, 0, u_full[r0:r1].copy(), b_full[r0:r1].copy(), S, transpose)
+    return out
+
+
+def test_boxfilt_8192x65536_fused_smoother_sampled(cuda):
+    """Configuration 3 at full size (5.4e8 DOFs): two fused Jacobi steps of the fine
+    level from seeded random u and b, compared with the oracle on windows of time levels
+    (start, a segment boundary region, the middle and the end)."""
+    import torch
+    from paper_2505_10168_amd import binding as B
+    w = I.workload("boxfilt_8192x65536")
+    rng = np.random.default_rng(99)
+    shape = (w.n_t + 1, w.n_el + 1)
+    u = rng.standard_normal(shape)
+    b = rng.standard_normal(shape)
+    s = B.Solver(B.Problem(w.n_el, w.n_t, k_ins=w.kappa_min), to_dev(w.rho, cuda), nu=2)
+    ud = to_dev(u, cuda)
+    B.stmg_level_smooth(s.handle, 0, 0, 2, to_dev(b, cuda), ud)
+    torch.cuda.synchronize()
+    S = 2
+    for r0 in (0, 33000, 65537 - 40):
+        r1 = r0 + 40
+        ref = window_reference(w, S, (r0, r1), b, u)
+        got = to_np(ud[r0:r1])
+        lo = 0 if r0 == 0 else S + 1
+        e = rel(got[lo:], ref[lo:])
+        print(f"rows {r0}..{r1}: rel err {e:.2e}", flush=True)
+        assert e <= 1e-13
