@@ -1,0 +1,131 @@
+"""GPU tests of the autograd Function and of the continuous-batching server."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from tests.helpers import I, O, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_theta_grad(rho, n_t, kmin, c_ins=1.0):
+    mat = O.Material(kmin, 1.0, c_ins, 1.0)
+    lv = O.make_fine_level(rho, mat, n_t, 1.0, 0.1)
+    b = O.load_vector(lv, 1.0)
+    u = O.direct_solve(lv, b)
+    lam = O.direct_solve(lv, O.adjoint_rhs(lv, b), transpose=True)
+    return O.objective(lv, b, u), O.gradient(lv, mat, rho, u, lam)
+
+
+@pytest.mark.parametrize("c_ins", [1.0, 0.1])
+def test_autograd_matches_oracle_gradient(c_ins, cuda):
+    import torch
+    from paper_2505_10168_amd import binding as B
+    from paper_2505_10168_amd.autograd import ComplianceSolver
+    n_el, n_t, kmin = 96, 160, 1e-2
+    rho = np.random.default_rng(3).uniform(0.2, 0.9, n_el)
+    prob = B.Problem(n_el, n_t, k_ins=kmin, c_ins=c_ins)
+    cs = ComplianceSolver(prob, to_dev(rho, cuda), nu=5, max_cycles=400)
+    x = to_dev(rho, cuda).requires_grad_(True)
+    theta = cs(x)
+    theta.backward()
+    th_ref, g_ref = oracle_theta_grad(rho, n_t, kmin, c_ins)
+    print(f"theta {theta.item():.12e} (oracle {th_ref:.12e}); grad rel err "
+          f"{rel(to_np(x.grad), g_ref):.2e}; cycles {cs.last_forward.cycles}/{cs.last_adjoint.cycles}")
+    assert theta.item() == pytest.approx(th_ref, rel=1e-9)
+    assert rel(to_np(x.grad), g_ref) <= 1e-8
+    # a second design on the same resident hierarchy, with a scaled upstream gradient
+    rho2 = np.clip(rho[::-1].copy() + 0.05, 0, 1)
+    y = to_dev(rho2, cuda).requires_grad_(True)
+    (3.0 * cs(y)).backward()
+    th2, g2 = oracle_theta_grad(rho2, n_t, kmin, c_ins)
+    assert rel(to_np(y.grad), 3.0 * g2) <= 1e-8
+    cs.close()
+
+
+def test_autograd_backward_after_interleaved_forward(cuda):
+    """backward re-loads the design of its own forward if another forward ran since."""
+    from paper_2505_10168_amd import binding as B
+    from paper_2505_10168_amd.autograd import ComplianceSolver
+    n_el, n_t, kmin = 64, 96, 1e-2
+    r1 = np.random.default_rng(4).uniform(0.2, 0.9, n_el)
+    r2 = np.random.default_rng(5).uniform(0.2, 0.9, n_el)
+    cs = ComplianceSolver(B.Problem(n_el, n_t, k_ins=kmin), to_dev(r1, cuda), nu=5, max_cycles=400)
+    a = to_dev(r1, cuda).requires_grad_(True)
+    b = to_dev(r2, cuda).requires_grad_(True)
+    ta, tb = cs(a), cs(b)
+    ta.backward()
+    tb.backward()
+    assert rel(to_np(a.grad), oracle_theta_grad(r1, n_t, kmin)[1]) <= 1e-8
+    assert rel(to_np(b.grad), oracle_theta_grad(r2, n_t, kmin)[1]) <= 1e-8
+    cs.close()
+
+
+def small_stream(n, seed):
+    return I.request_stream(n, 0.0, seed=seed, el_exp=(6, 9), t_exp=(7, 10))
+
+
+def to_req(r):
+    from paper_2505_10168_amd.serving import SolveRequest
+    return SolveRequest(r.n_el, r.n_t, r.rho, r.kappa_min, r.with_adjoint, rid=r.rid)
+
+
+def test_serving_results_same_alone_and_in_the_mix(cuda):
+    from paper_2505_10168_amd.serving import Server
+    reqs = small_stream(16, seed=11)
+    with Server(cuda, slots=4, nu=5, max_cycles=300) as srv:
+        futs = [srv.submit(to_req(r)) for r in reqs]
+        mixed = {f.result().rid: f.result() for f in futs}
+        stats = srv.stats
+    assert stats.completed == len(reqs) and stats.peak_in_flight > 1
+    with Server(cuda, slots=1, nu=5, max_cycles=300, keep_resident=False) as solo:
+        alone = {r.rid: solo.submit(to_req(r)).result() for r in reqs}
+    for r in reqs:
+        m, a = mixed[r.rid], alone[r.rid]
+        assert m.forward.status == 0 and m.forward.rel_residual < 1e-10
+        assert m.theta == a.theta
+        assert np.array_equal(m.final_temperature, a.final_temperature)
+        if r.with_adjoint:
+            assert np.array_equal(m.gradient, a.gradient)
+    # against the FP64 oracle (direct solves) for a few of them
+    for r in reqs[:4]:
+        th, g = oracle_theta_grad(r.rho, r.n_t, r.kappa_min)
+        assert mixed[r.rid].theta == pytest.approx(th, rel=1e-8)
+        if r.with_adjoint:
+            assert rel(mixed[r.rid].gradient, g) <= 1e-6
+
+
+def test_serving_admission_by_footprint(cuda):
+    from paper_2505_10168_amd import binding as B
+    from paper_2505_10168_amd.serving import Server, SolveRequest
+    reqs = small_stream(8, seed=12)
+    big = max(reqs, key=lambda r: r.dofs)
+    with Server(cuda, slots=4, nu=5, max_cycles=300, hbm_budget=1) as tiny:
+        fut = tiny.submit(to_req(big))
+        with pytest.raises(MemoryError):
+            fut.result()
+    # a budget that fits exactly one of the largest requests at a time
+    probe = Server(cuda, slots=1, nu=5)
+    one = probe._footprint(to_req(big))
+    probe.close()
+    with Server(cuda, slots=4, nu=5, max_cycles=300, hbm_budget=int(1.5 * one),
+                keep_resident=False) as srv:
+        futs = [srv.submit(to_req(r)) for r in reqs]
+        res = [f.result() for f in futs]
+        assert srv.stats.peak_bytes <= int(1.5 * one)
+    assert all(r.forward.status == 0 for r in res)
+
+
+def test_serving_reuses_resident_hierarchies(cuda):
+    from paper_2505_10168_amd.serving import Server, SolveRequest
+    rng = np.random.default_rng(2)
+    with Server(cuda, slots=2, nu=5, max_cycles=300) as srv:
+        outs = []
+        for k in range(4):
+            rho = I.block_density(128, 16, seed=30 + k)
+            outs.append(srv.submit(SolveRequest(128, 256, rho, 1e-3, True)).result())
+        assert srv.stats.reused >= 2 and srv.stats.created <= 2
+    for k, o in enumerate(outs):
+        th, g = oracle_theta_grad(I.block_density(128, 16, seed=30 + k), 256, 1e-3)
+        assert o.theta == pytest.approx(th, rel=1e-8)
