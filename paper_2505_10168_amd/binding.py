@@ -58,6 +58,10 @@ class stmg_info(C.Structure):
 def _load():
     if not LIB_PATH.exists():
         raise ImportError(f"libstmg.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    # PyTorch ships its own HIP and HSA runtimes (same SONAME, different file name).
+    # Import it first so that libstmg binds to the runtime torch uses: loading the
+    # system runtime first would put two HIP runtimes into the process.
+    import torch  # noqa: F401
     lib = C.CDLL(str(LIB_PATH))
     P, I, D, VP = C.POINTER, C.c_int, C.c_double, C.c_void_p
     sig = {
