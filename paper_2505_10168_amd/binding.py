@@ -9,12 +9,15 @@ no CPU fallback.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from dataclasses import dataclass, field
 from pathlib import Path
 
 import numpy as np
 
-LIB_PATH = Path(__file__).resolve().parent / "_lib" / "libstmg.so"
+# STMG_LIBRARY may point to another build of the library (e.g. a tuning variant).
+LIB_PATH = Path(os.environ.get("STMG_LIBRARY") or
+                Path(__file__).resolve().parent / "_lib" / "libstmg.so")
 
 STMG_OK, STMG_NOT_CONVERGED, STMG_DIVERGED = 0, 1, 2
 STMG_EINVAL, STMG_ENOMEM, STMG_EHIP, STMG_EUNSUPPORTED = -1, -2, -3, -4

@@ -118,8 +118,8 @@ void launch_level_stats(const double* k, const double* c, int n, double* out, hi
 // c_e h/6 [[2,1],[1,2]] to C and k_e/h [[1,-1],[-1,1]] to K.  A = C/dt + K.
 // Couplings to the Dirichlet node 0 are removed (Appendix A), so lo[1] = mlo[1] = 0.
 __global__ void k_stencil_coef(const double* __restrict__ k, const double* __restrict__ c, int N,
-                               double h, double tau, double omega, double* __restrict__ coef,
-                               float* __restrict__ coef32) {
+                               double h, double tau, double omega, double W,
+                               double* __restrict__ coef, float* __restrict__ coef32) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > N) return;
     const int64_t S = N + 1;
@@ -141,8 +141,11 @@ __global__ void k_stencil_coef(const double* __restrict__ k, const double* __res
         }
         wd = omega / di;
     }
-    const double kl = (i >= 1) ? k[i - 1] / h : 0.0;
+    // Node 0 is a Dirichlet row, J u = W u: its only non-zero entries are kl = W and
+    // wd = omega / W (the fused kernels evaluate it with a zero left neighbour).
+    const double kl = (i >= 1) ? k[i - 1] / h : W;
     const double kr = (i >= 1 && i < N) ? k[i] / h : 0.0;
+    if (i == 0) wd = omega / W;
     double v[9] = {lo, di, up, mlo, mdi, mup, wd, kl, kr};
     for (int a = 0; a < 9; ++a) {
         coef[a * S + i] = v[a];
@@ -151,9 +154,9 @@ __global__ void k_stencil_coef(const double* __restrict__ k, const double* __res
 }
 
 void launch_stencil_coef(const double* k, const double* c, int N, double h, double tau,
-                         double omega, double* coef, float* coef32, hipStream_t s) {
+                         double omega, double W, double* coef, float* coef32, hipStream_t s) {
     hipLaunchKernelGGL(k_stencil_coef, dim3(blocks_for(N + 1)), dim3(kBlock), 0, s, k, c, N, h,
-                       tau, omega, coef, coef32);
+                       tau, omega, W, coef, coef32);
 }
 
 // Thomas factors of the interior tridiagonal A (nodes 1..N); A is time invariant so

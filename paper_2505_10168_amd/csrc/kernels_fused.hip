@@ -31,7 +31,19 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
-constexpr int PF = 3;        // rows in flight per wave (register prefetch ring)
+#ifndef STMG_PREFETCH_ROWS
+#define STMG_PREFETCH_ROWS 3
+#endif
+#ifndef STMG_NT_STORES
+#define STMG_NT_STORES 1
+#endif
+#ifndef STMG_TARGET_WAVES
+#define STMG_TARGET_WAVES 16384
+#endif
+#ifndef STMG_MIN_SEGMENT
+#define STMG_MIN_SEGMENT 4
+#endif
+constexpr int PF = STMG_PREFETCH_ROWS;   // rows in flight per wave (register prefetch ring)
 constexpr int kXcds = 8;     // accelerator complex dies of an MI355X
 constexpr int kMaxFused = 6; // Jacobi steps one pass can fuse
 
@@ -100,10 +112,19 @@ __device__ __forceinline__ void ld(const float* p, float (&v)[4]) {
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 __device__ __forceinline__ void st(double* p, const double (&v)[2]) {
+#if STMG_NT_STORES
+    __builtin_nontemporal_store(v[0], p);
+    __builtin_nontemporal_store(v[1], p + 1);
+#else
     *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+#endif
 }
 __device__ __forceinline__ void st(float* p, const float (&v)[4]) {
+#if STMG_NT_STORES
+    for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(v[j], p + j);
+#else
     *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+#endif
 }
 // coarse x-prolongation / x-restriction touch K/2 coarse values per lane
 __device__ __forceinline__ void ldh(const double* p, double (&v)[1]) { v[0] = p[0]; }
@@ -123,34 +144,33 @@ struct LaneCoef {
 
 // One Jacobi step (JAC) or the residual (!JAC) of the lane's K columns at one row.
 // x: state at this row, xl/xr: neighbour columns; p/pl/pr: the same at the coupled
-// row.  Invalid columns yield 0.
+// row (all zero on uncoupled rows).  Column 0 (Dirichlet) is expressed through its
+// coefficients (kl = W_Diri, wd = omega / W_Diri, the rest 0, left neighbour 0), and
+// columns beyond the last node have zero coefficients and zero data, so no
+// per-element branch is needed; only column 1 drops its eliminated left neighbour.
+// Time level 0 is a Dirichlet row for every column (dir_row, uniform).
 template <typename T, int K, bool JAC>
 __device__ __forceinline__ void row_step(const LevelView<T>& L, const LaneCoef<T, K>& C,
-                                         const bool (&valid)[K], const bool (&col1)[K],
-                                         bool dir_col0, bool dir_row, bool coupled,
-                                         const T (&x)[K], T xl, T xr, const T (&p)[K], T pl,
-                                         T pr, const T (&bb)[K], T (&y)[K]) {
+                                         bool col1_lane, bool dir_row, const T (&x)[K], T xl,
+                                         T xr, const T (&p)[K], T pl, T pr, const T (&bb)[K],
+                                         T (&y)[K]) {
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        if (!valid[j]) {
-            y[j] = T(0);
-            continue;
-        }
         T Jx, scale;
-        if (dir_row || (j == 0 && dir_col0)) {
+        if (dir_row) {
             Jx = L.W * x[j];
             scale = L.wW;
         } else {
             T xm = (j > 0) ? x[j - 1] : xl;
             T pm = (j > 0) ? p[j - 1] : pl;
-            if (col1[j]) {
+            if (j == 1 && col1_lane) {
                 xm = T(0);
                 pm = T(0);
             }
             const T xp = (j < K - 1) ? x[j + 1] : xr;
             const T pp = (j < K - 1) ? p[j + 1] : pr;
             Jx = stencil_interior<T>(C.mlo[j], C.mdi[j], C.mup[j], C.kl[j], C.kr[j], xm, x[j], xp,
-                                     coupled, pm, p[j], pp);
+                                     true, pm, p[j], pp);
             scale = C.wd[j];
         }
         const T r = bb[j] - Jx;
@@ -158,7 +178,7 @@ __device__ __forceinline__ void row_step(const LevelView<T>& L, const LaneCoef<T
     }
 }
 
-template <typename T, int TR, int S, int TAIL>
+template <typename T, int TR, int S, int TAIL, bool HASZ>
 __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArgs<T>& a) {
     constexpr int K = Lanes<T>::K;
     constexpr int KH = K / 2;
@@ -181,13 +201,10 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
     const int N = L.N, Nt = L.Nt;
     const int64_t P = L.P;
 
-    bool valid[K], col1[K];
+    bool valid[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        valid[j] = lane_in && (g + j <= N);
-        col1[j] = (g + j == 1);
-    }
-    const bool dir_col0 = (g == 0);
+    for (int j = 0; j < K; ++j) valid[j] = lane_in && (g + j <= N);
+    const bool col1_lane = (g == 0);   // columns start at even indices: node 1 is j = 1 of lane g = 0
 
     LaneCoef<T, K> C;
 #pragma unroll
@@ -211,16 +228,13 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
     const int count = TR ? (first - n0 + 1) : (n1 - first);
     constexpr bool need_b = (S > 0 || TAIL != TAIL_NONE);
 
-    // Sweep states of the previous streamed row: level k = 0..S.
+    // Sweep states of the previous streamed row: level k = 0..S.  Their neighbour
+    // columns are fetched again by DPP when needed rather than kept in registers.
     T prev[S + 1][K];
-    T prevl[S + 1], prevr[S + 1];
 #pragma unroll
-    for (int k = 0; k <= S; ++k) {
+    for (int k = 0; k <= S; ++k)
 #pragma unroll
         for (int j = 0; j < K; ++j) prev[k][j] = T(0);
-        prevl[k] = T(0);
-        prevr[k] = T(0);
-    }
     T r_pair[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) r_pair[j] = T(0);
@@ -228,30 +242,34 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
 
     // Row buffers: rows are fetched PF steps ahead of use (a register ring that the
     // unrolled inner loop indexes statically).
-    T ru[PF][K], rb[PF][K], rz[PF][K];
-    auto fetch = [&](int n, T (&fu)[K], T (&fb)[K], T (&fz)[K]) {
+    constexpr int KZ = HASZ ? K : 1;
+    T ru[PF][K], rb[PF][K], rz[PF][KZ];
+    auto fetch = [&](int n, T (&fu)[K], T (&fb)[K], T (&fz)[KZ]) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             fu[j] = T(0);
             fb[j] = T(0);
-            fz[j] = T(0);
         }
+#pragma unroll
+        for (int j = 0; j < KZ; ++j) fz[j] = T(0);
         if (!lane_in) return;
         const int64_t ro = (int64_t)n * P + g;
         if (!a.zero_in) ld(a.u + ro, fu);
         if (need_b) ld(a.b + ro, fb);
-        if (a.head == 1) {
-            T zh[KH];
-            ldh(a.z + (int64_t)n * a.Pz + (g >> 1), zh);
+        if constexpr (HASZ) {
+            if (a.head == 1) {
+                T zh[KH];
+                ldh(a.z + (int64_t)n * a.Pz + (g >> 1), zh);
 #pragma unroll
-            for (int j = 0; j < KH; ++j) fz[j] = zh[j];
-        } else if (a.head == 2) {
-            ld(a.z + (int64_t)(n >> 1) * a.Pz + g, fz);
-        } else if constexpr (std::is_same<T, double>::value) {
-            if (a.head == 3) {
-                const float2 e = *reinterpret_cast<const float2*>(a.e32 + ro);
-                fz[0] = (T)e.x;
-                fz[1] = (T)e.y;
+                for (int j = 0; j < KH; ++j) fz[j] = zh[j];
+            } else if (a.head == 2) {
+                ld(a.z + (int64_t)(n >> 1) * a.Pz + g, fz);
+            } else if constexpr (std::is_same<T, double>::value) {
+                if (a.head == 3) {
+                    const float2 e = *reinterpret_cast<const float2*>(a.e32 + ro);
+                    fz[0] = (T)e.x;
+                    fz[1] = (T)e.y;
+                }
             }
         }
     };
@@ -271,19 +289,26 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
         for (int j = 0; j < K; ++j) {
             x[j] = ru[d][j];
             bb[j] = rb[d][j];
-            zz[j] = rz[d][j];
+            zz[j] = (HASZ && j < KZ) ? rz[d][j < KZ ? j : 0] : T(0);
         }
         if (it + PF < count) fetch(row_of(it + PF), ru[d], rb[d], rz[d]);
         const bool out_row = (n >= n0) && (n < n1);
         const bool dir_row = (n == 0);
         const bool coupled = TR ? (n < Nt) : (n >= 2);
+        if (!coupled) {
+            // first levels of J (last of J^T): no coupling, i.e. a zero coupled row
+#pragma unroll
+            for (int k = 0; k <= S; ++k)
+#pragma unroll
+                for (int j = 0; j < K; ++j) prev[k][j] = T(0);
+        }
 
         // Prolongation head: x += P z.
-        if (a.head == 1) {
+        if (!HASZ) {
+        } else if (a.head == 1) {
             const T znext = shfl_dn1(zz[0]);   // first coarse value of the next lane
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                if (!valid[j]) continue;
                 const T za = zz[j >> 1];
                 if ((j & 1) == 0) {
                     x[j] += za;
@@ -294,12 +319,16 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
             }
         } else if (a.head == 2) {
 #pragma unroll
-            for (int j = 0; j < K; ++j)
-                if (valid[j]) x[j] += zz[j];
+            for (int j = 0; j < K; ++j) x[j] += zz[j];
         } else if (a.head == 3) {
 #pragma unroll
-            for (int j = 0; j < K; ++j)
-                if (valid[j]) x[j] = fmaT((T)a.s_old, zz[j], x[j]);
+            for (int j = 0; j < K; ++j) x[j] = fmaT((T)a.s_old, zz[j], x[j]);
+        }
+        if constexpr (HASZ) {
+            // the interpolation reaches past the last node and into the lane left of
+            // column 0; those columns must stay zero (padding, eliminated neighbour)
+#pragma unroll
+            for (int j = 0; j < K; ++j) x[j] = valid[j] ? x[j] : T(0);
         }
         T xl = shfl_up1(x[K - 1]);
         T xr = shfl_dn1(x[0]);
@@ -307,15 +336,14 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             T y[K];
-            row_step<T, K, true>(L, C, valid, col1, dir_col0, dir_row, coupled, x, xl, xr,
-                                 prev[k], prevl[k], prevr[k], bb, y);
+            const T pl = shfl_up1(prev[k][K - 1]);
+            const T pr = shfl_dn1(prev[k][0]);
+            row_step<T, K, true>(L, C, col1_lane, dir_row, x, xl, xr, prev[k], pl, pr, bb, y);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 prev[k][j] = x[j];
                 x[j] = y[j];
             }
-            prevl[k] = xl;
-            prevr[k] = xr;
             xl = shfl_up1(x[K - 1]);
             xr = shfl_dn1(x[0]);
         }
@@ -324,12 +352,11 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
 
         if constexpr (TAIL != TAIL_NONE) {
             T r[K];
-            row_step<T, K, false>(L, C, valid, col1, dir_col0, dir_row, coupled, x, xl, xr,
-                                  prev[S], prevl[S], prevr[S], bb, r);
+            const T pl = shfl_up1(prev[S][K - 1]);
+            const T pr = shfl_dn1(prev[S][0]);
+            row_step<T, K, false>(L, C, col1_lane, dir_row, x, xl, xr, prev[S], pl, pr, bb, r);
 #pragma unroll
             for (int j = 0; j < K; ++j) prev[S][j] = x[j];
-            prevl[S] = xl;
-            prevr[S] = xr;
             if constexpr (TAIL == TAIL_RX) {
                 // coarse node I = (g + j)/2 for even j: r_{2I} + 1/2 (r_{2I-1} + r_{2I+1})
                 const T rl = shfl_up1(r[K - 1]);
@@ -413,13 +440,13 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
 
 // Two entry points with the same body: the finest level gets its own symbol so that
 // profiles attribute the dominant passes separately from the coarse levels.
-template <typename T, int TR, int S, int TAIL>
+template <typename T, int TR, int S, int TAIL, bool HASZ>
 __global__ __launch_bounds__(256) void k_fused(LevelView<T> L, FusedArgs<T> a) {
-    fused_body<T, TR, S, TAIL>(L, a);
+    fused_body<T, TR, S, TAIL, HASZ>(L, a);
 }
-template <typename T, int TR, int S, int TAIL>
+template <typename T, int TR, int S, int TAIL, bool HASZ>
 __global__ __launch_bounds__(256) void k_fused_fine(LevelView<T> L, FusedArgs<T> a) {
-    fused_body<T, TR, S, TAIL>(L, a);
+    fused_body<T, TR, S, TAIL, HASZ>(L, a);
 }
 
 struct Geometry {
@@ -440,9 +467,9 @@ Geometry geometry(int N, int Nt, int sweeps) {
     G.xw = (N + 1 + G.U - 1) / G.U;
     const int64_t rows = Nt + 1;
     // enough waves to keep every SIMD busy several times over
-    const int64_t target = 16384;
+    const int64_t target = STMG_TARGET_WAVES;
     int64_t seg = (rows * G.xw + target - 1) / target;
-    const int64_t min_seg = 4;
+    const int64_t min_seg = STMG_MIN_SEGMENT;
     if (seg < min_seg) seg = min_seg;
     if (seg > 1024) seg = 1024;
     if (seg & 1) ++seg;
@@ -451,25 +478,34 @@ Geometry geometry(int N, int Nt, int sweeps) {
     return G;
 }
 
-template <typename T, int TR, int S, int TAIL>
+template <typename T, int TR, int S, int TAIL, bool HASZ>
 void launch_one(const LevelView<T>& L, const FusedArgs<T>& a, bool fine, hipStream_t s) {
     const int blocks = (a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
     if (fine)
-        hipLaunchKernelGGL((k_fused_fine<T, TR, S, TAIL>), dim3(blocks),
+        hipLaunchKernelGGL((k_fused_fine<T, TR, S, TAIL, HASZ>), dim3(blocks),
                            dim3(kWave * kWavesPerBlock), 0, s, L, a);
     else
-        hipLaunchKernelGGL((k_fused<T, TR, S, TAIL>), dim3(blocks), dim3(kWave * kWavesPerBlock),
-                           0, s, L, a);
+        hipLaunchKernelGGL((k_fused<T, TR, S, TAIL, HASZ>), dim3(blocks),
+                           dim3(kWave * kWavesPerBlock), 0, s, L, a);
 }
 
+// Instantiated combinations: pre-smoothing passes (no head; restriction, norm or no
+// tail) and post-smoothing passes (prolongation head; norm or no tail).
 template <typename T, int TR, int S>
 void dispatch_tail(int tail, const LevelView<T>& L, const FusedArgs<T>& a, bool fine,
                    hipStream_t s) {
+    if (a.head != 0) {
+        if (tail == TAIL_NORM)
+            launch_one<T, TR, S, TAIL_NORM, true>(L, a, fine, s);
+        else
+            launch_one<T, TR, S, TAIL_NONE, true>(L, a, fine, s);
+        return;
+    }
     switch (tail) {
-        case TAIL_NONE: launch_one<T, TR, S, TAIL_NONE>(L, a, fine, s); break;
-        case TAIL_RX: launch_one<T, TR, S, TAIL_RX>(L, a, fine, s); break;
-        case TAIL_RT: launch_one<T, TR, S, TAIL_RT>(L, a, fine, s); break;
-        default: launch_one<T, TR, S, TAIL_NORM>(L, a, fine, s); break;
+        case TAIL_NONE: launch_one<T, TR, S, TAIL_NONE, false>(L, a, fine, s); break;
+        case TAIL_RX: launch_one<T, TR, S, TAIL_RX, false>(L, a, fine, s); break;
+        case TAIL_RT: launch_one<T, TR, S, TAIL_RT, false>(L, a, fine, s); break;
+        default: launch_one<T, TR, S, TAIL_NORM, false>(L, a, fine, s); break;
     }
 }
 
@@ -528,9 +564,9 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
         if constexpr (std::is_same<T, double>::value) {
             if (fp.sweeps != 0 || fp.tail != 'c' || fp.prolong != 'c') return -1;
             if (fp.trans)
-                launch_one<T, 1, 0, TAIL_DEFECT>(L, a, fp.fine != 0, s);
+                launch_one<T, 1, 0, TAIL_DEFECT, true>(L, a, fp.fine != 0, s);
             else
-                launch_one<T, 0, 0, TAIL_DEFECT>(L, a, fp.fine != 0, s);
+                launch_one<T, 0, 0, TAIL_DEFECT, true>(L, a, fp.fine != 0, s);
             return G.nwaves;
         } else {
             return -1;

@@ -348,7 +348,7 @@ int coarse_coefficients(stmg_ctx* h, const Level& f, char dir, Level& c) {
 }
 
 int finish_level(stmg_ctx* h, Level& l, bool coarsest) {
-    launch_stencil_coef(l.k, l.c, l.N, l.h, l.tau, h->o.omega, l.coef, l.coef32, h->s);
+    launch_stencil_coef(l.k, l.c, l.N, l.h, l.tau, h->o.omega, l.W, l.coef, l.coef32, h->s);
     if (coarsest) {
         launch_thomas_factors(l.coef, l.N, l.thomas, l.thomas + (l.N + 1), h->s);
         if (l.ainv)

@@ -24,7 +24,7 @@ void launch_coarsen_x(const double* k, const double* c, const double* chi, int n
 void launch_level_stats(const double* k, const double* c, int n, double* out, hipStream_t s);
 // coef: 9 arrays of N+1 doubles (lo, di, up, mlo, mdi, mup, wd, kl, kr); coef32: FP32 copy
 void launch_stencil_coef(const double* k, const double* c, int N, double h, double tau,
-                         double omega, double* coef, float* coef32, hipStream_t s);
+                         double omega, double W, double* coef, float* coef32, hipStream_t s);
 void launch_thomas_factors(const double* coef, int N, double* cp, double* inv, hipStream_t s);
 void launch_load_vector(const double* q, double q0, int N, int Nt, double h, double* b,
                         int64_t P, hipStream_t s);
