@@ -294,7 +294,7 @@ __global__ void k_apply(LevelView<T> L, int mode, const T* __restrict__ x,
                 y0 = x[q];
                 yp = (i == L.N) ? T(0) : x[q + 1];
             }
-            Jx = stencil_interior<T>(L.mlo[i], L.mdi[i], L.mup[i], L.kl[i], L.kr[i], xm, x0, xp,
+            Jx = stencil_interior<T>(L.mlo[i], L.mdi[i], L.mup[i], L.kl[i], L.kr[i], T(-1), xm, x0, xp,
                                      coupled, ym, y0, yp);
             scale = L.wd[i];
         }
@@ -634,7 +634,7 @@ __global__ void k_residual_sumsq(LevelView<T> L, const T* __restrict__ u, const 
                     y0 = u[q];
                     yp = (i == L.N) ? T(0) : u[q + 1];
                 }
-                Jx = stencil_interior<T>(L.mlo[i], L.mdi[i], L.mup[i], L.kl[i], L.kr[i],
+                Jx = stencil_interior<T>(L.mlo[i], L.mdi[i], L.mup[i], L.kl[i], L.kr[i], T(-1),
                                          (i == 1) ? T(0) : u[o - 1], u[o],
                                          (i == L.N) ? T(0) : u[o + 1], coupled, ym, y0, yp);
             }

@@ -40,6 +40,9 @@ constexpr int kWavesPerBlock = 4;
 #ifndef STMG_TARGET_WAVES
 #define STMG_TARGET_WAVES 16384
 #endif
+#ifndef STMG_TARGET_WAVES_ALU
+#define STMG_TARGET_WAVES_ALU 3072
+#endif
 #ifndef STMG_MIN_SEGMENT
 #define STMG_MIN_SEGMENT 4
 #endif
@@ -78,13 +81,13 @@ template <> struct Lanes<float> { static constexpr int K = 4; };
 
 // Neighbour exchange across the whole wave with DPP wave shifts (ALU latency, no LDS
 // round trip): shfl_up1 gives lane i the value of lane i-1, shfl_dn1 the value of
-// lane i+1; the edge lane keeps its own value.
+// lane i+1; the edge lane (0, resp. 63) receives 0.
 constexpr int kDppWaveShl1 = 0x130;
 constexpr int kDppWaveShr1 = 0x138;
 
 template <int CTRL>
 __device__ __forceinline__ int dpp32(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp64(double v) {
@@ -140,41 +143,57 @@ __device__ __forceinline__ void sth(float* p, const float (&v)[2]) {
 template <typename T, int K>
 struct LaneCoef {
     T mlo[K], mdi[K], mup[K], kl[K], kr[K], wd[K];
+    T me[K];   // multiplier of x_j in e_j = x_j - x_{j+1}: 0 for column 0, else 1
 };
 
 // One Jacobi step (JAC) or the residual (!JAC) of the lane's K columns at one row.
-// x: state at this row, xl/xr: neighbour columns; p/pl/pr: the same at the coupled
-// row (all zero on uncoupled rows).  Column 0 (Dirichlet) is expressed through its
-// coefficients (kl = W_Diri, wd = omega / W_Diri, the rest 0, left neighbour 0), and
-// columns beyond the last node have zero coefficients and zero data, so no
-// per-element branch is needed; only column 1 drops its eliminated left neighbour.
-// Time level 0 is a Dirichlet row for every column (dir_row, uniform).
-template <typename T, int K, bool JAC>
+// x: state at this row, p: the same sweep state at the coupled row (zero on uncoupled
+// rows).  The operands of stencil_interior are shared between neighbouring columns
+// instead of being formed per column:
+//   d_j = x_j - p_j        (the mass differences dm, d0, dp of columns j+1, j, j-1)
+//   e_j = x_j - x_{j+1}    (x0 - xp of column j; x0 - xm of column j+1 is -e_j)
+// Each rounded operation has the same operands as in stencil_interior (negation and
+// fma(1, a, -b) = a - b are exact), so the result is bit-identical, with 9 instead of
+// 12 floating-point operations per DOF.  Column 0 (Dirichlet) is expressed through its
+// coefficients (kl = W_Diri, wd = omega / W_Diri, the rest 0) and the zero column to
+// its left, which lies in a halo lane; column 1 drops its eliminated left neighbour
+// through me (e_0 = -x_1, and mlo[1] = 0); columns beyond the last node have zero
+// coefficients and zero data.  Time level 0 is a Dirichlet row for every column: DIR
+// selects that form at compile time (the caller branches once per row, on a
+// wave-uniform test).
+template <typename T, int K, bool JAC, bool DIR>
 __device__ __forceinline__ void row_step(const LevelView<T>& L, const LaneCoef<T, K>& C,
-                                         bool col1_lane, bool dir_row, const T (&x)[K], T xl,
-                                         T xr, const T (&p)[K], T pl, T pr, const T (&bb)[K],
+                                         const T (&x)[K], const T (&p)[K], const T (&bb)[K],
                                          T (&y)[K]) {
+    if constexpr (DIR) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        T Jx, scale;
-        if (dir_row) {
-            Jx = L.W * x[j];
-            scale = L.wW;
-        } else {
-            T xm = (j > 0) ? x[j - 1] : xl;
-            T pm = (j > 0) ? p[j - 1] : pl;
-            if (j == 1 && col1_lane) {
-                xm = T(0);
-                pm = T(0);
-            }
-            const T xp = (j < K - 1) ? x[j + 1] : xr;
-            const T pp = (j < K - 1) ? p[j + 1] : pr;
-            Jx = stencil_interior<T>(C.mlo[j], C.mdi[j], C.mup[j], C.kl[j], C.kr[j], xm, x[j], xp,
-                                     true, pm, p[j], pp);
-            scale = C.wd[j];
+        for (int j = 0; j < K; ++j) {
+            const T r = bb[j] - L.W * x[j];
+            y[j] = JAC ? jacobi_update<T>(x[j], L.wW, r) : r;
         }
-        const T r = bb[j] - Jx;
-        y[j] = JAC ? jacobi_update<T>(x[j], scale, r) : r;
+    } else {
+        T d[K], e[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) d[j] = x[j] - p[j];
+        const T xr = shfl_dn1(x[0]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) e[j] = fmaT(C.me[j], x[j], -((j < K - 1) ? x[j + 1] : xr));
+        const T dl = shfl_up1(d[K - 1]);
+        const T dr = shfl_dn1(d[0]);
+        const T el = shfl_up1(e[K - 1]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const T dm = (j > 0) ? d[j - 1] : dl;
+            const T dp = (j < K - 1) ? d[j + 1] : dr;
+            const T em = (j > 0) ? e[j - 1] : el;
+            T s = C.mdi[j] * d[j];
+            s = fmaT(C.mlo[j], dm, s);
+            s = fmaT(C.mup[j], dp, s);
+            s = fmaT(C.kl[j], -em, s);
+            s = fmaT(C.kr[j], e[j], s);
+            const T r = bb[j] - s;
+            y[j] = JAC ? jacobi_update<T>(x[j], C.wd[j], r) : r;
+        }
     }
 }
 
@@ -189,7 +208,9 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
     const int nb = gridDim.x, q = nb / kXcds, r = nb % kXcds;
     const int xcd = blockIdx.x % kXcds, idx = blockIdx.x / kXcds;
     const int lb = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-    const int wave = lb * kWavesPerBlock + (threadIdx.x >> 6);
+    // wave-uniform by construction; readfirstlane lets the compiler know it, so that
+    // the per-row tests below are scalar branches
+    const int wave = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (threadIdx.x >> 6));
     if (wave >= a.nwaves) return;
     const int HL = a.HL;
     const int U = (kWave - 2 * HL) * K;
@@ -204,7 +225,6 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
     bool valid[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) valid[j] = lane_in && (g + j <= N);
-    const bool col1_lane = (g == 0);   // columns start at even indices: node 1 is j = 1 of lane g = 0
 
     LaneCoef<T, K> C;
 #pragma unroll
@@ -217,6 +237,7 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
         C.kl[j] = v ? L.kl[c] : T(0);
         C.kr[j] = v ? L.kr[c] : T(0);
         C.wd[j] = v ? L.wd[c] : T(0);
+        C.me[j] = (c == 0) ? T(0) : T(1);
     }
 
     // Time segment and warm-up.
@@ -330,33 +351,35 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
 #pragma unroll
             for (int j = 0; j < K; ++j) x[j] = valid[j] ? x[j] : T(0);
         }
-        T xl = shfl_up1(x[K - 1]);
-        T xr = shfl_dn1(x[0]);
-
+        // S Jacobi steps, then (with a tail) the residual of the result; compiled
+        // twice, for the Dirichlet row 0 and for every other row.
+        T r[K];
+        auto sweeps = [&](auto dir_tag) {
+            constexpr bool DIR = decltype(dir_tag)::value;
 #pragma unroll
-        for (int k = 0; k < S; ++k) {
-            T y[K];
-            const T pl = shfl_up1(prev[k][K - 1]);
-            const T pr = shfl_dn1(prev[k][0]);
-            row_step<T, K, true>(L, C, col1_lane, dir_row, x, xl, xr, prev[k], pl, pr, bb, y);
+            for (int k = 0; k < S; ++k) {
+                T y[K];
+                row_step<T, K, true, DIR>(L, C, x, prev[k], bb, y);
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                prev[k][j] = x[j];
-                x[j] = y[j];
+                for (int j = 0; j < K; ++j) {
+                    prev[k][j] = x[j];
+                    x[j] = y[j];
+                }
             }
-            xl = shfl_up1(x[K - 1]);
-            xr = shfl_dn1(x[0]);
-        }
+            if constexpr (TAIL != TAIL_NONE) {
+                row_step<T, K, false, DIR>(L, C, x, prev[S], bb, r);
+#pragma unroll
+                for (int j = 0; j < K; ++j) prev[S][j] = x[j];
+            }
+        };
+        if (dir_row)
+            sweeps(std::true_type{});
+        else
+            sweeps(std::false_type{});
 
         if (out_row && useful && lane_in) st(a.out + (int64_t)n * P + g, x);
 
         if constexpr (TAIL != TAIL_NONE) {
-            T r[K];
-            const T pl = shfl_up1(prev[S][K - 1]);
-            const T pr = shfl_dn1(prev[S][0]);
-            row_step<T, K, false>(L, C, col1_lane, dir_row, x, xl, xr, prev[S], pl, pr, bb, r);
-#pragma unroll
-            for (int j = 0; j < K; ++j) prev[S][j] = x[j];
             if constexpr (TAIL == TAIL_RX) {
                 // coarse node I = (g + j)/2 for even j: r_{2I} + 1/2 (r_{2I-1} + r_{2I+1})
                 const T rl = shfl_up1(r[K - 1]);
@@ -466,8 +489,10 @@ Geometry geometry(int N, int Nt, int sweeps) {
     G.U = (kWave - 2 * G.HL) * K;
     G.xw = (N + 1 + G.U - 1) / G.U;
     const int64_t rows = Nt + 1;
-    // enough waves to keep every SIMD busy several times over
-    const int64_t target = STMG_TARGET_WAVES;
+    // Enough waves to keep every SIMD busy several times over.  Passes of four or
+    // more sweeps are bound by their arithmetic, not by memory latency: they get fewer,
+    // longer time segments, which cuts the recomputed warm-up rows.
+    const int64_t target = sweeps >= 4 ? STMG_TARGET_WAVES_ALU : STMG_TARGET_WAVES;
     int64_t seg = (rows * G.xw + target - 1) / target;
     const int64_t min_seg = STMG_MIN_SEGMENT;
     if (seg < min_seg) seg = min_seg;

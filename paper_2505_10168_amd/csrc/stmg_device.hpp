@@ -46,10 +46,13 @@ __device__ __forceinline__ float fmaT(float a, float b, float c) { return __buil
 //   sum_j (C/dt)_ij (x_{j,n} - x_{j,m}) + k_{i-1}/h (x_i - x_{i-1}) + k_i/h (x_i - x_{i+1})
 // which equals sum_j A_ij x_{j,n} - sum_j (C/dt)_ij x_{j,m} but keeps the large,
 // cancelling terms out of the rounding.  m = n-1 for J (coupled iff n >= 2) and
-// m = n+1 for J^T (coupled iff n < Nt); uncoupled rows use y = 0.  The caller passes
-// xm = ym = 0 at i = 1 (the column of node 0 is eliminated).
+// m = n+1 for J^T (coupled iff n < Nt); uncoupled rows use y = 0.
+// The left conductance term is formed as fma(nm, xm, x0): nm = -1 gives exactly
+// x0 - xm (one rounding of the exact difference), nm = 0 drops the left neighbour,
+// which is how i = 1 removes the eliminated column of node 0 (mlo[1] = 0 already
+// removes it from the mass term).
 template <typename T>
-__device__ __forceinline__ T stencil_interior(T mlo, T mdi, T mup, T kl, T kr,
+__device__ __forceinline__ T stencil_interior(T mlo, T mdi, T mup, T kl, T kr, T nm,
                                               T xm, T x0, T xp, bool coupled,
                                               T ym, T y0, T yp) {
     const T dm = coupled ? xm - ym : xm;
@@ -58,7 +61,7 @@ __device__ __forceinline__ T stencil_interior(T mlo, T mdi, T mup, T kl, T kr,
     T s = mdi * d0;
     s = fmaT(mlo, dm, s);
     s = fmaT(mup, dp, s);
-    s = fmaT(kl, x0 - xm, s);
+    s = fmaT(kl, fmaT(nm, xm, x0), s);
     s = fmaT(kr, x0 - xp, s);
     return s;
 }
