@@ -91,7 +91,10 @@ typedef struct {
     int32_t max_cycles;       /* stop after this many cycles (<= STMG_MAX_HISTORY)           */
     int32_t precision;        /* STMG_FP64 or STMG_MIXED                                      */
     double  w_diri_override;  /* > 0: use this W_Diri on every level; otherwise Appendix A    */
-    int32_t fused;            /* 1: fused streaming kernels; 0: one kernel per method step   */
+    int32_t fused;            /* 1: fused streaming kernels, and the smallest levels in one
+                                    single-workgroup launch with u, b in LDS; 2: fused streaming
+                                    kernels on every level; 0: one kernel per method step.
+                                    All three give bit-identical iterates.                     */
     int32_t time_kernels;     /* 1: time the fine-level fused passes with HIP events          */
 } stmg_options;
 
@@ -117,6 +120,8 @@ typedef struct {
     double  lambda_eff[64];          /* value that chose the direction leaving level l */
     char    path[64];                /* 'x' / 't' per coarsening step, NUL terminated  */
     size_t  device_bytes;            /* device memory held by the handle               */
+    int32_t tail_level;              /* first level of the single-workgroup V-cycle tail
+                                        (fused = 1), -1 when every level runs on its own */
 } stmg_info;
 
 typedef struct stmg_ctx* stmg_t;
@@ -184,7 +189,7 @@ int stmg_destroy(stmg_t h);
 int stmg_level_apply(stmg_t h, int level, int transpose, const double* d_x, double* d_y);
 
 /* nu damped-Jacobi steps u <- u + omega D^-1 (b - J u) in place (Section 3.1),
- * through the fused kernels when the handle has fused = 1. */
+ * through the fused kernels when the handle has fused = 1 or 2. */
 int stmg_level_smooth(stmg_t h, int level, int transpose, int nu, const double* d_b, double* d_u);
 
 /* b_c = R (b - J u) after nu pre-smoothing steps, i.e. lines "smooth" and

@@ -55,7 +55,7 @@ class stmg_info(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n_el", C.c_int32 * 64), ("n_t", C.c_int32 * 64),
                 ("h", C.c_double * 64), ("tau", C.c_double * 64), ("w_diri", C.c_double * 64),
                 ("lambda_eff", C.c_double * 64), ("path", C.c_char * 64),
-                ("device_bytes", C.c_size_t)]
+                ("device_bytes", C.c_size_t), ("tail_level", C.c_int32)]
 
 
 def _load():
@@ -311,7 +311,7 @@ class Solver:
         return {"n_levels": n, "n_el": list(i.n_el[:n]), "n_t": list(i.n_t[:n]),
                 "h": list(i.h[:n]), "tau": list(i.tau[:n]), "w_diri": list(i.w_diri[:n]),
                 "lambda_eff": list(i.lambda_eff[:max(n - 1, 0)]), "path": i.path.decode(),
-                "device_bytes": i.device_bytes}
+                "device_bytes": i.device_bytes, "tail_level": i.tail_level}
 
     def _new(self, shape=None):
         return self._torch.empty(shape or self.shape, dtype=self._torch.float64, device=self.device)

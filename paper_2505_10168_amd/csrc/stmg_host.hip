@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -59,6 +60,7 @@ struct Level {
     double* u = nullptr;
     double* b = nullptr;
     double* t = nullptr;
+    double* w = nullptr;     // fine level, pipelined solves: keeps the previous iterate
     float* u32 = nullptr;
     float* b32 = nullptr;
     float* t32 = nullptr;
@@ -137,12 +139,18 @@ struct stmg_ctx {
     size_t bytes = 0;
     KernelTimer timer;
     bool want_norm = false;      // fuse the residual norm into the fine post pass
+    int tail_start = -1;         // first level of the single-workgroup tail (-1: none)
+    bool rotate_in = false;      // the next fine pass keeps its input in L[0].w
+    hipEvent_t norm_ev[2] = {nullptr, nullptr};   // pipelined solve: residual of cycle k ready
+    int tail_lds = 0;            // its dynamic LDS bytes (FP64 vectors: an upper bound)
     int norm_parts = 0;          // partial count written by the last fused norm
 
     ~stmg_ctx() {
         for (void* q : allocs) (void)hipFree(q);
         if (hscal && hscal_pinned) (void)hipHostFree(hscal);
         else delete[] hscal;
+        for (hipEvent_t e : norm_ev)
+            if (e) (void)hipEventDestroy(e);
         for (auto& e : timer.ev) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
@@ -194,6 +202,7 @@ int validate(const stmg_problem* p, const stmg_options* o) {
     if (o->deff_mode < 0 || o->deff_mode > 1) return fail(STMG_EINVAL, "unknown deff_mode");
     if (o->precision != STMG_FP64 && o->precision != STMG_MIXED)
         return fail(STMG_EINVAL, "unknown precision");
+    if (o->fused < 0 || o->fused > 2) return fail(STMG_EINVAL, "fused must be 0, 1 or 2");
     if (!(o->tol > 0) || !(o->diverge > 0)) return fail(STMG_EINVAL, "tol and diverge must be > 0");
     return 0;
 }
@@ -202,13 +211,18 @@ bool can_x(int N) { return N % 2 == 0 && N >= 2; }
 bool can_t(int Nt) { return Nt % 2 == 0 && Nt >= 2; }
 
 // Bytes a level of (N, Nt) holds for the given precision and position.
-size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest) {
+// pipelined: the fine level of an FP64 handle with streaming kernels keeps a third
+// vector, so that one V-cycle can run while the previous one's residual is checked
+bool pipelined_options(const stmg_options* o) { return o->precision == STMG_FP64 && o->fused != 0; }
+
+size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest, bool pipelined) {
     const int64_t P = pitch_for(N), E = (int64_t)(Nt + 1) * P;
     size_t b = 3 * (size_t)N * 8 + kCoefArrays * (size_t)(N + 1) * 8;
     if (precision == STMG_MIXED) b += kCoefArrays * (size_t)(N + 1) * 4;
     if (coarsest) b += 3 * (size_t)(N + 1) * 8 + (N <= kDenseCoarsestMax ? (size_t)N * N * 8 : 0);
     if (precision == STMG_FP64 || fine) b += 3 * (size_t)E * 8;
     if (precision == STMG_MIXED) b += 3 * (size_t)E * 4;
+    if (fine && pipelined) b += (size_t)E * 8;
     return b;
 }
 
@@ -238,7 +252,7 @@ size_t footprint_of(const stmg_problem* p, const stmg_options* o) {
                 else if (want == 't' && !can_t(Nt)) want = can_x(N) ? 'x' : 0;
                 if (!want) last = true;
             }
-            total += level_bytes(N, Nt, o->precision, lev == 1, last);
+            total += level_bytes(N, Nt, o->precision, lev == 1, last, pipelined_options(o));
             if (last) break;
             if (want == 'x') { N /= 2; h *= 2; } else { Nt /= 2; tau *= 2; }
             ++lev;
@@ -256,7 +270,7 @@ size_t footprint_of(const stmg_problem* p, const stmg_options* o) {
         for (auto& f : frontier) {
             bool last = o->max_levels ? (lev == o->max_levels) : (dofs_of(f.N, f.Nt) <= o->min_coarse_dofs);
             if (!last && !can_x(f.N) && !can_t(f.Nt)) last = true;
-            worst = std::max(worst, level_bytes(f.N, f.Nt, o->precision, lev == 1, true));
+            worst = std::max(worst, level_bytes(f.N, f.Nt, o->precision, lev == 1, true, pipelined_options(o)));
             if (!last) {
                 any_continue = true;
                 if (can_x(f.N)) next.push_back({f.N / 2, f.Nt});
@@ -358,6 +372,41 @@ int finish_level(stmg_ctx* h, Level& l, bool coarsest) {
     return 0;
 }
 
+// The lowest levels that one workgroup solves with u and b in LDS: the longest chain
+// l_s .. coarsest (l_s >= 1) whose FP64 vectors fit the device's LDS per workgroup and
+// whose levels fit the kernel's thread mapping.  Sets tail_start = -1 when no chain
+// of at least two levels qualifies.
+void plan_tail(stmg_ctx* h) {
+    h->tail_start = -1;
+    const int nl = (int)h->L.size();
+    const Level& c = h->L[nl - 1];
+    if (nl < 3 || !c.ainv || c.N > kTailMaxCoarsestN) return;
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    int best = -1, best_bytes = 0;
+    for (int s0 = nl - 2; s0 >= 1 && nl - s0 <= kTailMaxLevels; --s0) {
+        const Level& l = h->L[s0];
+        if (tail_rows_per_owner(l.N, l.Nt) > kTailMaxRows) break;
+        int N[kTailMaxLevels], Nt[kTailMaxLevels];
+        for (int j = s0; j < nl; ++j) {
+            N[j - s0] = h->L[j].N;
+            Nt[j - s0] = h->L[j].Nt;
+        }
+        const int bytes = tail_lds_bytes<double>(N, Nt, nl - s0);
+        if (bytes > lds_max) break;
+        best = s0;
+        best_bytes = bytes;
+    }
+    if (best < 0) return;
+    if (tail_prepare<double>(best_bytes, c.N) != 0 || tail_prepare<float>(best_bytes, c.N) != 0) return;
+    h->tail_start = best;
+    h->tail_lds = best_bytes;
+}
+
 int build(stmg_ctx* h, const double* d_q) {
     const stmg_problem& p = h->p;
     Level f;
@@ -410,6 +459,7 @@ int build(stmg_ctx* h, const double* d_q) {
             CHK(h->alloc(&l.b, l.elems()));
             CHK(h->alloc(&l.t, l.elems()));
         }
+        if (fine && pipelined_options(&h->o)) CHK(h->alloc(&l.w, l.elems()));
         if (h->o.precision == STMG_MIXED) {
             CHK(h->alloc(&l.u32, l.elems()));
             CHK(h->alloc(&l.b32, l.elems()));
@@ -427,6 +477,7 @@ int build(stmg_ctx* h, const double* d_q) {
     need = std::max<int64_t>(need, (int64_t)gradient_chunks(fl.Nt) * fl.N);
     CHK(h->alloc(&h->parts, need));
     h->nparts = need;
+    plan_tail(h);
     HIPCHK(hipStreamSynchronize(h->s));
     return 0;
 }
@@ -496,6 +547,17 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
             timer_begin(h, timed);
             launch_fused<T>(V, fp, u, b, t, h->s);
             timer_end(h, timed, level_pass_bytes(lv, sizeof(T), !zero) + (lastc ? (double)cl.dofs() * sizeof(T) : 0.0));
+            if constexpr (std::is_same<T, double>::value) {
+                if (l == 0 && k == 0 && h->rotate_in) {
+                    // keep this cycle's input: (u, t, w) <- (t, w, u)
+                    T* in = u;
+                    u = t;
+                    t = lv.w;
+                    lv.w = in;
+                    zero = false;
+                    continue;
+                }
+            }
             std::swap(u, t);
             zero = false;
         }
@@ -570,10 +632,36 @@ int coarsest_solve(stmg_ctx* h, int l, int trans) {
     return 0;
 }
 
+// Levels l .. coarsest in one launch of the single-workgroup kernel (zero start).
+template <typename T>
+int tail_vcycle(stmg_ctx* h, int l, int trans) {
+    const int last = (int)h->L.size() - 1;
+    TailLaunch<T> t{};
+    t.nlev = last - l + 1;
+    for (int j = l; j <= last; ++j) {
+        t.V[j - l] = view<T>(h->L[j], h->o.omega);
+        t.dir[j - l] = h->L[j].dir;
+    }
+    t.nu = h->o.nu;
+    t.trans = trans;
+    t.lds_bytes = h->tail_lds;
+    t.Vc = view<double>(h->L[last], h->o.omega);
+    t.ainv = h->L[last].ainv;
+    t.b_in = B<T>(h->L[l]);
+    t.P_in = h->L[l].P;
+    t.u_out = U<T>(h->L[l]);
+    t.P_out = h->L[l].P;
+    if (launch_vcycle_tail<T>(t, h->s) != 0) return fail(STMG_EHIP, "V-cycle tail does not fit its kernel");
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
 template <typename T>
 int vcycle(stmg_ctx* h, int l, int trans, bool zero_start, bool norm) {
     const int last = (int)h->L.size() - 1;
     if (l == last) return coarsest_solve<T>(h, l, trans);
+    if (h->o.fused == 1 && l == h->tail_start && zero_start && !norm)
+        return tail_vcycle<T>(h, l, trans);
     CHK(pre_smooth_restrict<T>(h, l, trans, zero_start, h->o.nu));
     CHK(vcycle<T>(h, l + 1, trans, true, false));
     CHK(prolong_post_smooth<T>(h, l, trans, h->o.nu, norm));
@@ -657,6 +745,59 @@ int classify(const stmg_options& o, double r, bool* stop) {
     return STMG_NOT_CONVERGED;
 }
 
+// Residual norm^2 of the cycle just enqueued into device slot `slot`, copied to
+// pinned host memory, and the slot's event recorded; nothing waits.
+int post_norm_async(stmg_ctx* h, int slot) {
+    launch_reduce_final(h->parts, h->norm_parts, 1.0, h->dscal + 2 + slot, h->s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->hscal + 8 + slot, h->dscal + 2 + slot, sizeof(double),
+                          hipMemcpyDeviceToHost, h->s));
+    if (!h->norm_ev[slot]) HIPCHK(hipEventCreateWithFlags(&h->norm_ev[slot], hipEventDisableTiming));
+    HIPCHK(hipEventRecord(h->norm_ev[slot], h->s));
+    return 0;
+}
+
+// FP64 V-cycles with the termination test one cycle behind: cycle k+1 is enqueued
+// before the residual of cycle k is read, so the device never waits for the host.
+// Every cycle's first fine pass keeps its input (the previous result) in L[0].w; when
+// cycle k stops the iteration, the speculative cycle k+1 is discarded and u_k is
+// taken from w.  Iterates, residual history and cycle count are those of the plain
+// loop.
+int vcycles_pipelined(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* cycles,
+                      double* r_out, int* code) {
+    Level& f = h->L[0];
+    const int maxc = h->o.max_cycles;
+    auto enqueue = [&](int k) -> int {
+        CHK(vcycle<double>(h, 0, trans, false, true));
+        return post_norm_async(h, k & 1);
+    };
+    h->rotate_in = true;
+    int rc = enqueue(1);
+    int cyc = 1;
+    bool ahead = false, stop = false;
+    double r = 0;
+    while (rc == 0) {
+        ahead = cyc < maxc;
+        if (ahead && (rc = enqueue(cyc + 1)) != 0) break;
+        if (hipEventSynchronize(h->norm_ev[cyc & 1]) != hipSuccess) {
+            rc = fail(STMG_EHIP, "waiting for a V-cycle residual failed");
+            break;
+        }
+        r = std::sqrt(h->hscal[8 + (cyc & 1)]) / nb;
+        if (st) st->history[cyc] = r;
+        *code = classify(h->o, r, &stop);
+        if (stop || cyc == maxc) break;
+        ++cyc;
+    }
+    h->rotate_in = false;
+    if (hipStreamSynchronize(h->s) != hipSuccess && rc == 0) rc = fail(STMG_EHIP, "stream synchronisation failed");
+    if (rc != 0) return rc;
+    if (ahead) std::swap(f.u, f.w);   // the discarded cycle's input is the result
+    *cycles = cyc;
+    *r_out = r;
+    return 0;
+}
+
 int solve_fp64(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
     Level& f = h->L[0];
     double nb;
@@ -671,20 +812,25 @@ int solve_fp64(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
     bool stop = false;
     const bool timed = h->o.time_kernels != 0;
     const bool single = h->L.size() == 1;
-    for (cyc = 1; cyc <= h->o.max_cycles; ++cyc) {
-        CHK(vcycle<double>(h, 0, trans, false, true));
-        double ss;
-        if (single)
-            CHK(residual_norm64(h, trans, &ss));
-        else
-            CHK(finish_norm(h, h->norm_parts, &ss));
-        r = ss / nb;
+    if (!single && f.w && h->hscal_pinned) {
+        CHK(vcycles_pipelined(h, trans, nb, st, &cyc, &r, &code));
         if (timed) collect_timer(h, st);
-        if (st) st->history[cyc] = r;
-        code = classify(h->o, r, &stop);
-        if (stop) break;
+    } else {
+        for (cyc = 1; cyc <= h->o.max_cycles; ++cyc) {
+            CHK(vcycle<double>(h, 0, trans, false, true));
+            double ss;
+            if (single)
+                CHK(residual_norm64(h, trans, &ss));
+            else
+                CHK(finish_norm(h, h->norm_parts, &ss));
+            r = ss / nb;
+            if (timed) collect_timer(h, st);
+            if (st) st->history[cyc] = r;
+            code = classify(h->o, r, &stop);
+            if (stop) break;
+        }
+        if (cyc > h->o.max_cycles) cyc = h->o.max_cycles;
     }
-    if (cyc > h->o.max_cycles) cyc = h->o.max_cycles;
     if (st) {
         st->cycles = cyc;
         st->rel_residual = r;
@@ -988,6 +1134,7 @@ int stmg_get_info(stmg_t h, stmg_info* info) {
         if (i + 1 < h->L.size() && i < 63) info->path[i] = l.dir;
     }
     info->device_bytes = h->bytes;
+    info->tail_level = h->o.fused == 1 ? h->tail_start : -1;
     return 0;
 }
 

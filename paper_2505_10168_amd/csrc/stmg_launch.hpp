@@ -114,4 +114,40 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
 int fused_parts(int N, int Nt, int sweeps);
 int fused_max_sweeps();
 
+// ---- single-workgroup V-cycle tail (the smallest levels, resident in LDS) -----------
+constexpr int kTailThreads = 1024;     // one workgroup
+constexpr int kTailMaxLevels = 8;      // levels l_s .. coarsest
+#ifndef STMG_TAIL_MAX_ROWS
+#define STMG_TAIL_MAX_ROWS 4
+#endif
+constexpr int kTailMaxRows = STMG_TAIL_MAX_ROWS;   // time rows per thread and level
+constexpr int kTailMaxCoarsestN = 32;  // A^{-1} rows held in registers
+template <typename T>
+struct TailLaunch {
+    LevelView<T> V[kTailMaxLevels];    // index 0 = l_s, last = coarsest
+    int dir[kTailMaxLevels];           // 'x' / 't' towards the next level
+    int nlev;
+    int nu;
+    int trans;
+    int lds_bytes;                     // dynamic LDS made available by tail_prepare
+    LevelView<double> Vc;              // coarsest level, FP64 coefficients
+    const double* ainv;
+    const T* b_in;                     // restricted right-hand side of level l_s
+    int64_t P_in;
+    T* u_out;                          // its coarse-grid correction
+    int64_t P_out;
+};
+// time rows per thread on a level (it must not exceed kTailMaxRows)
+int tail_rows_per_owner(int N, int Nt);
+// LDS bytes of u and b of the given levels
+template <typename T>
+int tail_lds_bytes(const int* N, const int* Nt, int nlev);
+// allows lds_bytes of dynamic LDS for the kernels of a coarsest level with N nodes;
+// -1 when the device or the coarsest level does not allow it
+template <typename T>
+int tail_prepare(int lds_bytes, int coarsest_n);
+// -1 (nothing launched) when the levels do not fit the kernel's limits
+template <typename T>
+int launch_vcycle_tail(const TailLaunch<T>& t, hipStream_t s);
+
 }  // namespace stmg

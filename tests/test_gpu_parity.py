@@ -120,7 +120,7 @@ def test_coarsest_solve(name, transpose, cuda):
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("transpose", [0, 1])
-@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("fused", [1, 2, 0])
 def test_vcycle_iterates(name, transpose, fused, cuda):
     from paper_2505_10168_amd import binding as B
     s, _, lv, h = make_pair(name, cuda, fused=fused)
@@ -139,18 +139,31 @@ def test_vcycle_iterates(name, transpose, fused, cuda):
         assert r_gpu == pytest.approx(r_ref, rel=1e-9, abs=1e-15)
 
 
+# first level of the single-workgroup tail with fused = 1 (the coarsest level of
+# ramp_300x256 has 75 elements, beyond the tail kernel's dense solve)
+TAIL_LEVEL = {"uniform_64x64": 1, "block_256x600": 6, "ramp_300x256": -1}
+
+
 @pytest.mark.parametrize("name", list(CASES))
-def test_fused_and_reference_paths_identical(name, cuda):
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_fused_and_reference_paths_identical(name, transpose, cuda):
+    """Streaming kernels with the LDS tail (1), streaming kernels on every level (2)
+    and one kernel per step (0) give the same bits."""
     from paper_2505_10168_amd import binding as B
     outs = []
-    for fused in (1, 0):
+    for fused in (1, 2, 0):
         s, _, lv, h = make_pair(name, cuda, fused=fused)
-        bd = to_dev(O.load_vector(lv, 1.0), cuda)
+        assert s.info()["tail_level"] == (TAIL_LEVEL[name] if fused == 1 else -1)
+        b = O.load_vector(lv, 1.0)
+        if transpose:
+            b = O.adjoint_rhs(lv, b)
+        bd = to_dev(b, cuda)
         ud = to_dev(np.zeros(lv.shape), cuda)
         for _ in range(3):
-            B.stmg_vcycle(s.handle, 0, bd, ud)
+            B.stmg_vcycle(s.handle, transpose, bd, ud)
         outs.append(to_np(ud))
-    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+    assert np.array_equal(outs[1], outs[2])
 
 
 def test_solve_uniform_64x64_matches_oracle(cuda):
