@@ -44,7 +44,7 @@ constexpr int kWavesPerBlock = 4;
 #define STMG_TARGET_WAVES_ALU 3072
 #endif
 #ifndef STMG_MIN_SEGMENT
-#define STMG_MIN_SEGMENT 4
+#define STMG_MIN_SEGMENT 2
 #endif
 constexpr int PF = STMG_PREFETCH_ROWS;   // rows in flight per wave (register prefetch ring)
 constexpr int kXcds = 8;     // accelerator complex dies of an MI355X
