@@ -197,7 +197,8 @@ __device__ __forceinline__ void row_step(const LevelView<T>& L, const LaneCoef<T
     }
 }
 
-template <typename T, int TR, int S, int TAIL, bool HASZ>
+// HEAD: 0 none, 1 x prolongation, 2 t prolongation, 3 defect correction u += s e.
+template <typename T, int TR, int S, int TAIL, int HEAD>
 __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArgs<T>& a) {
     constexpr int K = Lanes<T>::K;
     constexpr int KH = K / 2;
@@ -263,7 +264,9 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
 
     // Row buffers: rows are fetched PF steps ahead of use (a register ring that the
     // unrolled inner loop indexes statically).
-    constexpr int KZ = HASZ ? K : 1;
+    constexpr bool HASZ = HEAD != 0;
+    // coarse values per lane and row: K/2 for the x prolongation, K otherwise
+    constexpr int KZ = HEAD == 1 ? KH : (HASZ ? K : 1);
     T ru[PF][K], rb[PF][K], rz[PF][KZ];
     auto fetch = [&](int n, T (&fu)[K], T (&fb)[K], T (&fz)[KZ]) {
 #pragma unroll
@@ -277,21 +280,14 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
         const int64_t ro = (int64_t)n * P + g;
         if (!a.zero_in) ld(a.u + ro, fu);
         if (need_b) ld(a.b + ro, fb);
-        if constexpr (HASZ) {
-            if (a.head == 1) {
-                T zh[KH];
-                ldh(a.z + (int64_t)n * a.Pz + (g >> 1), zh);
-#pragma unroll
-                for (int j = 0; j < KH; ++j) fz[j] = zh[j];
-            } else if (a.head == 2) {
-                ld(a.z + (int64_t)(n >> 1) * a.Pz + g, fz);
-            } else if constexpr (std::is_same<T, double>::value) {
-                if (a.head == 3) {
-                    const float2 e = *reinterpret_cast<const float2*>(a.e32 + ro);
-                    fz[0] = (T)e.x;
-                    fz[1] = (T)e.y;
-                }
-            }
+        if constexpr (HEAD == 1) {
+            ldh(a.z + (int64_t)n * a.Pz + (g >> 1), fz);
+        } else if constexpr (HEAD == 2) {
+            ld(a.z + (int64_t)(n >> 1) * a.Pz + g, fz);
+        } else if constexpr (HEAD == 3 && std::is_same<T, double>::value) {
+            const float2 e = *reinterpret_cast<const float2*>(a.e32 + ro);
+            fz[0] = (T)e.x;
+            fz[1] = (T)e.y;
         }
     };
     auto row_of = [&](int it) { return TR ? first - it : first + it; };
@@ -305,13 +301,14 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
         const int it = it0 + d;
         if (it >= count) break;
         const int n = row_of(it);
-        T x[K], bb[K], zz[K];
+        T x[K], bb[K], zz[KZ];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             x[j] = ru[d][j];
             bb[j] = rb[d][j];
-            zz[j] = (HASZ && j < KZ) ? rz[d][j < KZ ? j : 0] : T(0);
         }
+#pragma unroll
+        for (int j = 0; j < KZ; ++j) zz[j] = rz[d][j];
         if (it + PF < count) fetch(row_of(it + PF), ru[d], rb[d], rz[d]);
         const bool out_row = (n >= n0) && (n < n1);
         const bool dir_row = (n == 0);
@@ -325,8 +322,7 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
         }
 
         // Prolongation head: x += P z.
-        if (!HASZ) {
-        } else if (a.head == 1) {
+        if constexpr (HEAD == 1) {
             const T znext = shfl_dn1(zz[0]);   // first coarse value of the next lane
 #pragma unroll
             for (int j = 0; j < K; ++j) {
@@ -334,14 +330,14 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
                 if ((j & 1) == 0) {
                     x[j] += za;
                 } else {
-                    const T zb = ((j >> 1) + 1 < KH) ? zz[(j >> 1) + 1] : znext;
+                    const T zb = ((j >> 1) + 1 < KH) ? zz[((j >> 1) + 1) % KZ] : znext;
                     x[j] = fmaT(T(0.5), za + zb, x[j]);
                 }
             }
-        } else if (a.head == 2) {
+        } else if constexpr (HEAD == 2) {
 #pragma unroll
             for (int j = 0; j < K; ++j) x[j] += zz[j];
-        } else if (a.head == 3) {
+        } else if constexpr (HEAD == 3) {
 #pragma unroll
             for (int j = 0; j < K; ++j) x[j] = fmaT((T)a.s_old, zz[j], x[j]);
         }
@@ -463,13 +459,13 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
 
 // Two entry points with the same body: the finest level gets its own symbol so that
 // profiles attribute the dominant passes separately from the coarse levels.
-template <typename T, int TR, int S, int TAIL, bool HASZ>
+template <typename T, int TR, int S, int TAIL, int HEAD>
 __global__ __launch_bounds__(256) void k_fused(LevelView<T> L, FusedArgs<T> a) {
-    fused_body<T, TR, S, TAIL, HASZ>(L, a);
+    fused_body<T, TR, S, TAIL, HEAD>(L, a);
 }
-template <typename T, int TR, int S, int TAIL, bool HASZ>
+template <typename T, int TR, int S, int TAIL, int HEAD>
 __global__ __launch_bounds__(256) void k_fused_fine(LevelView<T> L, FusedArgs<T> a) {
-    fused_body<T, TR, S, TAIL, HASZ>(L, a);
+    fused_body<T, TR, S, TAIL, HEAD>(L, a);
 }
 
 struct Geometry {
@@ -503,14 +499,14 @@ Geometry geometry(int N, int Nt, int sweeps) {
     return G;
 }
 
-template <typename T, int TR, int S, int TAIL, bool HASZ>
+template <typename T, int TR, int S, int TAIL, int HEAD>
 void launch_one(const LevelView<T>& L, const FusedArgs<T>& a, bool fine, hipStream_t s) {
     const int blocks = (a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
     if (fine)
-        hipLaunchKernelGGL((k_fused_fine<T, TR, S, TAIL, HASZ>), dim3(blocks),
+        hipLaunchKernelGGL((k_fused_fine<T, TR, S, TAIL, HEAD>), dim3(blocks),
                            dim3(kWave * kWavesPerBlock), 0, s, L, a);
     else
-        hipLaunchKernelGGL((k_fused<T, TR, S, TAIL, HASZ>), dim3(blocks),
+        hipLaunchKernelGGL((k_fused<T, TR, S, TAIL, HEAD>), dim3(blocks),
                            dim3(kWave * kWavesPerBlock), 0, s, L, a);
 }
 
@@ -519,18 +515,25 @@ void launch_one(const LevelView<T>& L, const FusedArgs<T>& a, bool fine, hipStre
 template <typename T, int TR, int S>
 void dispatch_tail(int tail, const LevelView<T>& L, const FusedArgs<T>& a, bool fine,
                    hipStream_t s) {
-    if (a.head != 0) {
+    if (a.head == 1) {
         if (tail == TAIL_NORM)
-            launch_one<T, TR, S, TAIL_NORM, true>(L, a, fine, s);
+            launch_one<T, TR, S, TAIL_NORM, 1>(L, a, fine, s);
         else
-            launch_one<T, TR, S, TAIL_NONE, true>(L, a, fine, s);
+            launch_one<T, TR, S, TAIL_NONE, 1>(L, a, fine, s);
+        return;
+    }
+    if (a.head == 2) {
+        if (tail == TAIL_NORM)
+            launch_one<T, TR, S, TAIL_NORM, 2>(L, a, fine, s);
+        else
+            launch_one<T, TR, S, TAIL_NONE, 2>(L, a, fine, s);
         return;
     }
     switch (tail) {
-        case TAIL_NONE: launch_one<T, TR, S, TAIL_NONE, false>(L, a, fine, s); break;
-        case TAIL_RX: launch_one<T, TR, S, TAIL_RX, false>(L, a, fine, s); break;
-        case TAIL_RT: launch_one<T, TR, S, TAIL_RT, false>(L, a, fine, s); break;
-        default: launch_one<T, TR, S, TAIL_NORM, false>(L, a, fine, s); break;
+        case TAIL_NONE: launch_one<T, TR, S, TAIL_NONE, 0>(L, a, fine, s); break;
+        case TAIL_RX: launch_one<T, TR, S, TAIL_RX, 0>(L, a, fine, s); break;
+        case TAIL_RT: launch_one<T, TR, S, TAIL_RT, 0>(L, a, fine, s); break;
+        default: launch_one<T, TR, S, TAIL_NORM, 0>(L, a, fine, s); break;
     }
 }
 
@@ -589,9 +592,9 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
         if constexpr (std::is_same<T, double>::value) {
             if (fp.sweeps != 0 || fp.tail != 'c' || fp.prolong != 'c') return -1;
             if (fp.trans)
-                launch_one<T, 1, 0, TAIL_DEFECT, true>(L, a, fp.fine != 0, s);
+                launch_one<T, 1, 0, TAIL_DEFECT, 3>(L, a, fp.fine != 0, s);
             else
-                launch_one<T, 0, 0, TAIL_DEFECT, true>(L, a, fp.fine != 0, s);
+                launch_one<T, 0, 0, TAIL_DEFECT, 3>(L, a, fp.fine != 0, s);
             return G.nwaves;
         } else {
             return -1;
