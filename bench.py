@@ -54,6 +54,26 @@ def measured_traffic(workload: str):
     return entry["bytes_per_launch"] if entry else None
 
 
+def copy_peak_gbs(dev, nbytes: int = 2 << 30, reps: int = 5) -> float:
+    """Device-to-device copy rate of a 2 GiB FP64 buffer, (read + write bytes) / time:
+    the streaming rate this device sustains in practice, reported beside the spec peak."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else float("nan")
 
@@ -248,6 +268,7 @@ def main():
     launches = sum(s.fine_kernel_launches for s in solves)
     achieved = kern_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
     bad = [s.status for s in solves if s.status != 0]
+    copy_gbs = copy_peak_gbs(dev)
 
     out = {
         "metric": METRIC,
@@ -290,6 +311,8 @@ def main():
             "launches": launches,
             "avg_launch_us": 1e3 * kern_ms / launches if launches else None,
             "bytes_per_launch": kern_bytes / launches if launches else None,
+            "copy_GBs": copy_gbs,
+            "copy_frac": (achieved / copy_gbs) if achieved else None,
         },
     }
     if not args.no_cpu:

@@ -194,3 +194,30 @@ def test_solve_matches_oracle(name, transpose, cuda):
     assert st.cycles == ref.cycles
     assert {0: "converged", 1: "max_cycles", 2: "diverged"}[st.status] == ref.status
     assert rel(to_np(lam), ref.u) <= 1e-12
+
+
+@pytest.mark.parametrize("name,max_cycles", [("block_256x600", 3), ("uniform_64x64", 3),
+                                             ("uniform_64x64", 100)])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_pipelined_solve_returns_its_last_iterate(name, max_cycles, transpose, cuda):
+    """The FP64 solve enqueues V-cycle k+1 before it tests cycle k.  It must return the
+    k-th iterate exactly, both when the cycle cap ends it (no cycle runs ahead) and when
+    the tolerance does (uniform_64x64 converges in 13 cycles; the cycle that ran ahead is
+    discarded), with the residual history of those iterates."""
+    from paper_2505_10168_amd import binding as B
+    s, _, lv, h = make_pair(name, cuda, max_cycles=max_cycles)
+    b = O.load_vector(lv, 1.0)
+    if transpose:
+        b = O.adjoint_rhs(lv, b)
+    bd = to_dev(b, cuda)
+    solve = s.solve_adjoint if transpose else s.solve_forward
+    u, st = solve(rhs=bd)
+    if max_cycles == 3:
+        assert st.status == B.STMG_NOT_CONVERGED and st.cycles == 3
+    else:
+        assert st.status == B.STMG_OK and st.cycles < max_cycles
+    ref = to_dev(np.zeros(lv.shape), cuda)
+    for k in range(st.cycles):
+        r = B.stmg_vcycle(s.handle, transpose, bd, ref)
+        assert st.history[k + 1] == pytest.approx(r, rel=1e-9)
+    assert np.array_equal(to_np(u), to_np(ref))
