@@ -37,6 +37,11 @@ WORKLOADS = {
 }
 
 
+# The fine passes of every TIMED_EVERY-th V-cycle are bracketed by HIP events: enough
+# launches for the average, without an event marker between every pair of kernels.
+TIMED_EVERY = 8
+
+
 def measured_traffic(workload: str):
     """Per-launch HBM bytes of the fine-level passes from the committed counter runs,
     or None when the kernel sources changed since they were taken."""
@@ -232,7 +237,8 @@ def main():
     precision = B.STMG_MIXED if args.precision == "mixed" else B.STMG_FP64
     prob = B.Problem(w.n_el, w.n_t, w.length, w.t_final, k_ins=w.kappa_min)
     rho = torch.from_numpy(w.rho).to(dev)
-    solver = B.Solver(prob, rho, nu=nu, precision=precision, fused=args.fused, time_kernels=1)
+    solver = B.Solver(prob, rho, nu=nu, precision=precision, fused=args.fused,
+                      time_kernels=TIMED_EVERY)
     info = solver.info()
     u = solver._new()
     lam = solver._new()
@@ -311,6 +317,7 @@ def main():
             "launches": launches,
             "avg_launch_us": 1e3 * kern_ms / launches if launches else None,
             "bytes_per_launch": kern_bytes / launches if launches else None,
+            "timed_every_nth_cycle": TIMED_EVERY,
             "copy_GBs": copy_gbs,
             "copy_frac": (achieved / copy_gbs) if achieved else None,
         },

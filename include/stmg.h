@@ -95,7 +95,8 @@ typedef struct {
                                     single-workgroup launch with u, b in LDS; 2: fused streaming
                                     kernels on every level; 0: one kernel per method step.
                                     All three give bit-identical iterates.                     */
-    int32_t time_kernels;     /* 1: time the fine-level fused passes with HIP events          */
+    int32_t time_kernels;     /* k > 0: time the fine-level fused passes of every k-th V-cycle
+                                    with HIP events (1: all of them); 0: no timing            */
 } stmg_options;
 
 typedef struct {

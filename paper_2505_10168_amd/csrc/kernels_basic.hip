@@ -613,6 +613,26 @@ void launch_reduce_final(const double* parts, int n, double scale, double* out, 
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, s, parts, n, scale, out);
 }
 
+// The same sum, written to pinned host memory: host[0] = scale * sum, then (after a
+// system-scope fence) host[1] = tag, so a host that sees the tag sees the value.
+__global__ void k_reduce_to_host(const double* __restrict__ parts, int n, double scale,
+                                 double* host, double tag) {
+    __shared__ double sh[1024];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += parts[i];
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        *reinterpret_cast<volatile double*>(host) = scale * s;
+        __threadfence_system();
+        *reinterpret_cast<volatile double*>(host + 1) = tag;
+    }
+}
+
+void launch_reduce_to_host(const double* parts, int n, double scale, double* host, double tag,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_to_host, dim3(1), dim3(1024), 0, s, parts, n, scale, host, tag);
+}
+
 template <typename T, int TR>
 __global__ void k_residual_sumsq(LevelView<T> L, const T* __restrict__ u, const T* __restrict__ b,
                                  double* __restrict__ parts) {

@@ -46,7 +46,7 @@ constexpr int kWavesPerBlock = 4;
 #ifndef STMG_MIN_SEGMENT
 #define STMG_MIN_SEGMENT 2
 #endif
-constexpr int PF = STMG_PREFETCH_ROWS;   // rows in flight per wave (register prefetch ring)
+constexpr int kPrefetchRows = STMG_PREFETCH_ROWS;   // rows in flight per wave (register ring)
 constexpr int kXcds = 8;     // accelerator complex dies of an MI355X
 constexpr int kMaxFused = 6; // Jacobi steps one pass can fuse
 
@@ -197,21 +197,27 @@ __device__ __forceinline__ void row_step(const LevelView<T>& L, const LaneCoef<T
     }
 }
 
-// HEAD: 0 none, 1 x prolongation, 2 t prolongation, 3 defect correction u += s e.
-template <typename T, int TR, int S, int TAIL, int HEAD>
-__device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArgs<T>& a) {
-    constexpr int K = Lanes<T>::K;
-    constexpr int KH = K / 2;
-    const int lane = threadIdx.x & (kWave - 1);
-    // Workgroups are dealt to the 8 XCDs round robin; renumber them so that each XCD
-    // gets a contiguous range of strips and time segments, whose shared halo columns
-    // and warm-up rows then hit the same L2.
+// Wave index of a multi-workgroup launch.  Workgroups are dealt to the 8 XCDs round
+// robin; renumber them so that each XCD gets a contiguous range of strips and time
+// segments, whose shared halo columns and warm-up rows then hit the same L2.
+// Wave-uniform by construction; readfirstlane lets the compiler know it, so that the
+// per-row tests of the pass are scalar branches.
+__device__ __forceinline__ int grid_wave() {
     const int nb = gridDim.x, q = nb / kXcds, r = nb % kXcds;
     const int xcd = blockIdx.x % kXcds, idx = blockIdx.x / kXcds;
     const int lb = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-    // wave-uniform by construction; readfirstlane lets the compiler know it, so that
-    // the per-row tests below are scalar branches
-    const int wave = __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (threadIdx.x >> 6));
+    return __builtin_amdgcn_readfirstlane(lb * kWavesPerBlock + (threadIdx.x >> 6));
+}
+
+// One fused pass as executed by wave `wave` of the a.nwaves waves of the pass.
+// HEAD: 0 none, 1 x prolongation, 2 t prolongation, 3 defect correction u += s e.
+// PF: rows in flight per wave (register prefetch ring).
+template <typename T, int TR, int S, int TAIL, int HEAD, int PF = kPrefetchRows>
+__device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArgs<T>& a,
+                                           const int wave) {
+    constexpr int K = Lanes<T>::K;
+    constexpr int KH = K / 2;
+    const int lane = threadIdx.x & (kWave - 1);
     if (wave >= a.nwaves) return;
     const int HL = a.HL;
     const int U = (kWave - 2 * HL) * K;
@@ -461,11 +467,11 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
 // profiles attribute the dominant passes separately from the coarse levels.
 template <typename T, int TR, int S, int TAIL, int HEAD>
 __global__ __launch_bounds__(256) void k_fused(LevelView<T> L, FusedArgs<T> a) {
-    fused_body<T, TR, S, TAIL, HEAD>(L, a);
+    fused_body<T, TR, S, TAIL, HEAD>(L, a, grid_wave());
 }
 template <typename T, int TR, int S, int TAIL, int HEAD>
 __global__ __launch_bounds__(256) void k_fused_fine(LevelView<T> L, FusedArgs<T> a) {
-    fused_body<T, TR, S, TAIL, HEAD>(L, a);
+    fused_body<T, TR, S, TAIL, HEAD>(L, a, grid_wave());
 }
 
 struct Geometry {

@@ -10,6 +10,7 @@
 #include <string>
 #include <type_traits>
 #include <utility>
+#include <atomic>
 #include <vector>
 
 #include "stmg.h"
@@ -141,7 +142,7 @@ struct stmg_ctx {
     bool want_norm = false;      // fuse the residual norm into the fine post pass
     int tail_start = -1;         // first level of the single-workgroup tail (-1: none)
     bool rotate_in = false;      // the next fine pass keeps its input in L[0].w
-    hipEvent_t norm_ev[2] = {nullptr, nullptr};   // pipelined solve: residual of cycle k ready
+    uint64_t vcycles = 0;        // fine-level V-cycles started (sampled kernel timing)
     int tail_lds = 0;            // its dynamic LDS bytes (FP64 vectors: an upper bound)
     int norm_parts = 0;          // partial count written by the last fused norm
 
@@ -149,8 +150,6 @@ struct stmg_ctx {
         for (void* q : allocs) (void)hipFree(q);
         if (hscal && hscal_pinned) (void)hipHostFree(hscal);
         else delete[] hscal;
-        for (hipEvent_t e : norm_ev)
-            if (e) (void)hipEventDestroy(e);
         for (auto& e : timer.ev) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
@@ -203,6 +202,7 @@ int validate(const stmg_problem* p, const stmg_options* o) {
     if (o->precision != STMG_FP64 && o->precision != STMG_MIXED)
         return fail(STMG_EINVAL, "unknown precision");
     if (o->fused < 0 || o->fused > 2) return fail(STMG_EINVAL, "fused must be 0, 1 or 2");
+    if (o->time_kernels < 0) return fail(STMG_EINVAL, "time_kernels must be >= 0");
     if (!(o->tol > 0) || !(o->diverge > 0)) return fail(STMG_EINVAL, "tol and diverge must be > 0");
     return 0;
 }
@@ -528,7 +528,7 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
     T*& u = U<T>(lv);
     T* b = B<T>(lv);
     T*& t = Tt<T>(lv);
-    const bool timed = h->o.time_kernels && l == 0;
+    const bool timed = l == 0 && h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
     if (h->o.fused) {
         std::vector<int> ch = chunks_of(nu);
         bool zero = zero_start;
@@ -583,7 +583,7 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
     T* b = B<T>(lv);
     T*& t = Tt<T>(lv);
     const T* z = U<T>(cl);
-    const bool timed = h->o.time_kernels && l == 0;
+    const bool timed = l == 0 && h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
     if (h->o.fused) {
         std::vector<int> ch = chunks_of(nu);
         for (size_t k = 0; k < ch.size(); ++k) {
@@ -665,6 +665,7 @@ int vcycle(stmg_ctx* h, int l, int trans, bool zero_start, bool norm) {
     CHK(pre_smooth_restrict<T>(h, l, trans, zero_start, h->o.nu));
     CHK(vcycle<T>(h, l + 1, trans, true, false));
     CHK(prolong_post_smooth<T>(h, l, trans, h->o.nu, norm));
+    if (l == 0) ++h->vcycles;
     return 0;
 }
 
@@ -745,15 +746,37 @@ int classify(const stmg_options& o, double r, bool* stop) {
     return STMG_NOT_CONVERGED;
 }
 
-// Residual norm^2 of the cycle just enqueued into device slot `slot`, copied to
-// pinned host memory, and the slot's event recorded; nothing waits.
-int post_norm_async(stmg_ctx* h, int slot) {
-    launch_reduce_final(h->parts, h->norm_parts, 1.0, h->dscal + 2 + slot, h->s);
+// Residual norm^2 of the cycle just enqueued, reduced straight into slot `slot` of the
+// pinned host scalars (value at hscal[8 + 2 slot], then the tag at hscal[9 + 2 slot]);
+// nothing waits.  Tags come from one process-wide counter: pinned blocks are recycled
+// between handles with their old contents, so a per-handle count could find a stale
+// slot already carrying the tag it waits for.
+std::atomic<uint64_t> g_norm_tag{0};
+
+int post_norm_async(stmg_ctx* h, int slot, double* tag) {
+    *tag = (double)++g_norm_tag;
+    launch_reduce_to_host(h->parts, h->norm_parts, 1.0, h->hscal + 8 + 2 * slot, *tag, h->s);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(h->hscal + 8 + slot, h->dscal + 2 + slot, sizeof(double),
-                          hipMemcpyDeviceToHost, h->s));
-    if (!h->norm_ev[slot]) HIPCHK(hipEventCreateWithFlags(&h->norm_ev[slot], hipEventDisableTiming));
-    HIPCHK(hipEventRecord(h->norm_ev[slot], h->s));
+    return 0;
+}
+
+// Wait (spinning) until slot `slot` carries `tag`, then read its value.  Gives up with
+// an error when the stream fails, or finishes without having written the tag.
+int wait_norm(stmg_ctx* h, int slot, double tag, double* out) {
+    volatile double* v = h->hscal + 8 + 2 * slot;
+    for (unsigned long spins = 1; v[1] != tag; ++spins) {
+        __builtin_ia32_pause();
+        if ((spins & 4095) != 0) continue;
+        const hipError_t e = hipStreamQuery(h->s);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(STMG_EHIP, "V-cycle stream failed while waiting for its residual");
+        }
+        if (v[1] != tag) return fail(STMG_EHIP, "V-cycle residual was not delivered");
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    *out = v[0];
     return 0;
 }
 
@@ -767,9 +790,10 @@ int vcycles_pipelined(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* cy
                       double* r_out, int* code) {
     Level& f = h->L[0];
     const int maxc = h->o.max_cycles;
+    double tags[2] = {0, 0};
     auto enqueue = [&](int k) -> int {
         CHK(vcycle<double>(h, 0, trans, false, true));
-        return post_norm_async(h, k & 1);
+        return post_norm_async(h, k & 1, &tags[k & 1]);
     };
     h->rotate_in = true;
     int rc = enqueue(1);
@@ -779,11 +803,9 @@ int vcycles_pipelined(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* cy
     while (rc == 0) {
         ahead = cyc < maxc;
         if (ahead && (rc = enqueue(cyc + 1)) != 0) break;
-        if (hipEventSynchronize(h->norm_ev[cyc & 1]) != hipSuccess) {
-            rc = fail(STMG_EHIP, "waiting for a V-cycle residual failed");
-            break;
-        }
-        r = std::sqrt(h->hscal[8 + (cyc & 1)]) / nb;
+        double ss = 0;
+        if ((rc = wait_norm(h, cyc & 1, tags[cyc & 1], &ss)) != 0) break;
+        r = std::sqrt(ss) / nb;
         if (st) st->history[cyc] = r;
         *code = classify(h->o, r, &stop);
         if (stop || cyc == maxc) break;
@@ -863,7 +885,7 @@ int defect_step(stmg_ctx* h, int trans, double s_e, double s_f, double* norm) {
         fp.inv_s_new = inv;
         fp.parts = h->parts;
         fp.fine = 1;
-        const bool timed = h->o.time_kernels != 0;
+        const bool timed = h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
         timer_begin(h, timed);
         const int nw = launch_fused<double>(V64, fp, f.u, f.b, f.t, h->s);
         // u, e, b read; u, f written
@@ -1042,6 +1064,7 @@ int stmg_create(stmg_t* handle, const stmg_problem* p, const stmg_options* o,
             h->hscal = new double[64];
             h->hscal_pinned = false;
         }
+        std::memset(h->hscal, 0, 64 * sizeof(double));   // no tag is 0
         if ((rc = h->alloc(&h->rho, p->n_el)) < 0) break;
         if ((rc = h->alloc(&h->kp, p->n_el)) < 0) break;
         if ((rc = h->alloc(&h->cpd, p->n_el)) < 0) break;

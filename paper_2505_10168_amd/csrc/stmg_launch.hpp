@@ -73,6 +73,9 @@ void launch_dot_partial(const double* a, const double* b, int rows, int cols, in
                         int64_t Pb, double* parts, hipStream_t s);
 // out[0] = scale * sum(parts[0..n))
 void launch_reduce_final(const double* parts, int n, double scale, double* out, hipStream_t s);
+// host[0] = scale * sum(parts[0..n)), then host[1] = tag; host is pinned host memory
+void launch_reduce_to_host(const double* parts, int n, double scale, double* host, double tag,
+                           hipStream_t s);
 // residual norm^2 of the fine level, one-thread-per-DOF: parts from b - J u
 template <typename T>
 void launch_residual_sumsq_partial(const LevelView<T>& L, int trans, const T* u, const T* b,
