@@ -54,24 +54,34 @@ struct Owner {
     int i, n0, M;
     bool act;
 };
-__device__ __forceinline__ int rows_per_owner(int W, int Nt) {
+// M: rows per thread; even when the level restricts in t, so that a time pair
+// (2J, 2J+1) stays with one thread.
+__device__ __forceinline__ int rows_per_owner(int W, int Nt, bool even) {
     const int R = kTailThreads / W;
     const int M = (Nt + 1 + R - 1) / R;
-    return M + (M & 1);
+    return even ? M + (M & 1) : M;
 }
-__device__ __forceinline__ Owner owner_of(int W, int Nt) {
+__device__ __forceinline__ Owner owner_of(int W, int Nt, bool even) {
     Owner o;
-    o.M = rows_per_owner(W, Nt);
+    o.M = rows_per_owner(W, Nt, even);
     o.i = threadIdx.x % W;
     const int g = threadIdx.x / W;
     o.n0 = g * o.M;
     o.act = g < kTailThreads / W && o.n0 <= Nt;
     return o;
 }
+// Time level of owned row k.  For J the rows run forward from n0; for J^T backward from
+// n0 + M - 1.  Either way the row row k is coupled to is owned row k - 1, and for k = 0
+// the row outside the block.
+template <int TR>
+__device__ __forceinline__ int row_of(const Owner& o, int k) {
+    return TR ? o.n0 + o.M - 1 - k : o.n0 + k;
+}
 
 template <typename T>
 struct ColCoef {
     T mlo, mdi, mup, kl, kr, wd;
+    T nm;   // multiplier of the left neighbour: 0 at nodes 0 and 1, -1 elsewhere
 };
 template <typename T>
 __device__ __forceinline__ ColCoef<T> col_coef(const LevelView<T>& V, int i) {
@@ -82,18 +92,21 @@ __device__ __forceinline__ ColCoef<T> col_coef(const LevelView<T>& V, int i) {
     c.kl = V.kl[i];
     c.kr = V.kr[i];
     c.wd = V.wd[i];
+    c.nm = i <= 1 ? T(0) : T(-1);
     return c;
 }
 
 // One damped Jacobi step (JAC) or the residual r = b - J x (!JAC) of the owned DOFs,
 // in place in x.  bb: the owned b; u: the level's current iterate in LDS (row pitch
-// W), which holds the same values as x for the owned DOFs.  The neighbour columns of
-// the owned rows and the coupled row outside the block are loaded unconditionally
-// (rows clamped into range) and the boundary cases selected afterwards, so that each
-// value gets exactly the operands k_apply gives it.  Rows are visited against the
-// direction of the time coupling (J: last to first; J^T: first to last), so the
-// coupled row of the owner is still at its old value when it is read.  Rows beyond
-// Nt produce values that are never stored.
+// W), which holds the same values as x for the owned DOFs.  Neighbour columns are
+// loaded unconditionally (clamped into range) and need no boundary selects: node 1
+// drops its eliminated left neighbour through nm, node N has zero right coefficients,
+// and node 0 (Dirichlet) is expressed through its coefficients (kl = W_Diri,
+// wd = omega / W_Diri, the rest 0, nm = 0), exactly as the fused kernels do.  An
+// uncoupled row forms its differences as fma(0, y, x) = x.  Each rounded operation
+// has the operands k_apply gives it.  Rows are visited from k = M-1 down to 0, so the
+// coupled row k-1 is still at its old value when read.  Rows beyond Nt produce values
+// that are never stored.
 template <typename T, int TR, bool JAC>
 __device__ __forceinline__ void owned_step(const LevelView<T>& V, const ColCoef<T>& c,
                                            const Owner& o, const T* u, T (&x)[kTailMaxRows],
@@ -104,7 +117,7 @@ __device__ __forceinline__ void owned_step(const LevelView<T>& V, const ColCoef<
 #pragma unroll
     for (int k = 0; k < kTailMaxRows; ++k) {
         if (k < M) {
-            const int n = min(o.n0 + k, Nt);
+            const int n = min(row_of<TR>(o, k), Nt);
             XM[k] = u[n * W + im];
             XP[k] = u[n * W + ip];
         }
@@ -113,24 +126,24 @@ __device__ __forceinline__ void owned_step(const LevelView<T>& V, const ColCoef<
     const T EM = u[e * W + im], E0 = u[e * W + i], EP = u[e * W + ip];
 #pragma unroll
     for (int kk = 0; kk < kTailMaxRows; ++kk) {
-        const int k = TR ? kk : kTailMaxRows - 1 - kk;
+        const int k = kTailMaxRows - 1 - kk;
         if (k < M) {
-            const int n = o.n0 + k;
-            const bool coupled = TR ? (n < Nt) : (n >= 2);
-            const bool outside = TR ? (k == M - 1) : (k == 0);
-            const int kc = TR ? (k + 1 < kTailMaxRows ? k + 1 : k) : (k > 0 ? k - 1 : 0);
-            const T cm = outside ? EM : XM[kc];
-            const T c0 = outside ? E0 : x[kc];
-            const T cp = outside ? EP : XP[kc];
-            const T xm = (i == 1) ? T(0) : XM[k];
-            const T xp = (i == N) ? T(0) : XP[k];
-            const T ym = (i == 1) ? T(0) : cm;
-            const T yp = (i == N) ? T(0) : cp;
-            const T Ji = stencil_interior<T>(c.mlo, c.mdi, c.mup, c.kl, c.kr, T(-1), xm, x[k], xp,
-                                             coupled, ym, c0, yp);
-            const bool dir = (n == 0) || (i == 0);
-            const T r = bb[k] - (dir ? V.W * x[k] : Ji);
-            x[k] = JAC ? jacobi_update<T>(x[k], dir ? V.wW : c.wd, r) : r;
+            const int n = row_of<TR>(o, k);
+            const T negc = (TR ? (n < Nt) : (n >= 2)) ? T(-1) : T(0);
+            const T cm = k == 0 ? EM : XM[k > 0 ? k - 1 : 0];
+            const T c0 = k == 0 ? E0 : x[k > 0 ? k - 1 : 0];
+            const T cp = k == 0 ? EP : XP[k > 0 ? k - 1 : 0];
+            const T dm = fmaT(negc, cm, XM[k]);
+            const T d0 = fmaT(negc, c0, x[k]);
+            const T dp = fmaT(negc, cp, XP[k]);
+            T s = c.mdi * d0;
+            s = fmaT(c.mlo, dm, s);
+            s = fmaT(c.mup, dp, s);
+            s = fmaT(c.kl, fmaT(c.nm, XM[k], x[k]), s);
+            s = fmaT(c.kr, x[k] - XP[k], s);
+            const bool dir_row = n == 0;
+            const T r = bb[k] - (dir_row ? V.W * x[k] : s);
+            x[k] = JAC ? jacobi_update<T>(x[k], dir_row ? V.wW : c.wd, r) : r;
         }
     }
 }
@@ -144,19 +157,21 @@ __device__ void tail_smooth(const LevelView<T>& V, const ColCoef<T>& c, const Ow
         owned_step<T, TR, true>(V, c, o, u, x, bb);
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kTailMaxRows; ++k)
-            if (k < o.M && o.act && o.n0 + k <= V.Nt) u[(o.n0 + k) * W + o.i] = x[k];
+        for (int k = 0; k < kTailMaxRows; ++k) {
+            const int n = row_of<TR>(o, k);
+            if (k < o.M && o.act && n <= V.Nt) u[n * W + o.i] = x[k];
+        }
         __syncthreads();
     }
 }
 
 // Owned rows of u and b from LDS into registers (zero where not owned).
-template <typename T>
+template <typename T, int TR>
 __device__ __forceinline__ void load_owned(const Owner& o, int W, int Nt, const T* v,
                                            T (&x)[kTailMaxRows]) {
 #pragma unroll
     for (int k = 0; k < kTailMaxRows; ++k) {
-        const int n = o.n0 + k;
+        const int n = row_of<TR>(o, k);
         x[k] = (k < o.M && o.act && n <= Nt) ? v[n * W + o.i] : T(0);
     }
 }
@@ -168,24 +183,26 @@ template <typename T, int TR>
 __device__ void tail_down(const LevelView<T>& F, T* u, const T* b, int dir, T* uc, T* bc,
                           int nu) {
     const int W = F.N + 1, Nt = F.Nt;
-    const Owner o = owner_of(W, Nt);
+    const Owner o = owner_of(W, Nt, dir == 't');
     ColCoef<T> c{};
     if (o.act) c = col_coef(F, o.i);
     T x[kTailMaxRows], bb[kTailMaxRows];
-    load_owned(o, W, Nt, b, bb);
+    load_owned<T, TR>(o, W, Nt, b, bb);
 #pragma unroll
     for (int k = 0; k < kTailMaxRows; ++k) x[k] = T(0);
     tail_smooth<T, TR>(F, c, o, u, x, bb, nu);
     T (&r)[kTailMaxRows] = x;
     owned_step<T, TR, false>(F, c, o, u, r, bb);
     if (dir == 't') {
-        // pairs (2J, 2J+1) of one owner: bc_J = 1/2 (r_2J + r_2J+1 [2J+1 <= Nt])
+        // pairs (2J, 2J+1) of one owner: bc_J = 1/2 (r_2J + r_2J+1 [2J+1 <= Nt]); time
+        // level 2J is owned row k = 2m (J) or 2m+1 (J^T), 2J+1 the row next to it
 #pragma unroll
-        for (int k = 0; k < kTailMaxRows; k += 2) {
-            const int n = o.n0 + k;
+        for (int k = TR ? 1 : 0; k < kTailMaxRows; k += 2) {
+            const int n = row_of<TR>(o, k);
+            const int k1 = TR ? k - 1 : (k + 1 < kTailMaxRows ? k + 1 : k);
             if (k < o.M && o.act && n <= Nt) {
                 T v = r[k];
-                if (n + 1 <= Nt) v += r[k + 1];
+                if (n + 1 <= Nt) v += r[k1];
                 bc[(n >> 1) * W + o.i] = T(0.5) * v;
             }
         }
@@ -195,11 +212,13 @@ __device__ void tail_down(const LevelView<T>& F, T* u, const T* b, int dir, T* u
     // x: stage r (pitch W) over uc/bc, then bc_I = r_2I + 1/2 (r_2I-1 [I>=1] + r_2I+1 [I<Nc])
     T* rs = uc;
 #pragma unroll
-    for (int k = 0; k < kTailMaxRows; ++k)
-        if (k < o.M && o.act && o.n0 + k <= Nt) rs[(o.n0 + k) * W + o.i] = r[k];
+    for (int k = 0; k < kTailMaxRows; ++k) {
+        const int n = row_of<TR>(o, k);
+        if (k < o.M && o.act && n <= Nt) rs[n * W + o.i] = r[k];
+    }
     __syncthreads();
     const int Nc = F.N / 2, Wc = Nc + 1;
-    const Owner q = owner_of(Wc, Nt);
+    const Owner q = owner_of(Wc, Nt, false);
     const int I = q.i;
     T v[kTailMaxRows];
 #pragma unroll
@@ -230,16 +249,16 @@ __device__ void tail_down(const LevelView<T>& F, T* u, const T* b, int dir, T* u
 template <typename T, int TR>
 __device__ void tail_up(const LevelView<T>& F, T* u, const T* b, int dir, const T* z, int nu) {
     const int W = F.N + 1, Nt = F.Nt;
-    const Owner o = owner_of(W, Nt);
+    const Owner o = owner_of(W, Nt, dir == 't');
     ColCoef<T> c{};
     if (o.act) c = col_coef(F, o.i);
     T x[kTailMaxRows], bb[kTailMaxRows];
-    load_owned(o, W, Nt, u, x);
-    load_owned(o, W, Nt, b, bb);
+    load_owned<T, TR>(o, W, Nt, u, x);
+    load_owned<T, TR>(o, W, Nt, b, bb);
     const int f = o.i;
 #pragma unroll
     for (int k = 0; k < kTailMaxRows; ++k) {
-        const int n = o.n0 + k;
+        const int n = row_of<TR>(o, k);
         if (k < o.M && o.act && n <= Nt) {
             if (dir == 'x') {
                 const T* zr = z + n * (F.N / 2 + 1);
@@ -361,12 +380,12 @@ void* tail_kernel_for(int trans, int nmax) {
 
 }  // namespace
 
-int tail_rows_per_owner(int N, int Nt) {
+int tail_rows_per_owner(int N, int Nt, bool even) {
     const int W = N + 1;
     if (W > kTailThreads) return kTailMaxRows + 1;
     const int R = kTailThreads / W;
     const int M = (Nt + 1 + R - 1) / R;
-    return M + (M & 1);
+    return even ? M + (M & 1) : M;
 }
 
 template <typename T>
@@ -399,7 +418,7 @@ int launch_vcycle_tail(const TailLaunch<T>& t, hipStream_t s) {
         const LevelView<T>& V = t.V[l];
         const int W = V.N + 1;
         // every level but the coarsest (solved by wave 0) is mapped onto the threads
-        if (l + 1 < t.nlev && tail_rows_per_owner(V.N, V.Nt) > kTailMaxRows) return -1;
+        if (l + 1 < t.nlev && tail_rows_per_owner(V.N, V.Nt, t.dir[l] == 't') > kTailMaxRows) return -1;
         a.V[l] = V;
         a.dir[l] = t.dir[l];
         a.off_u[l] = off;

@@ -390,7 +390,7 @@ void plan_tail(stmg_ctx* h) {
     int best = -1, best_bytes = 0;
     for (int s0 = nl - 2; s0 >= 1 && nl - s0 <= kTailMaxLevels; --s0) {
         const Level& l = h->L[s0];
-        if (tail_rows_per_owner(l.N, l.Nt) > kTailMaxRows) break;
+        if (tail_rows_per_owner(l.N, l.Nt, l.dir == 't') > kTailMaxRows) break;
         int N[kTailMaxLevels], Nt[kTailMaxLevels];
         for (int j = s0; j < nl; ++j) {
             N[j - s0] = h->L[j].N;

@@ -140,8 +140,9 @@ struct TailLaunch {
     T* u_out;                          // its coarse-grid correction
     int64_t P_out;
 };
-// time rows per thread on a level (it must not exceed kTailMaxRows)
-int tail_rows_per_owner(int N, int Nt);
+// time rows per thread on a level (it must not exceed kTailMaxRows); even when the
+// level restricts in t
+int tail_rows_per_owner(int N, int Nt, bool even);
 // LDS bytes of u and b of the given levels
 template <typename T>
 int tail_lds_bytes(const int* N, const int* Nt, int nlev);
