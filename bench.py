@@ -11,6 +11,7 @@ Prints ONE JSON line (rank 0).  --gpus above 1 is rejected: this build runs on o
 from __future__ import annotations
 
 import argparse
+from concurrent.futures import ThreadPoolExecutor
 import json
 import os
 import subprocess
@@ -209,6 +210,9 @@ def main():
     ap.add_argument("--nu", type=int, default=None)
     ap.add_argument("--fused", type=int, default=1)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--sequential", action="store_true",
+                    help="run the forward and adjoint solves of a step one after the other "
+                         "on one handle instead of concurrently on two")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving", type=int, default=0,
@@ -237,20 +241,38 @@ def main():
     precision = B.STMG_MIXED if args.precision == "mixed" else B.STMG_FP64
     prob = B.Problem(w.n_el, w.n_t, w.length, w.t_final, k_ins=w.kappa_min)
     rho = torch.from_numpy(w.rho).to(dev)
-    solver = B.Solver(prob, rho, nu=nu, precision=precision, fused=args.fused,
-                      time_kernels=TIMED_EVERY)
+    # The adjoint right-hand side does not depend on u, so a step's two solves are
+    # independent: by default each runs on its own handle and stream from its own host
+    # thread, and the latency-bound coarse levels of one overlap the other's work.
+    concurrent = not (args.sequential or args.no_adjoint)
+    s_fwd = torch.cuda.Stream(device=dev) if concurrent else None
+    s_adj = torch.cuda.Stream(device=dev) if concurrent else None
+    opts = dict(nu=nu, precision=precision, fused=args.fused, time_kernels=TIMED_EVERY)
+    solver = B.Solver(prob, rho, stream=s_fwd, **opts)
+    adj_solver = B.Solver(prob, rho, stream=s_adj, **opts) if concurrent else solver
+    pool = ThreadPoolExecutor(max_workers=2) if concurrent else None
     info = solver.info()
     u = solver._new()
     lam = solver._new()
     grad = torch.empty(w.n_el, dtype=torch.float64, device=dev)
 
-    def step(record):
+    def forward():
         solver.set_design(rho)
-        _, st = solver.solve_forward(out=u)
-        rec = {"fwd": st}
+        return solver.solve_forward(out=u)[1]
+
+    def adjoint():
+        adj_solver.set_design(rho)
+        return adj_solver.solve_adjoint(out=lam)[1]
+
+    def step(record):
+        if concurrent:
+            fa, fb = pool.submit(forward), pool.submit(adjoint)
+            rec = {"fwd": fa.result(), "adj": fb.result()}
+        else:
+            rec = {"fwd": forward()}
+            if not args.no_adjoint:
+                rec["adj"] = adjoint()
         if not args.no_adjoint:
-            _, sa = solver.solve_adjoint(out=lam)
-            rec["adj"] = sa
             B.stmg_gradient(solver.handle, u, lam, grad)
         rec["theta"] = solver.objective(u)
         record.append(rec)
@@ -295,6 +317,8 @@ def main():
             "path": info["path"], "levels": info["n_levels"],
             "step": "reassemble + forward solve" + ("" if args.no_adjoint else
                                                   " + adjoint solve + gradient") + " + objective",
+            "solves": ("forward and adjoint concurrently, one handle and stream each"
+                       if concurrent else "one after the other"),
         },
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
                        "solves": len(lat)},
@@ -325,6 +349,9 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, nu, args.cpu_budget)
     solver.close()
+    if concurrent:
+        adj_solver.close()
+        pool.shutdown()
     print(json.dumps(out), flush=True)
 
 

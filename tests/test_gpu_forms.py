@@ -44,6 +44,21 @@ def test_mixed_precision_tracks_fp64(name, transpose, fused, cuda):
         assert r_or < 2e-10
 
 
+@pytest.mark.parametrize("name", ["uniform_64x64", "block_256x600"])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_mixed_tail_is_bit_identical(name, transpose, cuda):
+    """The FP32 V-cycle through the single-workgroup tail (fused = 1) and through
+    streaming launches on every level (fused = 2) give the same bits."""
+    from paper_2505_10168_amd import binding as B
+    outs = []
+    for fused in (1, 2):
+        s, _, lv, h = make_pair(name, cuda, fused=fused, precision=B.STMG_MIXED, max_cycles=5)
+        assert (s.info()["tail_level"] > 0) == (fused == 1)
+        u, st = (s.solve_adjoint if transpose else s.solve_forward)()
+        outs.append((to_np(u), st.history))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_objective_and_gradient_match_oracle(name, cuda):
     s, mat, lv, h = make_pair(name, cuda)
