@@ -159,7 +159,11 @@ int stmg_set_design(stmg_t h, const double* d_rho);
  *   d_u0  : initial guess, or NULL for u = 0 (the paper's choice).
  *   d_u   : output (may alias d_u0).
  *   st    : optional statistics.
- * Returns OK, NOT_CONVERGED or DIVERGED (d_u holds the last iterate in all three). */
+ * Returns OK, NOT_CONVERGED or DIVERGED (d_u holds the last iterate in all three).
+ * In FP64 with fused != 0 the residual of cycle k is tested while cycle k+1 already
+ * runs; a cycle run past the stopping point is discarded, so iterates, history and
+ * cycle count are those of the plain loop (the fine level keeps one more vector for
+ * this; stmg_footprint counts it). */
 int stmg_solve_forward(stmg_t h, const double* d_rhs, const double* d_u0,
                        double* d_u, stmg_stats* st);
 

@@ -139,7 +139,6 @@ struct stmg_ctx {
     std::vector<void*> allocs;
     size_t bytes = 0;
     KernelTimer timer;
-    bool want_norm = false;      // fuse the residual norm into the fine post pass
     int tail_start = -1;         // first level of the single-workgroup tail (-1: none)
     bool rotate_in = false;      // the next fine pass keeps its input in L[0].w
     uint64_t vcycles = 0;        // fine-level V-cycles started (sampled kernel timing)
