@@ -2,17 +2,31 @@
 
 ``ThermalCompliance.apply(rho, solver)`` returns Theta = b^T u dt / Theta_ref
 (Section 7.1) for the element densities ``rho`` on a device-resident STMG hierarchy;
-its backward pass is the adjoint STMG solve J^T Lambda = b dt / Theta_ref (Section
-7.2) followed by the gradient kernel g_e = -Lambda^T (dJ/drho_e) u, all in libstmg.
-PyTorch only carries the tensors and the autograd graph.
+its backward pass is the gradient g_e = -Lambda^T (dJ/drho_e) u with Lambda from the
+adjoint system J^T Lambda = b dt / Theta_ref (Section 7.2), all in libstmg.  PyTorch
+only carries the tensors and the autograd graph.
+
+The adjoint right-hand side does not depend on u, so by default the forward pass also
+solves the adjoint system, concurrently, on a second handle with its own stream (the
+latency-bound coarse levels of one solve overlap the other's work); backward then only
+forms the gradient.  With ``concurrent_adjoint=False`` the adjoint is solved in
+backward, on the same handle.
 """
 from __future__ import annotations
+
+from concurrent.futures import ThreadPoolExecutor
 
 import torch
 
 from . import binding as B
 
 _STATUS = {B.STMG_OK: "ok", B.STMG_NOT_CONVERGED: "not converged", B.STMG_DIVERGED: "diverged"}
+
+
+def _check(st, what, strict):
+    if st.status != B.STMG_OK and strict:
+        raise RuntimeError(f"{what} STMG solve {_STATUS.get(st.status, st.status)}: "
+                           f"relative residual {st.rel_residual:.3e} after {st.cycles} cycles")
 
 
 class ThermalCompliance(torch.autograd.Function):
@@ -22,42 +36,55 @@ class ThermalCompliance(torch.autograd.Function):
     def forward(ctx, rho: torch.Tensor, solver: "ComplianceSolver") -> torch.Tensor:
         rho = rho.detach().to(torch.float64).contiguous()
         version = solver._load_design(rho)
+        pending = solver._start_adjoint() if solver.concurrent else None
         u, st = solver.solver.solve_forward()
         solver.last_forward = st
-        if st.status != B.STMG_OK and solver.strict:
-            raise RuntimeError(f"forward STMG solve {_STATUS.get(st.status, st.status)}: "
-                               f"relative residual {st.rel_residual:.3e} after {st.cycles} cycles")
+        lam = None
+        if pending is not None:
+            lam, sa = pending.result()
+            solver.last_adjoint = sa
+            _check(sa, "adjoint", solver.strict)
+        _check(st, "forward", solver.strict)
         theta = solver.solver.objective(u)
         ctx.solver = solver
         ctx.version = version
-        ctx.save_for_backward(rho, u)
+        ctx.save_for_backward(rho, u, lam if lam is not None else u.new_empty(0))
+        ctx.has_lam = lam is not None
         return torch.tensor(theta, dtype=torch.float64, device=rho.device)
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
-        rho, u = ctx.saved_tensors
+        rho, u, lam = ctx.saved_tensors
         solver = ctx.solver
         if solver.version != ctx.version:
             solver._load_design(rho)
-        lam, st = solver.solver.solve_adjoint()
-        solver.last_adjoint = st
-        if st.status != B.STMG_OK and solver.strict:
-            raise RuntimeError(f"adjoint STMG solve {_STATUS.get(st.status, st.status)}: "
-                               f"relative residual {st.rel_residual:.3e} after {st.cycles} cycles")
+        if not ctx.has_lam:
+            lam, st = solver.solver.solve_adjoint()
+            solver.last_adjoint = st
+            _check(st, "adjoint", solver.strict)
         g = solver.solver.gradient(u, lam)
         return grad_out * g, None
 
 
 class ComplianceSolver:
-    """Owns one STMG hierarchy for a fixed grid and material; designs are loaded into
-    it by re-assembly.  deff_mode = 1 (Section 7.2) keeps the coarsening path fixed
-    across designs, so the hierarchy never needs to be rebuilt."""
+    """Owns the STMG hierarchy (two, with the concurrent adjoint) for a fixed grid and
+    material; designs are loaded into it by re-assembly.  deff_mode = 1 (Section 7.2)
+    keeps the coarsening path fixed across designs, so the hierarchy never needs to be
+    rebuilt."""
 
-    def __init__(self, problem: B.Problem, rho0: torch.Tensor, strict: bool = True, **options):
+    def __init__(self, problem: B.Problem, rho0: torch.Tensor, strict: bool = True,
+                 concurrent_adjoint: bool = True, **options):
         options.setdefault("deff_mode", 1)
-        self.solver = B.Solver(problem, rho0.detach().to(torch.float64).contiguous(), **options)
+        rho0 = rho0.detach().to(torch.float64).contiguous()
+        self.concurrent = concurrent_adjoint
+        dev = rho0.device
+        s1 = torch.cuda.Stream(device=dev) if concurrent_adjoint else None
+        s2 = torch.cuda.Stream(device=dev) if concurrent_adjoint else None
+        self.solver = B.Solver(problem, rho0, stream=s1, **options)
+        self.adjoint_solver = B.Solver(problem, rho0, stream=s2, **options) if concurrent_adjoint else None
+        self._pool = ThreadPoolExecutor(max_workers=1) if concurrent_adjoint else None
         self.version = 0
-        self._current = rho0.detach().clone()
+        self._current = rho0.clone()
         self.strict = strict
         self.last_forward = None
         self.last_adjoint = None
@@ -65,12 +92,20 @@ class ComplianceSolver:
     def _load_design(self, rho: torch.Tensor) -> int:
         if not (self._current.shape == rho.shape and torch.equal(self._current, rho)):
             self.solver.set_design(rho)
+            if self.adjoint_solver is not None:
+                self.adjoint_solver.set_design(rho)
             self._current = rho.clone()
             self.version += 1
         return self.version
+
+    def _start_adjoint(self):
+        return self._pool.submit(self.adjoint_solver.solve_adjoint)
 
     def __call__(self, rho: torch.Tensor) -> torch.Tensor:
         return ThermalCompliance.apply(rho, self)
 
     def close(self):
         self.solver.close()
+        if self.adjoint_solver is not None:
+            self.adjoint_solver.close()
+            self._pool.shutdown()

@@ -19,14 +19,16 @@ def oracle_theta_grad(rho, n_t, kmin, c_ins=1.0):
 
 
 @pytest.mark.parametrize("c_ins", [1.0, 0.1])
-def test_autograd_matches_oracle_gradient(c_ins, cuda):
+@pytest.mark.parametrize("concurrent", [True, False])
+def test_autograd_matches_oracle_gradient(c_ins, concurrent, cuda):
     import torch
     from paper_2505_10168_amd import binding as B
     from paper_2505_10168_amd.autograd import ComplianceSolver
     n_el, n_t, kmin = 96, 160, 1e-2
     rho = np.random.default_rng(3).uniform(0.2, 0.9, n_el)
     prob = B.Problem(n_el, n_t, k_ins=kmin, c_ins=c_ins)
-    cs = ComplianceSolver(prob, to_dev(rho, cuda), nu=5, max_cycles=400)
+    cs = ComplianceSolver(prob, to_dev(rho, cuda), concurrent_adjoint=concurrent, nu=5,
+                          max_cycles=400)
     x = to_dev(rho, cuda).requires_grad_(True)
     theta = cs(x)
     theta.backward()
