@@ -510,10 +510,14 @@ __global__ __launch_bounds__(64) void k_coarsest_dense(LevelView<double> L,
     const double mdi = act ? L.mdi[node] : 0.0;
     const double mup = act ? L.mup[node] : 0.0;
     double zprev = 0.0;
+    // the right-hand side of the next step is loaded one step ahead
+    auto row = [&](int s) { return trans ? Nt - s : 1 + s; };
+    double bn = (act && Nt > 0) ? (double)b[(int64_t)row(0) * P + node] : 0.0;
     for (int s = 0; s < Nt; ++s) {
-        const int n = trans ? Nt - s : 1 + s;
+        const int n = row(s);
         const bool coupled = trans ? (n < Nt) : (n >= 2);
-        double rhs = act ? (double)b[(int64_t)n * P + node] : 0.0;
+        double rhs = bn;
+        if (s + 1 < Nt) bn = act ? (double)b[(int64_t)row(s + 1) * P + node] : 0.0;
         const double zl = __shfl_up(zprev, 1, 64);
         const double zr = __shfl_down(zprev, 1, 64);
         if (coupled) {
