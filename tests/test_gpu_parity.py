@@ -221,3 +221,42 @@ def test_pipelined_solve_returns_its_last_iterate(name, max_cycles, transpose, c
         r = B.stmg_vcycle(s.handle, transpose, bd, ref)
         assert st.history[k + 1] == pytest.approx(r, rel=1e-9)
     assert np.array_equal(to_np(u), to_np(ref))
+
+
+# Coarsening and re-assembly variants (Section 5.1 K and D methods, the Algorithm 4
+# small-feature guard, a fixed level count, the Section 7.2 field-independent D_eff):
+# (name, case, libstmg options, oracle options)
+VARIANTS = [
+    ("K", "block_256x600", {"reassembly": 1}, {"reassembly": "K"}),
+    ("D", "ramp_300x256", {"reassembly": 2}, {"reassembly": "D"}),
+    ("M_guard", "block_256x600", {"M_min_elems": 100}, {"M_min_elems": 100}),   # xtttxxxx
+    ("max_levels", "block_256x600", {"max_levels": 4}, {"max_levels": 4}),
+    ("deff_simp", "ramp_300x256", {"deff_mode": 1}, {"deff_mode": "simp"}),
+]
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=[v[0] for v in VARIANTS])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_variants_match_oracle(variant, transpose, cuda):
+    from paper_2505_10168_amd import binding as B
+    _, name, gpu_opts, oracle_opts = variant
+    rho, n_t, kmin, c_ins, opts = CASES[name]
+    prob = B.Problem(len(rho), n_t, k_ins=kmin, c_ins=c_ins)
+    s = B.Solver(prob, to_dev(rho, cuda), **dict(opts, **gpu_opts))
+    mat, lv, h = oracle_setup(rho, n_t, kmin, c_ins=c_ins, nu=opts.get("nu", 2), **oracle_opts)
+    info = s.info()
+    print(f"{variant[0]}: path {info['path']} (oracle {h.path})")
+    assert info["path"] == h.path
+    for a, l in zip(info["w_diri"], h.levels):
+        assert a == pytest.approx(l.W, rel=1e-15)
+    for a, b in zip(info["lambda_eff"], h.lambdas):
+        assert a == pytest.approx(b, rel=1e-14)
+    b = O.load_vector(lv, 1.0)
+    if transpose:
+        b = O.adjoint_rhs(lv, b)
+    u = np.zeros(lv.shape)
+    ud, bd = to_dev(u, cuda), to_dev(b, cuda)
+    for it in range(3):
+        B.stmg_vcycle(s.handle, transpose, bd, ud)
+        u = O.vcycle(h, 0, u, b, bool(transpose))
+        assert rel(to_np(ud), u) <= 1e-12, (it, rel(to_np(ud), u))
