@@ -209,6 +209,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--nu", type=int, default=None)
     ap.add_argument("--fused", type=int, default=1)
+    ap.add_argument("--interp", default="C", choices=["C", "B"],
+                    help="interpolation in time: causal (C, the paper's default) or bilinear (B)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--sequential", action="store_true",
                     help="run the forward and adjoint solves of a step one after the other "
@@ -247,7 +249,8 @@ def main():
     concurrent = not (args.sequential or args.no_adjoint)
     s_fwd = torch.cuda.Stream(device=dev) if concurrent else None
     s_adj = torch.cuda.Stream(device=dev) if concurrent else None
-    opts = dict(nu=nu, precision=precision, fused=args.fused, time_kernels=TIMED_EVERY)
+    opts = dict(nu=nu, precision=precision, fused=args.fused, time_kernels=TIMED_EVERY,
+                interp=B.STMG_INTERP_B if args.interp == "B" else B.STMG_INTERP_C)
     solver = B.Solver(prob, rho, stream=s_fwd, **opts)
     adj_solver = B.Solver(prob, rho, stream=s_adj, **opts) if concurrent else solver
     pool = ThreadPoolExecutor(max_workers=2) if concurrent else None
@@ -314,6 +317,7 @@ def main():
         "config": {
             "workload": args.workload, "n_el": w.n_el, "n_t": w.n_t, "dofs": w.dofs,
             "kappa_min": w.kappa_min, "nu": nu, "tol": 1e-10, "precision": args.precision,
+            "interp": args.interp,
             "path": info["path"], "levels": info["n_levels"],
             "step": "reassemble + forward solve" + ("" if args.no_adjoint else
                                                   " + adjoint solve + gradient") + " + objective",

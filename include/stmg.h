@@ -54,6 +54,10 @@ extern "C" {
 #define STMG_FP64             0   /* everything in FP64                             */
 #define STMG_MIXED            1   /* FP64 outer defect correction around FP32 cycles */
 
+/* interpolation in time (Section 5.1) */
+#define STMG_INTERP_C         0   /* causal: coarse level J to fine levels 2J and 2J+1 */
+#define STMG_INTERP_B         1   /* bilinear: fine 2J <- 1, fine 2J +- 1 <- 1/2      */
+
 #define STMG_MAX_HISTORY   1024   /* longest residual history kept in the stats     */
 
 /* Physical problem.  Materials: k(rho) = k_ins + (k_con - k_ins) rho^p_k and
@@ -75,7 +79,7 @@ typedef struct {
 /* Solver options.  stmg_default_options() fills: nu = 2, omega = 0.5,
  * lambda_crit = 0.25, max_levels = 0, min_coarse_dofs = 1024, M_min_elems = 0,
  * reassembly = R, deff_mode = 0, tol = 1e-10, diverge = 1e9, max_cycles = 100,
- * precision = FP64, w_diri_override = 0, fused = 1, time_kernels = 0. */
+ * precision = FP64, w_diri_override = 0, fused = 1, time_kernels = 0, interp = C. */
 typedef struct {
     int32_t nu;               /* smoothing steps before and after the coarse correction (Algorithm 1) */
     double  omega;            /* Jacobi damping (Section 3.1 uses 1/2)                       */
@@ -97,6 +101,10 @@ typedef struct {
                                     All three give bit-identical iterates.                     */
     int32_t time_kernels;     /* k > 0: time the fine-level fused passes of every k-th V-cycle
                                     with HIP events (1: all of them); 0: no timing            */
+    int32_t interp;           /* STMG_INTERP_C or STMG_INTERP_B: prolongation P in time, and
+                                    R = P^T / 2.  With B the t transfers run as separate
+                                    one-thread-per-DOF kernels beside the fused smoothing
+                                    passes, and no single-workgroup tail is used              */
 } stmg_options;
 
 typedef struct {

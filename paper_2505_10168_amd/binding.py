@@ -22,6 +22,7 @@ LIB_PATH = Path(os.environ.get("STMG_LIBRARY") or
 STMG_OK, STMG_NOT_CONVERGED, STMG_DIVERGED = 0, 1, 2
 STMG_EINVAL, STMG_ENOMEM, STMG_EHIP, STMG_EUNSUPPORTED = -1, -2, -3, -4
 STMG_REASSEMBLE_R, STMG_REASSEMBLE_K, STMG_REASSEMBLE_D = 0, 1, 2
+STMG_INTERP_C, STMG_INTERP_B = 0, 1
 STMG_FP64, STMG_MIXED = 0, 1
 STMG_MAX_HISTORY = 1024
 
@@ -39,7 +40,7 @@ class stmg_options(C.Structure):
                 ("M_min_elems", C.c_int32), ("reassembly", C.c_int32), ("deff_mode", C.c_int32),
                 ("tol", C.c_double), ("diverge", C.c_double), ("max_cycles", C.c_int32),
                 ("precision", C.c_int32), ("w_diri_override", C.c_double), ("fused", C.c_int32),
-                ("time_kernels", C.c_int32)]
+                ("time_kernels", C.c_int32), ("interp", C.c_int32)]
 
 
 class stmg_stats(C.Structure):

@@ -348,11 +348,30 @@ __global__ void k_restrict_t(LevelView<T> F, const T* __restrict__ r, T* __restr
     }
 }
 
+// Bilinear interpolation in time (B, Section 5.1), s = 1/2:
+//   bc_{J,i} = 1/2 (r_{2J,i} + 1/2 (r_{2J-1,i} [J>=1] + r_{2J+1,i} [2J+1 <= Nt]))
+template <typename T>
+__global__ void k_restrict_tB(LevelView<T> F, const T* __restrict__ r, T* __restrict__ bc,
+                              int64_t Pc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > F.N) return;
+    const int Ntc = F.Nt / 2;
+    for (int J = blockIdx.y; J <= Ntc; J += gridDim.y) {
+        T side = T(0);
+        if (J >= 1) side += r[(int64_t)(2 * J - 1) * F.P + i];
+        if (2 * J + 1 <= F.Nt) side += r[(int64_t)(2 * J + 1) * F.P + i];
+        bc[(int64_t)J * Pc + i] = T(0.5) * fmaT(T(0.5), side, r[(int64_t)(2 * J) * F.P + i]);
+    }
+}
+
 template <typename T>
 void launch_restrict(char dir, const LevelView<T>& F, const T* r, T* bc, int64_t Pc,
-                     hipStream_t s) {
+                     hipStream_t s, int interp) {
     if (dir == 'x')
         hipLaunchKernelGGL((k_restrict_x<T>), dim3(blocks_for(F.N / 2 + 1), rows_grid(F.Nt + 1)),
+                           dim3(kBlock), 0, s, F, r, bc, Pc);
+    else if (interp == 1)
+        hipLaunchKernelGGL((k_restrict_tB<T>), dim3(blocks_for(F.N + 1), rows_grid(F.Nt / 2 + 1)),
                            dim3(kBlock), 0, s, F, r, bc, Pc);
     else
         hipLaunchKernelGGL((k_restrict_t<T>), dim3(blocks_for(F.N + 1), rows_grid(F.Nt / 2 + 1)),
@@ -386,12 +405,31 @@ __global__ void k_prolong_t(LevelView<T> F, const T* __restrict__ z, int64_t Pc,
         u[(int64_t)n * F.P + i] += z[(int64_t)(n >> 1) * Pc + i];
 }
 
+// Bilinear in time (B):  u_{2J,i} += z_{J,i},  u_{2J+1,i} += 1/2 (z_{J,i} + z_{J+1,i})
+// (a t-coarsened level has an even N_t, so J+1 <= N_t/2 for every odd fine level).
+template <typename T>
+__global__ void k_prolong_tB(LevelView<T> F, const T* __restrict__ z, int64_t Pc,
+                             T* __restrict__ u) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > F.N) return;
+    for (int n = blockIdx.y; n <= F.Nt; n += gridDim.y) {
+        T* uo = u + (int64_t)n * F.P + i;
+        const T* zr = z + (int64_t)(n >> 1) * Pc + i;
+        if (n & 1)
+            *uo = fmaT(T(0.5), zr[0] + zr[Pc], *uo);
+        else
+            *uo += zr[0];
+    }
+}
+
 template <typename T>
 void launch_prolong_add(char dir, const LevelView<T>& F, const T* z, int64_t Pc, T* u,
-                        hipStream_t s) {
+                        hipStream_t s, int interp) {
     dim3 g(blocks_for(F.N + 1), rows_grid(F.Nt + 1));
     if (dir == 'x')
         hipLaunchKernelGGL((k_prolong_x<T>), g, dim3(kBlock), 0, s, F, z, Pc, u);
+    else if (interp == 1)
+        hipLaunchKernelGGL((k_prolong_tB<T>), g, dim3(kBlock), 0, s, F, z, Pc, u);
     else
         hipLaunchKernelGGL((k_prolong_t<T>), g, dim3(kBlock), 0, s, F, z, Pc, u);
 }
@@ -761,13 +799,13 @@ template void launch_apply<double>(const LevelView<double>&, int, int, const dou
 template void launch_apply<float>(const LevelView<float>&, int, int, const float*, const float*,
                                   float*, bool, hipStream_t);
 template void launch_restrict<double>(char, const LevelView<double>&, const double*, double*,
-                                      int64_t, hipStream_t);
+                                      int64_t, hipStream_t, int);
 template void launch_restrict<float>(char, const LevelView<float>&, const float*, float*,
-                                     int64_t, hipStream_t);
+                                     int64_t, hipStream_t, int);
 template void launch_prolong_add<double>(char, const LevelView<double>&, const double*, int64_t,
-                                         double*, hipStream_t);
+                                         double*, hipStream_t, int);
 template void launch_prolong_add<float>(char, const LevelView<float>&, const float*, int64_t,
-                                        float*, hipStream_t);
+                                        float*, hipStream_t, int);
 template void launch_coarsest<double>(const LevelView<double>&, const double*, const double*,
                                       const double*, double*, int, hipStream_t);
 template void launch_coarsest<float>(const LevelView<double>&, const double*, const double*,

@@ -202,6 +202,8 @@ int validate(const stmg_problem* p, const stmg_options* o) {
         return fail(STMG_EINVAL, "unknown precision");
     if (o->fused < 0 || o->fused > 2) return fail(STMG_EINVAL, "fused must be 0, 1 or 2");
     if (o->time_kernels < 0) return fail(STMG_EINVAL, "time_kernels must be >= 0");
+    if (o->interp != STMG_INTERP_C && o->interp != STMG_INTERP_B)
+        return fail(STMG_EINVAL, "unknown interpolation");
     if (!(o->tol > 0) || !(o->diverge > 0)) return fail(STMG_EINVAL, "tol and diverge must be > 0");
     return 0;
 }
@@ -377,6 +379,7 @@ int finish_level(stmg_ctx* h, Level& l, bool coarsest) {
 // of at least two levels qualifies.
 void plan_tail(stmg_ctx* h) {
     h->tail_start = -1;
+    if (h->o.interp != STMG_INTERP_C) return;   // the tail kernel transfers causally
     const int nl = (int)h->L.size();
     const Level& c = h->L[nl - 1];
     if (nl < 3 || !c.ainv || c.N > kTailMaxCoarsestN) return;
@@ -528,6 +531,8 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
     T* b = B<T>(lv);
     T*& t = Tt<T>(lv);
     const bool timed = l == 0 && h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
+    // bilinear t transfers run as their own kernels after the fused passes
+    const bool split = lv.dir == 't' && h->o.interp == STMG_INTERP_B;
     if (h->o.fused) {
         std::vector<int> ch = chunks_of(nu);
         bool zero = zero_start;
@@ -537,7 +542,7 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
             fp.sweeps = ch[k];
             fp.zero_in = zero;
             const bool lastc = k + 1 == ch.size();
-            fp.tail = lastc ? lv.dir : 0;
+            fp.tail = (lastc && !split) ? lv.dir : 0;
             fp.bc = B<T>(cl);
             fp.Pbc = cl.P;
             fp.Nc = cl.N;
@@ -560,6 +565,10 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
             std::swap(u, t);
             zero = false;
         }
+        if (split) {
+            launch_apply<T>(V, trans, APPLY_RESIDUAL, u, b, t, false, h->s);
+            launch_restrict<T>(lv.dir, V, t, B<T>(cl), cl.P, h->s, h->o.interp);
+        }
     } else {
         for (int k = 0; k < nu; ++k) {
             launch_apply<T>(V, trans, APPLY_JACOBI, u, b, t, zero_start && k == 0, h->s);
@@ -567,7 +576,7 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
         }
         if (nu == 0 && zero_start) launch_fill<T>(u, lv.elems(), T(0), h->s);
         launch_apply<T>(V, trans, APPLY_RESIDUAL, u, b, t, false, h->s);
-        launch_restrict<T>(lv.dir, V, t, B<T>(cl), cl.P, h->s);
+        launch_restrict<T>(lv.dir, V, t, B<T>(cl), cl.P, h->s, h->o.interp);
     }
     HIPCHK(hipGetLastError());
     return 0;
@@ -583,13 +592,15 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
     T*& t = Tt<T>(lv);
     const T* z = U<T>(cl);
     const bool timed = l == 0 && h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
+    const bool split = lv.dir == 't' && h->o.interp == STMG_INTERP_B;
     if (h->o.fused) {
+        if (split) launch_prolong_add<T>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
         std::vector<int> ch = chunks_of(nu);
         for (size_t k = 0; k < ch.size(); ++k) {
             FusedPass fp{};
             fp.trans = trans;
             fp.sweeps = ch[k];
-            fp.prolong = k == 0 ? lv.dir : 0;
+            fp.prolong = (k == 0 && !split) ? lv.dir : 0;
             fp.z = z;
             fp.Pz = cl.P;
             fp.Nc = cl.N;
@@ -605,7 +616,7 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
             std::swap(u, t);
         }
     } else {
-        launch_prolong_add<T>(lv.dir, V, z, cl.P, u, h->s);
+        launch_prolong_add<T>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
         for (int k = 0; k < nu; ++k) {
             launch_apply<T>(V, trans, APPLY_JACOBI, u, b, t, false, h->s);
             std::swap(u, t);
@@ -1032,6 +1043,7 @@ int stmg_default_options(stmg_options* o) {
     o->w_diri_override = 0.0;
     o->fused = 1;
     o->time_kernels = 0;
+    o->interp = STMG_INTERP_C;
     return 0;
 }
 

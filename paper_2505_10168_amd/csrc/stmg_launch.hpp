@@ -45,12 +45,13 @@ void launch_axpy2d(const Tin* src, int64_t sp, double* dst, int64_t dp, int rows
 template <typename T>
 void launch_apply(const LevelView<T>& L, int trans, int mode, const T* x, const T* b, T* y,
                   bool zero_in, hipStream_t s);
+// interp: 0 = causal (C), 1 = bilinear in time (B); only t transfers differ
 template <typename T>
 void launch_restrict(char dir, const LevelView<T>& F, const T* r, T* bc, int64_t Pc,
-                     hipStream_t s);
+                     hipStream_t s, int interp);
 template <typename T>
 void launch_prolong_add(char dir, const LevelView<T>& F, const T* z, int64_t Pc, T* u,
-                        hipStream_t s);
+                        hipStream_t s, int interp);
 // Exact coarsest solve (time stepping + Thomas) in FP64 on vectors of type TV.
 template <typename TV>
 void launch_coarsest(const LevelView<double>& L, const double* cp, const double* inv,

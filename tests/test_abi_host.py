@@ -73,7 +73,7 @@ def test_create_rejects_bad_problem_without_device_work(field, value):
 @pytest.mark.parametrize("field,value", [("nu", -1), ("omega", 0.0), ("max_cycles", 0),
                                          ("max_cycles", 5000), ("precision", 7), ("reassembly", 9),
                                          ("min_coarse_dofs", 0), ("tol", -1.0), ("fused", 3),
-                                         ("fused", -1), ("time_kernels", -1)])
+                                         ("fused", -1), ("time_kernels", -1), ("interp", 2)])
 def test_create_rejects_bad_options(field, value):
     p = B.Problem(8, 8).c_struct()
     o = B.make_options(**{field: value})

@@ -232,6 +232,8 @@ VARIANTS = [
     ("M_guard", "block_256x600", {"M_min_elems": 100}, {"M_min_elems": 100}),   # xtttxxxx
     ("max_levels", "block_256x600", {"max_levels": 4}, {"max_levels": 4}),
     ("deff_simp", "ramp_300x256", {"deff_mode": 1}, {"deff_mode": "simp"}),
+    ("B_block", "block_256x600", {"interp": 1}, {"interp": "B"}),
+    ("B_ramp", "ramp_300x256", {"interp": 1}, {"interp": "B"}),
 ]
 
 
@@ -260,3 +262,22 @@ def test_variants_match_oracle(variant, transpose, cuda):
         B.stmg_vcycle(s.handle, transpose, bd, ud)
         u = O.vcycle(h, 0, u, b, bool(transpose))
         assert rel(to_np(ud), u) <= 1e-12, (it, rel(to_np(ud), u))
+
+
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_bilinear_fused_and_reference_identical(transpose, cuda):
+    """Bilinear time interpolation: fused smoothing passes with separate t transfers
+    (fused = 1) and one kernel per step (fused = 0) give the same bits."""
+    from paper_2505_10168_amd import binding as B
+    outs = []
+    for fused in (1, 0):
+        s, _, lv, h = make_pair("block_256x600", cuda, fused=fused, interp=B.STMG_INTERP_B)
+        assert s.info()["tail_level"] == -1
+        b = O.load_vector(lv, 1.0)
+        if transpose:
+            b = O.adjoint_rhs(lv, b)
+        bd, ud = to_dev(b, cuda), to_dev(np.zeros(lv.shape), cuda)
+        for _ in range(3):
+            B.stmg_vcycle(s.handle, transpose, bd, ud)
+        outs.append(to_np(ud))
+    assert np.array_equal(outs[0], outs[1])

@@ -352,6 +352,27 @@ def test_prolongation_stencils():
     expect = np.zeros(lv.shape)
     expect[2:4, 4] = 1.0          # coarse level J -> fine 2J and 2J+1 (forward in time)
     np.testing.assert_array_equal(pt, expect)
+    # bilinear in time (Section 5.1, B): fine 2J <- 1, fine 2J -+ 1 <- 1/2
+    pb = O.prolong(lv, "t", zt, interp="B")
+    expect = np.zeros(lv.shape)
+    expect[1:4, 4] = [0.5, 1.0, 0.5]
+    np.testing.assert_array_equal(pb, expect)
+
+
+def test_bilinear_restriction_is_half_transpose():
+    """R = s P^T with s = 1/2 for t (Section 3.1), for the bilinear P as well: the
+    duality <R r, z> = s <r, P z> on random vectors."""
+    lv = uniform_level(6, 8)
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal(lv.shape)
+    z = rng.standard_normal((5, 7))
+    lhs = np.sum(O.restrict(lv, "t", r, interp="B") * z)
+    rhs = 0.5 * np.sum(r * O.prolong(lv, "t", z, interp="B"))
+    assert lhs == pytest.approx(rhs, rel=1e-13)
+    # interior coarse level J: 1/2 (r_2J + (r_2J-1 + r_2J+1)/2)
+    e = np.zeros(lv.shape)
+    e[3:6, 2] = [1.0, 2.0, 4.0]
+    np.testing.assert_allclose(O.restrict(lv, "t", e, interp="B")[2, 2], 0.5 * (2.0 + 2.5))
 
 
 # ---------------------------------------------------------------------------------------
