@@ -16,6 +16,8 @@ multigrid      : coarsening strategies (Algorithms 2-4), rediscretisation method
                  V-cycle and the solve loop with the termination rule of Section 3.1.
 sensitivity    : objective, adjoint right-hand side and the discrete-adjoint gradient
                  of Section 7.
+design         : optimality-criteria design update and design loop for the
+                 optimisation problem of Section 7.
 
 Parity status
 -------------
@@ -28,3 +30,4 @@ fixed-point/linearity invariants of the cycle.
 from .discretisation import *  # noqa: F401,F403
 from .multigrid import *  # noqa: F401,F403
 from .sensitivity import *  # noqa: F401,F403
+from .design import *  # noqa: F401,F403
