@@ -190,6 +190,25 @@ int stmg_objective(stmg_t h, const double* d_u, double* theta);
  * d_grad: N_el FP64 (device). */
 int stmg_gradient(stmg_t h, const double* d_u, const double* d_lambda, double* d_grad);
 
+/* One design update for the optimisation problem of Section 7.1: minimise Theta
+ * subject to 0 <= rho_e <= 1 and the volume bound mean(rho) <= volume (the paper's
+ * bound is volume = 1/2).  The paper moves the design with MMA, which it only cites;
+ * this is the optimality-criteria step for one volume constraint (Bendsoe 1995):
+ *   D_e = max(-grad_e, 0),  lo_e = max(rho_min, rho_e - move),  hi_e = min(1, rho_e + move),
+ *   rho_new_e = min(max(rho_e (D_e / lam)^eta, lo_e), hi_e),
+ * with the multiplier lam from 96 halvings of [1e-40, 1e40] max_e D_e in log space
+ * (midpoint sqrt(a) sqrt(b), stepping up while mean(rho_new) > volume), so that
+ * mean(rho_new) = volume to rounding when the bound is active; when it is not, every
+ * element with D_e > 0 moves to hi_e.  Elements with D_e = 0 move to lo_e.
+ *   d_rho     : N_el FP64 (device), the current design.
+ *   d_grad    : N_el FP64 (device), dTheta/drho (e.g. from stmg_gradient).
+ *   d_rho_new : N_el FP64 (device) output; may alias d_rho.
+ * The handle supplies N_el and the stream; its hierarchy is not touched (load the new
+ * design with stmg_set_design).  Returns after the update has finished.
+ * Errors: EINVAL unless 0 < volume <= 1, move > 0, 0 < eta <= 1, 0 <= rho_min < 1. */
+int stmg_oc_update(stmg_t h, const double* d_rho, const double* d_grad, double volume,
+                   double move, double eta, double rho_min, double* d_rho_new);
+
 int stmg_get_info(stmg_t h, stmg_info* info);
 int stmg_destroy(stmg_t h);
 

@@ -10,7 +10,9 @@ The adjoint right-hand side does not depend on u, so by default the forward pass
 solves the adjoint system, concurrently, on a second handle with its own stream (the
 latency-bound coarse levels of one solve overlap the other's work); backward then only
 forms the gradient.  With ``concurrent_adjoint=False`` the adjoint is solved in
-backward, on the same handle.
+backward, on the same handle.  With ``warm_start=True`` each solve starts from the
+previous design's solution instead of zero (a design loop changes the design a little
+per step, so fewer V-cycles reach the tolerance).
 """
 from __future__ import annotations
 
@@ -37,8 +39,10 @@ class ThermalCompliance(torch.autograd.Function):
         rho = rho.detach().to(torch.float64).contiguous()
         version = solver._load_design(rho)
         pending = solver._start_adjoint() if solver.concurrent else None
-        u, st = solver.solver.solve_forward()
+        u, st = solver.solver.solve_forward(u0=solver._u_prev if solver.warm_start else None)
         solver.last_forward = st
+        if solver.warm_start:
+            solver._u_prev = u
         lam = None
         if pending is not None:
             lam, sa = pending.result()
@@ -59,9 +63,12 @@ class ThermalCompliance(torch.autograd.Function):
         if solver.version != ctx.version:
             solver._load_design(rho)
         if not ctx.has_lam:
-            lam, st = solver.solver.solve_adjoint()
+            lam, st = solver.solver.solve_adjoint(
+                l0=solver._lam_prev if solver.warm_start else None)
             solver.last_adjoint = st
             _check(st, "adjoint", solver.strict)
+            if solver.warm_start:
+                solver._lam_prev = lam
         g = solver.solver.gradient(u, lam)
         return grad_out * g, None
 
@@ -72,20 +79,25 @@ class ComplianceSolver:
     keeps the coarsening path fixed across designs, so the hierarchy never needs to be
     rebuilt."""
 
-    def __init__(self, problem: B.Problem, rho0: torch.Tensor, strict: bool = True,
-                 concurrent_adjoint: bool = True, **options):
+    def __init__(self, problem: B.Problem, rho0: torch.Tensor, q: torch.Tensor | None = None,
+                 strict: bool = True, concurrent_adjoint: bool = True,
+                 warm_start: bool = False, **options):
         options.setdefault("deff_mode", 1)
         rho0 = rho0.detach().to(torch.float64).contiguous()
         self.concurrent = concurrent_adjoint
         dev = rho0.device
         s1 = torch.cuda.Stream(device=dev) if concurrent_adjoint else None
         s2 = torch.cuda.Stream(device=dev) if concurrent_adjoint else None
-        self.solver = B.Solver(problem, rho0, stream=s1, **options)
-        self.adjoint_solver = B.Solver(problem, rho0, stream=s2, **options) if concurrent_adjoint else None
+        self.solver = B.Solver(problem, rho0, q=q, stream=s1, **options)
+        self.adjoint_solver = (B.Solver(problem, rho0, q=q, stream=s2, **options)
+                               if concurrent_adjoint else None)
         self._pool = ThreadPoolExecutor(max_workers=1) if concurrent_adjoint else None
         self.version = 0
         self._current = rho0.clone()
         self.strict = strict
+        self.warm_start = warm_start
+        self._u_prev = None
+        self._lam_prev = None
         self.last_forward = None
         self.last_adjoint = None
 
@@ -99,7 +111,13 @@ class ComplianceSolver:
         return self.version
 
     def _start_adjoint(self):
-        return self._pool.submit(self.adjoint_solver.solve_adjoint)
+        def run():
+            lam, st = self.adjoint_solver.solve_adjoint(
+                l0=self._lam_prev if self.warm_start else None)
+            if self.warm_start:
+                self._lam_prev = lam
+            return lam, st
+        return self._pool.submit(run)
 
     def __call__(self, rho: torch.Tensor) -> torch.Tensor:
         return ThermalCompliance.apply(rho, self)

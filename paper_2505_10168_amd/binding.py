@@ -77,6 +77,7 @@ def _load():
         "stmg_solve_adjoint": (I, [VP, VP, VP, VP, P(stmg_stats)]),
         "stmg_objective": (I, [VP, VP, P(D)]),
         "stmg_gradient": (I, [VP, VP, VP, VP]),
+        "stmg_oc_update": (I, [VP, VP, VP, D, D, D, D, VP]),
         "stmg_get_info": (I, [VP, P(stmg_info)]),
         "stmg_destroy": (I, [VP]),
         "stmg_level_apply": (I, [VP, I, I, VP, VP]),
@@ -101,6 +102,7 @@ lib = _load()
 EXPORTED = [
     "stmg_default_options", "stmg_footprint", "stmg_create", "stmg_set_design",
     "stmg_solve_forward", "stmg_solve_adjoint", "stmg_objective", "stmg_gradient",
+    "stmg_oc_update",
     "stmg_get_info", "stmg_destroy", "stmg_level_apply", "stmg_level_smooth",
     "stmg_level_presmooth_restrict", "stmg_level_prolong_postsmooth",
     "stmg_level_coarsest_solve", "stmg_vcycle", "stmg_status_string", "stmg_last_error",
@@ -181,6 +183,12 @@ def stmg_objective(h: int, u) -> float:
 
 def stmg_gradient(h: int, u, lam, grad) -> int:
     return _check(lib.stmg_gradient(h, _ptr(u), _ptr(lam), _ptr(grad)), "stmg_gradient")
+
+
+def stmg_oc_update(h: int, rho, grad, volume: float, move: float, eta: float, rho_min: float,
+                   rho_new) -> int:
+    return _check(lib.stmg_oc_update(h, _ptr(rho), _ptr(grad), volume, move, eta, rho_min,
+                                     _ptr(rho_new)), "stmg_oc_update")
 
 
 def stmg_get_info(h: int) -> stmg_info:
@@ -339,6 +347,12 @@ class Solver:
 
     def set_design(self, rho):
         stmg_set_design(self.handle, rho)
+
+    def oc_update(self, rho, grad, volume: float, move: float = 0.2, eta: float = 0.5,
+                  rho_min: float = 1e-3, out=None):
+        new = out if out is not None else self._torch.empty_like(rho)
+        stmg_oc_update(self.handle, rho, grad, volume, move, eta, rho_min, new)
+        return new
 
 
 def rel_err(a, b) -> float:

@@ -779,6 +779,84 @@ void launch_gradient_final(const double* parts, int N, int chunks, double* g, hi
                        chunks, g);
 }
 
+// =====================================================================================
+// Design update (optimisation problem of Section 7.1)
+// =====================================================================================
+
+// One workgroup: thread t owns elements t, t + kOcThreads, ...  Every sum and maximum
+// goes through the same fixed tree (butterfly inside a wave, then the 16 wave values
+// in order), so the bisection takes the same steps on every run.
+constexpr int kOcThreads = 1024;
+constexpr int kOcWaves = kOcThreads / 64;
+constexpr int kOcHalvings = 96;
+constexpr double kOcBracket = 1e40;
+
+__device__ __forceinline__ double oc_trial(double chi, double drive, double lam, double eta,
+                                           double lo, double hi) {
+    return fmin(fmax(chi * pow(drive / lam, eta), lo), hi);
+}
+
+// sum (MAX = false) or maximum (MAX = true) over the workgroup, returned to every
+// thread; sh[buf * kOcWaves ...] is written, so consecutive calls alternate buf
+template <bool MAX>
+__device__ __forceinline__ double oc_block_reduce(double v, double* sh, int buf) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o);
+        v = MAX ? fmax(v, w) : v + w;
+    }
+    if ((threadIdx.x & 63) == 0) sh[buf * kOcWaves + (threadIdx.x >> 6)] = v;
+    __syncthreads();
+    double r = sh[buf * kOcWaves];
+    for (int i = 1; i < kOcWaves; ++i) {
+        const double w = sh[buf * kOcWaves + i];
+        r = MAX ? fmax(r, w) : r + w;
+    }
+    return r;
+}
+
+// Optimality-criteria step: D = max(-g, 0), lo = max(chi_min, chi - move),
+// hi = min(1, chi + move), chi'(lam) = min(max(chi (D / lam)^eta, lo), hi), with lam
+// from kOcHalvings halvings of [maxD / kOcBracket, maxD kOcBracket] in log space,
+// stepping up while mean(chi'(lam)) exceeds the volume bound.  chi_new may alias chi:
+// a thread writes only its own elements, after its last read of them.
+__global__ __launch_bounds__(kOcThreads) void k_oc_update(const double* chi,
+                                                          const double* __restrict__ g, int n,
+                                                          double volume, double move,
+                                                          double eta, double chi_min,
+                                                          double* chi_new) {
+    __shared__ double sh[2 * kOcWaves];
+    const int t = threadIdx.x;
+    double dmax = 0.0;
+    for (int e = t; e < n; e += kOcThreads) dmax = fmax(dmax, fmax(-g[e], 0.0));
+    dmax = oc_block_reduce<true>(dmax, sh, 1);
+    const double scale = dmax > 0.0 ? dmax : 1.0;
+    double a = scale / kOcBracket, b = scale * kOcBracket;
+    for (int it = 0; it < kOcHalvings; ++it) {
+        const double mid = sqrt(a) * sqrt(b);
+        double s = 0.0;
+        for (int e = t; e < n; e += kOcThreads) {
+            const double c = chi[e];
+            s += oc_trial(c, fmax(-g[e], 0.0), mid, eta, fmax(chi_min, c - move),
+                          fmin(1.0, c + move));
+        }
+        s = oc_block_reduce<false>(s, sh, it & 1);
+        if (s / n > volume) a = mid;
+        else b = mid;
+    }
+    const double lam = sqrt(a) * sqrt(b);
+    for (int e = t; e < n; e += kOcThreads) {
+        const double c = chi[e];
+        chi_new[e] = oc_trial(c, fmax(-g[e], 0.0), lam, eta, fmax(chi_min, c - move),
+                              fmin(1.0, c + move));
+    }
+}
+
+void launch_oc_update(const double* chi, const double* g, int n, double volume, double move,
+                      double eta, double chi_min, double* chi_new, hipStream_t s) {
+    hipLaunchKernelGGL(k_oc_update, dim3(1), dim3(kOcThreads), 0, s, chi, g, n, volume, move,
+                       eta, chi_min, chi_new);
+}
+
 // ---- explicit instantiations ---------------------------------------------------------
 template void launch_fill<double>(double*, int64_t, double, hipStream_t);
 template void launch_fill<float>(float*, int64_t, float, hipStream_t);

@@ -1153,6 +1153,19 @@ int stmg_gradient(stmg_t h, const double* d_u, const double* d_lambda, double* d
     return 0;
 }
 
+int stmg_oc_update(stmg_t h, const double* d_rho, const double* d_grad, double volume,
+                   double move, double eta, double rho_min, double* d_rho_new) {
+    if (!h || !d_rho || !d_grad || !d_rho_new) return fail(STMG_EINVAL, "null argument");
+    if (!(volume > 0.0 && volume <= 1.0) || !(move > 0.0) || !(eta > 0.0 && eta <= 1.0) ||
+        !(rho_min >= 0.0 && rho_min < 1.0))
+        return fail(STMG_EINVAL, "design update needs 0 < volume <= 1, move > 0, "
+                                 "0 < eta <= 1 and 0 <= rho_min < 1");
+    launch_oc_update(d_rho, d_grad, h->p.n_el, volume, move, eta, rho_min, d_rho_new, h->s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
 int stmg_get_info(stmg_t h, stmg_info* info) {
     if (!h || !info) return fail(STMG_EINVAL, "null argument");
     std::memset(info, 0, sizeof(*info));

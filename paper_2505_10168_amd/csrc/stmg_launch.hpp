@@ -89,6 +89,9 @@ void launch_gradient_partial(const double* u, const double* lam, int N, int Nt, 
                              double tau, double* parts, hipStream_t s);
 void launch_gradient_final(const double* parts, int N, int chunks, double* grad,
                            hipStream_t s);
+// optimality-criteria design update (one workgroup); chi_new may alias chi
+void launch_oc_update(const double* chi, const double* grad, int n, double volume, double move,
+                      double eta, double chi_min, double* chi_new, hipStream_t s);
 
 // ---- fused streaming kernels ----------------------------------------------------------
 // Pass descriptor of one fused streaming launch on a level.

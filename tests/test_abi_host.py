@@ -86,5 +86,6 @@ def test_null_arguments():
     assert B.lib.stmg_default_options(None) == B.STMG_EINVAL
     assert B.lib.stmg_solve_forward(None, None, None, None, None) == B.STMG_EINVAL
     assert B.lib.stmg_objective(None, None, None) == B.STMG_EINVAL
+    assert B.lib.stmg_oc_update(None, None, None, 0.5, 0.2, 0.5, 1e-3, None) == B.STMG_EINVAL
     assert B.lib.stmg_destroy(None) == 0
     assert B.lib.stmg_status_string(B.STMG_DIVERGED) == b"diverged"

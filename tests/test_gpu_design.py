@@ -1,0 +1,130 @@
+"""GPU tests of the design update (stmg_oc_update) and of the Section 7 design loop:
+the update against the oracle's on the same inputs, every cycle of the loop against
+the oracle's Theta, gradient and update at the same design, and warm restarts."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.helpers import rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+SECTION7_MATERIAL = O.Material(0.197, 214.0, 1.67e6, 2.41e6)
+
+
+def oc_case(n, kind, seed):
+    rng = np.random.default_rng(seed)
+    chi = rng.uniform(0.0, 1.0, n)
+    chi[rng.integers(0, n, max(n // 20, 1))] = 0.0
+    chi[rng.integers(0, n, max(n // 20, 1))] = 1.0
+    g = -10 ** rng.uniform(-4, 0, n)
+    vol = float(np.clip(chi.mean(), 0.05, 1.0))
+    if kind == "mixed_sign":
+        g[rng.integers(0, n, max(n // 10, 1))] = 1e-3
+    elif kind == "inactive":
+        vol = 1.0
+    elif kind == "no_drive":
+        g = np.abs(g)
+    return chi, g, vol
+
+
+@pytest.mark.parametrize("n", [1, 5, 1000, 8192, 65537])
+@pytest.mark.parametrize("kind", ["active", "mixed_sign", "inactive", "no_drive"])
+def test_oc_update_matches_oracle(n, kind, cuda):
+    from paper_2505_10168_amd import binding as B
+    chi, g, vol = oc_case(n, kind, seed=n + len(kind))
+    s = B.Solver(B.Problem(n, 2), to_dev(np.full(n, 0.5), cuda))
+    for move, eta, cmin in [(0.2, 0.5, 1e-3), (0.05, 0.3, 0.0)]:
+        got = to_np(s.oc_update(to_dev(chi, cuda), to_dev(g, cuda), vol, move, eta, cmin))
+        ref = O.oc_update(chi, g, vol, move, eta, cmin)
+        err = float(np.abs(got - ref).max())
+        print(f"n {n} {kind} move {move} eta {eta}: max |gpu - oracle| {err:.2e}")
+        assert err <= 1e-12
+    # in place (output aliases the design)
+    x = to_dev(chi, cuda)
+    s.oc_update(x, to_dev(g, cuda), vol, out=x)
+    assert float(np.abs(to_np(x) - O.oc_update(chi, g, vol)).max()) <= 1e-12
+    s.close()
+
+
+def test_oc_update_rejects_bad_parameters(cuda):
+    from paper_2505_10168_amd import binding as B
+    s = B.Solver(B.Problem(8, 2), to_dev(np.full(8, 0.5), cuda))
+    x, g = to_dev(np.full(8, 0.5), cuda), to_dev(-np.ones(8), cuda)
+    for vol, move, eta, cmin in [(0.0, 0.2, 0.5, 0.0), (1.5, 0.2, 0.5, 0.0),
+                                 (0.5, 0.0, 0.5, 0.0), (0.5, 0.2, 0.0, 0.0),
+                                 (0.5, 0.2, 1.5, 0.0), (0.5, 0.2, 0.5, 1.0)]:
+        with pytest.raises(B.StmgError):
+            s.oc_update(x, g, vol, move, eta, cmin)
+    s.close()
+
+
+def section7_loop(cuda, n=256, warm=True, **kw):
+    from paper_2505_10168_amd.design import SECTION7_OPTIONS, DesignLoop, section7_problem
+    prob, q = section7_problem(n, n)
+    loop = DesignLoop(prob, to_dev(np.full(n, 0.5), cuda), 0.5, q=to_dev(q, cuda),
+                      warm_start=warm, **SECTION7_OPTIONS, **kw)
+    return loop, q
+
+
+def test_design_loop_cycles_match_oracle(cuda):
+    n = 256
+    loop, q = section7_loop(cuda, n)
+    thetas = []
+    for k in range(6):
+        chi = to_np(loop.rho)
+        loop.step()
+        g = to_np(loop.last_gradient)
+        th_ref, g_ref = O.theta_and_gradient(chi, SECTION7_MATERIAL, n, 0.1, 10.0, q, 1e6)
+        new_ref = O.oc_update(chi, g, 0.5)
+        th = loop.history.theta[-1]
+        print(f"cycle {k}: theta {th:.12e} (oracle {th_ref:.12e}) grad rel {rel(g, g_ref):.2e} "
+              f"cycles {loop.history.forward_cycles[-1]}/{loop.history.adjoint_cycles[-1]}")
+        assert th == pytest.approx(th_ref, rel=1e-9)
+        assert rel(g, g_ref) <= 1e-8
+        assert float(np.abs(to_np(loop.rho) - new_ref).max()) <= 1e-12
+        assert abs(to_np(loop.rho).mean() - 0.5) <= 1e-12
+        # the paper's robustness claim for this problem: fewer than 80 cycles per solve
+        assert loop.history.forward_cycles[-1] < 80 and loop.history.adjoint_cycles[-1] < 80
+        thetas.append(th)
+    assert all(b < a for a, b in zip(thetas, thetas[1:]))
+    loop.close()
+
+
+def test_design_loop_runs_to_the_stopping_rule_like_the_oracle(cuda):
+    n = 256
+    loop, q = section7_loop(cuda, n)
+    hist = loop.run(80)
+    designs, thetas = O.design_loop(np.full(n, 0.5), SECTION7_MATERIAL, n, 0.1, 10.0, q, 1e6,
+                                    0.5, 80)
+    m = min(len(thetas), len(hist.theta))
+    drift = max(abs(a - b) / abs(b) for a, b in zip(hist.theta[:m], thetas[:m]))
+    print(f"gpu {len(hist.theta)} cycles, oracle {len(thetas)}; final theta "
+          f"{hist.theta[-1]:.10f} / {thetas[-1]:.10f}; max theta drift {drift:.2e}; "
+          f"solve cycles max {max(hist.forward_cycles)}/{max(hist.adjoint_cycles)}")
+    # every solve stops at a relative residual below 1e-10, so Theta and the gradient
+    # carry errors of about that size; 29 OC steps amplify them little (6.8e-13 seen)
+    assert hist.converged and len(hist.theta) == len(thetas)
+    assert drift <= 1e-8
+    assert hist.theta[-1] == pytest.approx(thetas[-1], rel=1e-8)
+    loop.close()
+
+
+def test_warm_restarts_cut_cycles_and_keep_the_designs(cuda):
+    runs = {}
+    for warm in (False, True):
+        loop, _ = section7_loop(cuda, 256, warm=warm)
+        loop.run(8)
+        runs[warm] = (loop.history, to_np(loop.rho))
+        loop.close()
+    (hc, rc), (hw, rw) = runs[False], runs[True]
+    cold = sum(hc.forward_cycles[1:]) + sum(hc.adjoint_cycles[1:])
+    warm = sum(hw.forward_cycles[1:]) + sum(hw.adjoint_cycles[1:])
+    print(f"cycles after the first design: cold {cold}, warm {warm}; "
+          f"design diff {np.abs(rc - rw).max():.2e}")
+    assert hc.forward_cycles[0] == hw.forward_cycles[0]
+    assert warm < cold
+    assert float(np.abs(rc - rw).max()) <= 1e-8
+    assert max(abs(a - b) / b for a, b in zip(hc.theta, hw.theta)) <= 1e-9
