@@ -265,6 +265,9 @@ def main():
     ap.add_argument("--fused", type=int, default=1)
     ap.add_argument("--interp", default="C", choices=["C", "B"],
                     help="interpolation in time: causal (C, the paper's default) or bilinear (B)")
+    ap.add_argument("--reassembly", default="R", choices=["R", "K", "D", "P"],
+                    help="coarse operators: resistivity (R, default), conductivity (K) or "
+                         "design-field (D) averaging, or Galerkin products (P)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--sequential", action="store_true",
                     help="run the forward and adjoint solves of a step one after the other "
@@ -311,7 +314,8 @@ def main():
     s_fwd = torch.cuda.Stream(device=dev) if concurrent else None
     s_adj = torch.cuda.Stream(device=dev) if concurrent else None
     opts = dict(nu=nu, precision=precision, fused=args.fused, time_kernels=TIMED_EVERY,
-                interp=B.STMG_INTERP_B if args.interp == "B" else B.STMG_INTERP_C)
+                interp=B.STMG_INTERP_B if args.interp == "B" else B.STMG_INTERP_C,
+                reassembly="RKDP".index(args.reassembly))
     solver = B.Solver(prob, rho, stream=s_fwd, **opts)
     adj_solver = B.Solver(prob, rho, stream=s_adj, **opts) if concurrent else solver
     pool = ThreadPoolExecutor(max_workers=2) if concurrent else None
@@ -378,7 +382,7 @@ def main():
         "config": {
             "workload": args.workload, "n_el": w.n_el, "n_t": w.n_t, "dofs": w.dofs,
             "kappa_min": w.kappa_min, "nu": nu, "tol": 1e-10, "precision": args.precision,
-            "interp": args.interp,
+            "interp": args.interp, "reassembly": args.reassembly,
             "path": info["path"], "levels": info["n_levels"],
             "step": "reassemble + forward solve" + ("" if args.no_adjoint else
                                                   " + adjoint solve + gradient") + " + objective",

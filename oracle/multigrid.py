@@ -234,7 +234,8 @@ def restrict(fine: Level, direction: str, r: np.ndarray, interp: str = "C") -> n
 # Galerkin reassembly (P method)
 # --------------------------------------------------------------------------------------
 
-def _sparse_J(level: Level, transpose: bool = False) -> sp.csr_matrix:
+def _sparse_J_by_columns(level: Level, transpose: bool = False) -> sp.csr_matrix:
+    """J as a sparse matrix, one application of J per unit vector (tiny grids)."""
     n = dofs(level)
     cols = []
     for j in range(n):
@@ -242,6 +243,34 @@ def _sparse_J(level: Level, transpose: bool = False) -> sp.csr_matrix:
         e[j] = 1.0
         cols.append(sp.csr_matrix(apply_J(level, e.reshape(level.shape), transpose).reshape(-1, 1)))
     return sp.hstack(cols).tocsr()
+
+
+def _sparse_J(level: Level, transpose: bool = False) -> sp.csr_matrix:
+    """J as a sparse matrix from 9 applications of J.  Row (n, i) of J (and of J^T)
+    involves only columns (n + dt, i + dx) with |dt|, |dx| <= 1, so the unit vectors
+    of all DOFs (m, j) with m = a, j = b (mod 3) have images that do not overlap:
+    applying J to their sum gives column (m, j) in the rows (m + dt, j + dx)."""
+    nt1, n1 = level.shape
+    rows, cols, vals = [], [], []
+    for a in range(3):
+        for b in range(3):
+            e = np.zeros(level.shape)
+            e[a::3, b::3] = 1.0
+            y = apply_J(level, e, transpose)
+            m, j = np.meshgrid(np.arange(a, nt1, 3), np.arange(b, n1, 3), indexing="ij")
+            m, j = m.ravel(), j.ravel()
+            for dt in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    r, c = m + dt, j + dx
+                    ok = (r >= 0) & (r < nt1) & (c >= 0) & (c < n1)
+                    v = y[r[ok], c[ok]]
+                    nz = v != 0.0
+                    rows.append((r[ok] * n1 + c[ok])[nz])
+                    cols.append((m[ok] * n1 + j[ok])[nz])
+                    vals.append(v[nz])
+    n = nt1 * n1
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n, n))
 
 
 def _galerkin_operators(h: Hierarchy):

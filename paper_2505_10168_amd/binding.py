@@ -21,7 +21,7 @@ LIB_PATH = Path(os.environ.get("STMG_LIBRARY") or
 
 STMG_OK, STMG_NOT_CONVERGED, STMG_DIVERGED = 0, 1, 2
 STMG_EINVAL, STMG_ENOMEM, STMG_EHIP, STMG_EUNSUPPORTED = -1, -2, -3, -4
-STMG_REASSEMBLE_R, STMG_REASSEMBLE_K, STMG_REASSEMBLE_D = 0, 1, 2
+STMG_REASSEMBLE_R, STMG_REASSEMBLE_K, STMG_REASSEMBLE_D, STMG_REASSEMBLE_P = 0, 1, 2, 3
 STMG_INTERP_C, STMG_INTERP_B = 0, 1
 STMG_FP64, STMG_MIXED = 0, 1
 STMG_MAX_HISTORY = 1024

@@ -58,6 +58,8 @@ struct Level {
     float* coef32 = nullptr;
     double* thomas = nullptr;  // coarsest: cp, inv, rhs scratch (3 (N+1))
     double* ainv = nullptr;    // coarsest with N <= kDenseCoarsestMax: A^{-1}, N x N
+    double* sten = nullptr;    // Galerkin levels: 9-point stencil, 9 elems()
+    double* sfac = nullptr;    // coarsest Galerkin level: Thomas factors, 4 elems()
     double* u = nullptr;
     double* b = nullptr;
     double* t = nullptr;
@@ -68,6 +70,10 @@ struct Level {
     int64_t elems() const { return (int64_t)(Nt + 1) * P; }
     int64_t dofs() const { return dofs_of(N, Nt); }
 };
+
+StencilView stencil_view(const Level& l) {
+    return StencilView{l.N, l.Nt, l.P, l.elems(), l.sten};
+}
 
 template <typename T> T*& U(Level& l);
 template <typename T> T*& B(Level& l);
@@ -196,7 +202,10 @@ int validate(const stmg_problem* p, const stmg_options* o) {
     if (o->min_coarse_dofs < 1) return fail(STMG_EINVAL, "min_coarse_dofs must be >= 1");
     if (o->max_cycles < 1 || o->max_cycles > STMG_MAX_HISTORY)
         return fail(STMG_EINVAL, "max_cycles must be in [1, STMG_MAX_HISTORY]");
-    if (o->reassembly < 0 || o->reassembly > 2) return fail(STMG_EINVAL, "unknown reassembly method");
+    if (o->reassembly < 0 || o->reassembly > 3) return fail(STMG_EINVAL, "unknown reassembly method");
+    if (o->reassembly == STMG_REASSEMBLE_P &&
+        (o->interp != STMG_INTERP_C || o->precision != STMG_FP64))
+        return fail(STMG_EINVAL, "Galerkin reassembly needs causal interpolation and FP64");
     if (o->deff_mode < 0 || o->deff_mode > 1) return fail(STMG_EINVAL, "unknown deff_mode");
     if (o->precision != STMG_FP64 && o->precision != STMG_MIXED)
         return fail(STMG_EINVAL, "unknown precision");
@@ -216,9 +225,11 @@ bool can_t(int Nt) { return Nt % 2 == 0 && Nt >= 2; }
 // vector, so that one V-cycle can run while the previous one's residual is checked
 bool pipelined_options(const stmg_options* o) { return o->precision == STMG_FP64 && o->fused != 0; }
 
-size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest, bool pipelined) {
+size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest, bool pipelined,
+                   bool galerkin) {
     const int64_t P = pitch_for(N), E = (int64_t)(Nt + 1) * P;
     size_t b = 3 * (size_t)N * 8 + kCoefArrays * (size_t)(N + 1) * 8;
+    if (galerkin && !fine) b += (9 + (coarsest ? 4 : 0)) * (size_t)E * 8;
     if (precision == STMG_MIXED) b += kCoefArrays * (size_t)(N + 1) * 4;
     if (coarsest) b += 3 * (size_t)(N + 1) * 8 + (N <= kDenseCoarsestMax ? (size_t)N * N * 8 : 0);
     if (precision == STMG_FP64 || fine) b += 3 * (size_t)E * 8;
@@ -253,7 +264,8 @@ size_t footprint_of(const stmg_problem* p, const stmg_options* o) {
                 else if (want == 't' && !can_t(Nt)) want = can_x(N) ? 'x' : 0;
                 if (!want) last = true;
             }
-            total += level_bytes(N, Nt, o->precision, lev == 1, last, pipelined_options(o));
+            total += level_bytes(N, Nt, o->precision, lev == 1, last, pipelined_options(o),
+                                 o->reassembly == STMG_REASSEMBLE_P);
             if (last) break;
             if (want == 'x') { N /= 2; h *= 2; } else { Nt /= 2; tau *= 2; }
             ++lev;
@@ -271,7 +283,9 @@ size_t footprint_of(const stmg_problem* p, const stmg_options* o) {
         for (auto& f : frontier) {
             bool last = o->max_levels ? (lev == o->max_levels) : (dofs_of(f.N, f.Nt) <= o->min_coarse_dofs);
             if (!last && !can_x(f.N) && !can_t(f.Nt)) last = true;
-            worst = std::max(worst, level_bytes(f.N, f.Nt, o->precision, lev == 1, true, pipelined_options(o)));
+            worst = std::max(worst, level_bytes(f.N, f.Nt, o->precision, lev == 1, true,
+                                                pipelined_options(o),
+                                                o->reassembly == STMG_REASSEMBLE_P));
             if (!last) {
                 any_continue = true;
                 if (can_x(f.N)) next.push_back({f.N / 2, f.Nt});
@@ -356,7 +370,8 @@ int coarse_coefficients(stmg_ctx* h, const Level& f, char dir, Level& c) {
         HIPCHK(hipMemcpyAsync(c.chi, f.chi, (size_t)f.N * 8, hipMemcpyDeviceToDevice, h->s));
         return 0;
     }
-    const int method = h->o.reassembly == STMG_REASSEMBLE_R ? 0 : (h->o.reassembly == STMG_REASSEMBLE_K ? 1 : 2);
+    // P keeps K-averaged k and c as the proxy that steers the coarsening decision
+    const int method = h->o.reassembly == STMG_REASSEMBLE_R ? 0 : (h->o.reassembly == STMG_REASSEMBLE_D ? 2 : 1);
     launch_coarsen_x(f.k, f.c, f.chi, c.N, method, h->simp, c.k, c.c, c.chi, h->s);
     HIPCHK(hipGetLastError());
     return 0;
@@ -380,6 +395,7 @@ int finish_level(stmg_ctx* h, Level& l, bool coarsest) {
 void plan_tail(stmg_ctx* h) {
     h->tail_start = -1;
     if (h->o.interp != STMG_INTERP_C) return;   // the tail kernel transfers causally
+    if (h->o.reassembly == STMG_REASSEMBLE_P) return;   // it rediscretises every level
     const int nl = (int)h->L.size();
     const Level& c = h->L[nl - 1];
     if (nl < 3 || !c.ainv || c.N > kTailMaxCoarsestN) return;
@@ -407,6 +423,21 @@ void plan_tail(stmg_ctx* h) {
     if (tail_prepare<double>(best_bytes, c.N) != 0 || tail_prepare<float>(best_bytes, c.N) != 0) return;
     h->tail_start = best;
     h->tail_lds = best_bytes;
+}
+
+// Galerkin operators of levels 1 .. coarsest (Section 5.1, P method), each from the
+// level above, and the time-stepping factors of the coarsest one.
+int galerkin_levels(stmg_ctx* h) {
+    const size_t nl = h->L.size();
+    for (size_t i = 0; i + 1 < nl; ++i) {
+        const Level& f = h->L[i];
+        Level& c = h->L[i + 1];
+        launch_galerkin(view<double>(f, h->o.omega), i == 0 ? nullptr : f.sten, f.dir, h->o.interp,
+                        c.N, c.Nt, c.P, c.sten, h->s);
+    }
+    if (nl > 1) launch_stencil_thomas(stencil_view(h->L[nl - 1]), h->L[nl - 1].sfac, h->s);
+    HIPCHK(hipGetLastError());
+    return 0;
 }
 
 int build(stmg_ctx* h, const double* d_q) {
@@ -456,6 +487,14 @@ int build(stmg_ctx* h, const double* d_q) {
         if (h->o.precision == STMG_MIXED) CHK(h->alloc(&l.coef32, kCoefArrays * (int64_t)(l.N + 1)));
         if (last) CHK(h->alloc(&l.thomas, 3 * (int64_t)(l.N + 1)));
         if (last && l.N <= kDenseCoarsestMax) CHK(h->alloc(&l.ainv, (int64_t)l.N * l.N));
+        if (h->o.reassembly == STMG_REASSEMBLE_P && !fine) {
+            if (last && l.N + 1 > kStencilCoarsestMaxNodes)
+                return fail(STMG_EUNSUPPORTED, "Galerkin coarsest level wider than " +
+                                                   std::to_string(kStencilCoarsestMaxNodes) +
+                                                   " nodes (allow more levels)");
+            CHK(h->alloc(&l.sten, 9 * l.elems()));
+            if (last) CHK(h->alloc(&l.sfac, 4 * l.elems()));
+        }
         if (h->o.precision == STMG_FP64 || fine) {
             CHK(h->alloc(&l.u, l.elems()));
             CHK(h->alloc(&l.b, l.elems()));
@@ -469,6 +508,7 @@ int build(stmg_ctx* h, const double* d_q) {
         }
         CHK(finish_level(h, l, last));
     }
+    if (h->o.reassembly == STMG_REASSEMBLE_P) CHK(galerkin_levels(h));
     Level& fl = h->L[0];
     CHK(h->alloc(&h->bload, fl.elems()));
     launch_load_vector(d_q, p.q_uniform, fl.N, fl.Nt, fl.h, h->bload, fl.P, h->s);
@@ -522,11 +562,32 @@ std::vector<int> chunks_of(int nu) {
     return c;
 }
 
+// nu damped Jacobi steps on a Galerkin level (stored stencil), in place
+void stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu) {
+    const StencilView S = stencil_view(lv);
+    for (int k = 0; k < nu; ++k) {
+        launch_apply_stencil(S, trans, APPLY_JACOBI, h->o.omega, lv.u, lv.b, lv.t,
+                             zero_start && k == 0, h->s);
+        std::swap(lv.u, lv.t);
+    }
+    if (nu == 0 && zero_start) launch_fill<double>(lv.u, lv.elems(), 0.0, h->s);
+}
+
 template <typename T>
 int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) {
     Level& lv = h->L[l];
     Level& cl = h->L[l + 1];
     const auto V = view<T>(lv, h->o.omega);
+    if constexpr (std::is_same<T, double>::value) {
+        if (lv.sten) {
+            stencil_smooth(h, lv, trans, zero_start, nu);
+            launch_apply_stencil(stencil_view(lv), trans, APPLY_RESIDUAL, h->o.omega, lv.u, lv.b,
+                                 lv.t, false, h->s);
+            launch_restrict<double>(lv.dir, V, lv.t, cl.b, cl.P, h->s, h->o.interp);
+            HIPCHK(hipGetLastError());
+            return 0;
+        }
+    }
     T*& u = U<T>(lv);
     T* b = B<T>(lv);
     T*& t = Tt<T>(lv);
@@ -593,6 +654,15 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
     const T* z = U<T>(cl);
     const bool timed = l == 0 && h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
     const bool split = lv.dir == 't' && h->o.interp == STMG_INTERP_B;
+    if constexpr (std::is_same<T, double>::value) {
+        if (lv.sten) {
+            // norms are taken on the finest level only, which is never a stencil level
+            launch_prolong_add<double>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
+            stencil_smooth(h, lv, trans, false, nu);
+            HIPCHK(hipGetLastError());
+            return 0;
+        }
+    }
     if (h->o.fused) {
         if (split) launch_prolong_add<T>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
         std::vector<int> ch = chunks_of(nu);
@@ -634,6 +704,13 @@ template <typename T>
 int coarsest_solve(stmg_ctx* h, int l, int trans) {
     Level& lv = h->L[l];
     const auto V = view<double>(lv, h->o.omega);
+    if constexpr (std::is_same<T, double>::value) {
+        if (lv.sten) {
+            launch_stencil_coarsest(stencil_view(lv), lv.sfac, trans, lv.b, lv.u, h->s);
+            HIPCHK(hipGetLastError());
+            return 0;
+        }
+    }
     if (lv.ainv)
         launch_coarsest_dense<T>(V, lv.ainv, B<T>(lv), U<T>(lv), trans, h->s);
     else
@@ -1013,6 +1090,7 @@ int reassemble(stmg_ctx* h, bool check_path) {
         l.W = level_w(h->o, l, st);
         CHK(finish_level(h, l, i + 1 == h->L.size()));
     }
+    if (h->o.reassembly == STMG_REASSEMBLE_P) CHK(galerkin_levels(h));
     HIPCHK(hipStreamSynchronize(h->s));
     return 0;
 }
@@ -1197,7 +1275,12 @@ int stmg_level_apply(stmg_t h, int level, int transpose, const double* d_x, doub
     if (!d_x || !d_y) return fail(STMG_EINVAL, "null vector");
     Level& l = h->L[level];
     CHK(copy_in(h, l, d_x, l.u));
-    launch_apply<double>(view<double>(l, h->o.omega), transpose, APPLY_J, l.u, l.b, l.t, false, h->s);
+    if (l.sten)
+        launch_apply_stencil(stencil_view(l), transpose, APPLY_J, h->o.omega, l.u, l.b, l.t, false,
+                             h->s);
+    else
+        launch_apply<double>(view<double>(l, h->o.omega), transpose, APPLY_J, l.u, l.b, l.t, false,
+                             h->s);
     CHK(copy_out(h, l, l.t, d_y));
     HIPCHK(hipStreamSynchronize(h->s));
     return 0;
@@ -1210,7 +1293,9 @@ int stmg_level_smooth(stmg_t h, int level, int transpose, int nu, const double* 
     CHK(copy_in(h, l, d_b, l.b));
     CHK(copy_in(h, l, d_u, l.u));
     const auto V = view<double>(l, h->o.omega);
-    if (h->o.fused) {
+    if (l.sten) {
+        stencil_smooth(h, l, transpose, false, nu);
+    } else if (h->o.fused) {
         for (int S : chunks_of(nu)) {
             FusedPass fp{};
             fp.trans = transpose;

@@ -93,6 +93,29 @@ void launch_gradient_final(const double* parts, int N, int chunks, double* grad,
 void launch_oc_update(const double* chi, const double* grad, int n, double volume, double move,
                       double eta, double chi_min, double* chi_new, hipStream_t s);
 
+// ---- Galerkin levels (P reassembly): stored 9-point stencils ---------------------------
+// 9 arrays of E = (Nt+1) P doubles; array 3 (dt+1) + (dx+1) holds the coefficient of
+// x(n+dt, i+dx) in row (n, i)
+struct StencilView {
+    int N;
+    int Nt;
+    int64_t P;
+    int64_t E;
+    const double* s;
+};
+// widest coarsest stencil level the time-stepping solve takes (nodes per time level)
+constexpr int kStencilCoarsestMaxNodes = 1536;
+// cs = stencil of R J P for the level below F: F's rediscretised operator when fs is
+// null, else F's stored stencil fs
+void launch_galerkin(const LevelView<double>& F, const double* fs, char dir, int interp,
+                     int Nc, int Ntc, int64_t Pc, double* cs, hipStream_t s);
+void launch_apply_stencil(const StencilView& S, int trans, int mode, double omega, const double* x,
+                          const double* b, double* y, bool zero_in, hipStream_t s);
+// factors: 4 arrays of E doubles (cp, inv of J's blocks, then of J^T's)
+void launch_stencil_thomas(const StencilView& S, double* factors, hipStream_t s);
+void launch_stencil_coarsest(const StencilView& S, const double* factors, int trans,
+                             const double* b, double* z, hipStream_t s);
+
 // ---- fused streaming kernels ----------------------------------------------------------
 // Pass descriptor of one fused streaming launch on a level.
 struct FusedPass {

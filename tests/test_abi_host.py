@@ -89,3 +89,13 @@ def test_null_arguments():
     assert B.lib.stmg_oc_update(None, None, None, 0.5, 0.2, 0.5, 1e-3, None) == B.STMG_EINVAL
     assert B.lib.stmg_destroy(None) == 0
     assert B.lib.stmg_status_string(B.STMG_DIVERGED) == b"diverged"
+
+
+def test_galerkin_needs_causal_interpolation_and_fp64():
+    p = B.Problem(16, 16).c_struct()
+    for extra in ({"interp": B.STMG_INTERP_B}, {"precision": B.STMG_MIXED}):
+        o = B.make_options(reassembly=B.STMG_REASSEMBLE_P, **extra)
+        h = C.c_void_p()
+        rc = B.lib.stmg_create(C.byref(h), C.byref(p), C.byref(o), C.c_void_p(1), None, None)
+        assert rc == B.STMG_EINVAL
+        assert b"Galerkin" in B.lib.stmg_last_error()

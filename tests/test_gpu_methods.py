@@ -1,0 +1,51 @@
+"""The comparisons of Section 5.2 on problem 7 (L = 0.1 m, 256 x 256, t_T = 10 s,
+Table 3 materials, ramp design alpha = 5/L, the Section 3.1 heat load; nu = 5,
+lambda_crit = 0.25, stop at r < 1e-9): the estimated convergence factors of the
+rediscretisation methods as the number of levels grows."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from tests.helpers import I, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def factors(cuda, methods, levels):
+    from paper_2505_10168_amd import binding as B
+    n, L = 256, 0.1
+    prob = B.Problem(n, n, length=L, t_final=10.0, k_ins=0.197, k_con=214.0, c_ins=1.67e6,
+                     c_con=2.41e6, theta_ref=1e6)
+    rho = to_dev(I.ramp_design(n, L, 5.0 / L, L / 2), cuda)
+    q = to_dev(I.paper_heat_load(n, n, L, 10.0), cuda)
+    out = {}
+    for m in methods:
+        for nl in levels:
+            s = B.Solver(prob, rho, q=q, nu=5, lambda_crit=0.25, max_levels=nl, tol=1e-9,
+                         max_cycles=100, reassembly="RKDP".index(m[1]),
+                         interp=B.STMG_INTERP_B if m[0] == "B" else B.STMG_INTERP_C)
+            _, st = s.solve_forward()
+            assert st.status == 0, (m, nl, st.status)
+            out[m, nl] = st.conv_factor
+            s.close()
+    return out
+
+
+def test_rediscretisation_methods_on_problem7(cuda):
+    methods = ["CR", "CK", "CD", "CP", "BR", "BK", "BD"]
+    f = factors(cuda, methods, [4, 5, 6, 8])
+    for nl in (4, 5, 6, 8):
+        print(nl, {m: round(f[m, nl], 4) for m in methods})
+    # up to 5 levels the methods are nearly identical
+    for nl in (4, 5):
+        v = [f[m, nl] for m in methods]
+        assert max(v) - min(v) < 0.02
+    # from 6 levels on, bilinear interpolation is noticeably worse than causal
+    for nl in (6, 8):
+        assert min(f["B" + r, nl] for r in "RKD") > max(f["C" + r, nl] for r in "RKDP") + 0.05
+    # the reassembly method has only a minor impact
+    for nl in (4, 5, 6, 8):
+        for i in "CB":
+            v = [f[i + r, nl] for r in ("RKDP" if i == "C" else "RKD")]
+            assert max(v) - min(v) < 0.02

@@ -234,6 +234,8 @@ VARIANTS = [
     ("deff_simp", "ramp_300x256", {"deff_mode": 1}, {"deff_mode": "simp"}),
     ("B_block", "block_256x600", {"interp": 1}, {"interp": "B"}),
     ("B_ramp", "ramp_300x256", {"interp": 1}, {"interp": "B"}),
+    ("P_block", "block_256x600", {"reassembly": 3}, {"reassembly": "P"}),
+    ("P_ramp", "ramp_300x256", {"reassembly": 3}, {"reassembly": "P"}),
 ]
 
 
@@ -281,3 +283,63 @@ def test_bilinear_fused_and_reference_identical(transpose, cuda):
             B.stmg_vcycle(s.handle, transpose, bd, ud)
         outs.append(to_np(ud))
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("name", ["block_256x600", "ramp_300x256"])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_galerkin_levels_match_oracle(name, transpose, cuda):
+    """P reassembly: every coarse operator R J P (stored stencil) applied, and the
+    coarsest level solved by time stepping, against the oracle's sparse products."""
+    import scipy.sparse.linalg as spla
+
+    from paper_2505_10168_amd import binding as B
+    s, _, lv, h = make_pair(name, cuda, reassembly=B.STMG_REASSEMBLE_P)
+    h = O.build_hierarchy(lv, O.Options(material=h.opts.material, nu=h.opts.nu, reassembly="P"))
+    info = s.info()
+    assert info["path"] == h.path and info["tail_level"] == -1
+    rng = np.random.default_rng(4)
+    for l in range(1, info["n_levels"]):
+        G = h.galerkin[l].T if transpose else h.galerkin[l]
+        shape = h.levels[l].shape
+        x = rng.standard_normal(shape)
+        y = to_dev(np.zeros(shape), cuda)
+        B.stmg_level_apply(s.handle, l, transpose, to_dev(x, cuda), y)
+        ref = (G @ x.ravel()).reshape(shape)
+        print(f"level {l} {shape}: apply rel {rel(to_np(y), ref):.1e}")
+        assert rel(to_np(y), ref) <= 1e-13
+    last = info["n_levels"] - 1
+    G = (h.galerkin[last].T if transpose else h.galerkin[last]).tocsc()
+    b = rng.standard_normal(h.levels[last].shape)
+    z = to_dev(np.zeros(b.shape), cuda)
+    B.stmg_level_coarsest_solve(s.handle, transpose, to_dev(b, cuda), z)
+    ref = spla.spsolve(G, b.ravel()).reshape(b.shape)
+    print(f"coarsest {b.shape}: rel {rel(to_np(z), ref):.1e}")
+    assert rel(to_np(z), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_galerkin_fused_and_reference_identical_and_solve(transpose, cuda):
+    """P reassembly: the fine level's fused passes and its one-kernel-per-step path give
+    the same iterates; the solve reaches the direct solution."""
+    from paper_2505_10168_amd import binding as B
+    outs = []
+    for fused in (1, 0):
+        s, _, lv, h = make_pair("block_256x600", cuda, fused=fused, reassembly=B.STMG_REASSEMBLE_P)
+        b = O.load_vector(lv, 1.0)
+        if transpose:
+            b = O.adjoint_rhs(lv, b)
+        bd, ud = to_dev(b, cuda), to_dev(np.zeros(lv.shape), cuda)
+        for _ in range(3):
+            B.stmg_vcycle(s.handle, transpose, bd, ud)
+        outs.append(to_np(ud))
+    assert np.array_equal(outs[0], outs[1])
+    s, _, lv, h = make_pair("block_256x600", cuda, reassembly=B.STMG_REASSEMBLE_P, max_cycles=300)
+    b = O.load_vector(lv, 1.0)
+    if transpose:
+        b = O.adjoint_rhs(lv, b)
+    u, st = (s.solve_adjoint if transpose else s.solve_forward)(to_dev(b, cuda))
+    ref = O.direct_solve(lv, b, transpose=bool(transpose))
+    print(f"P solve: {st.cycles} cycles, residual {st.rel_residual:.2e}, "
+          f"factor {st.conv_factor:.3f}, rel err {rel(to_np(u), ref):.1e}")
+    assert st.status == 0 and st.rel_residual < 1e-10
+    assert rel(to_np(u), ref) <= 1e-8

@@ -505,3 +505,47 @@ def test_two_grid_uniform_x_versus_t():
         f = {p: two_grid_factor(lv, p, cycles=8) for p in "xtf"}
         assert min(f, key=lambda p: f[p]) in (winner, "f") and f[winner] <= f["f"] + 1e-12
         assert f[winner] < f["t" if winner == "x" else "x"]
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_probed_sparse_J_equals_column_by_column_assembly(transpose):
+    from oracle.multigrid import _sparse_J, _sparse_J_by_columns
+    for n_el, n_t, seed in [(5, 7, 1), (8, 3, 2), (1, 2, 3)]:
+        lv = random_level(n_el, n_t, seed)
+        A = _sparse_J(lv, transpose).toarray()
+        B = _sparse_J_by_columns(lv, transpose).toarray()
+        assert np.array_equal(A, B)
+        assert np.array_equal(A, O.dense_J(lv, transpose))
+
+
+def _problem7_level():
+    m = GOLD["table3_materials"]["value"]
+    mat = O.Material(m["k_ins"], m["k_con"], m["c_ins"], m["c_con"])
+    chi = I.ramp_design(256, 0.1, 5.0 / 0.1, 0.05)
+    lv = O.make_fine_level(chi, mat, 256, 0.1, 10.0)
+    return mat, lv, O.load_vector(lv, I.paper_heat_load(256, 256, 0.1, 10.0))
+
+
+def test_bp_method_blows_up_on_problem7_as_printed():
+    """Galerkin coarse operators with bilinear time interpolation (BP, Section 5.2):
+    stable up to 4 levels, diverging beyond, and the printed factor at 10 levels.  A
+    wrong Galerkin product, transfer or restriction scale moves these by orders of
+    magnitude."""
+    g = GOLD["bp_problem7"]["value"]
+    mat, lv, b = _problem7_level()
+
+    def factor(nl, interp="B"):
+        h = O.build_hierarchy(lv, O.Options(material=mat, nu=5, lambda_crit=0.25, max_levels=nl,
+                                            interp=interp, reassembly="P", tol=1e-9,
+                                            max_cycles=100))
+        return O.stmg_solve(h, b)
+
+    stable = factor(g["last_stable_levels"])
+    assert stable.status == "converged" and stable.conv_factor < 0.6
+    assert factor(g["last_stable_levels"] + 1).status == "diverged"
+    blown = factor(10)
+    assert blown.status == "diverged"
+    assert blown.conv_factor == pytest.approx(g["factor_at_10_levels"], rel=g["rel_tol"])
+    # the causal Galerkin method (CP) stays stable on the same path
+    cp = factor(10, interp="C")
+    assert cp.status == "converged" and cp.conv_factor < 0.6
