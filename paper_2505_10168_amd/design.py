@@ -74,7 +74,7 @@ class DesignLoop:
         h = self.history
         if self.designs is not None:
             self.designs.append(self.rho.clone())
-        h.theta.append(float(theta))
+        h.theta.append(float(theta.detach()))
         h.volume.append(float(self.rho.mean()))
         h.forward_cycles.append(self.compliance.last_forward.cycles)
         h.adjoint_cycles.append(self.compliance.last_adjoint.cycles)

@@ -343,3 +343,50 @@ def test_galerkin_fused_and_reference_identical_and_solve(transpose, cuda):
           f"factor {st.conv_factor:.3f}, rel err {rel(to_np(u), ref):.1e}")
     assert st.status == 0 and st.rel_residual < 1e-10
     assert rel(to_np(u), ref) <= 1e-8
+
+
+GALERKIN_EDGE = [
+    # (id, rho, n_t, kappa_min, extra options)
+    ("odd_x_75x64", I.block_density(75, 5, seed=3), 64, 1e-2, {}),
+    ("one_level", I.block_density(64, 8, seed=5), 64, 1e-3, {"max_levels": 1}),
+    ("two_grid", I.block_density(64, 8, seed=5), 64, 1e-3, {"max_levels": 2}),
+    ("tiny_2x2", np.array([0.3, 0.9]), 2, 1e-2, {"max_levels": 2}),
+    ("single_element_1x8", np.array([0.7]), 8, 1e-2, {"max_levels": 3}),
+]
+
+
+@pytest.mark.parametrize("case", GALERKIN_EDGE, ids=[c[0] for c in GALERKIN_EDGE])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_galerkin_edge_cases(case, transpose, cuda):
+    """P reassembly on grids that cannot halve, with one or two levels, and on the
+    smallest grids: path and V-cycle iterates against the oracle."""
+    from paper_2505_10168_amd import binding as B
+    _, rho, n_t, kmin, extra = case
+    prob = B.Problem(len(rho), n_t, k_ins=kmin)
+    s = B.Solver(prob, to_dev(rho, cuda), nu=2, reassembly=B.STMG_REASSEMBLE_P, **extra)
+    mat, lv, h = oracle_setup(rho, n_t, kmin, nu=2, reassembly="P", **extra)
+    assert s.info()["path"] == h.path
+    b = O.load_vector(lv, 1.0)
+    if transpose:
+        b = O.adjoint_rhs(lv, b)
+    u = np.zeros(lv.shape)
+    ud, bd = to_dev(u, cuda), to_dev(b, cuda)
+    for it in range(3):
+        B.stmg_vcycle(s.handle, transpose, bd, ud)
+        u = O.vcycle(h, 0, u, b, bool(transpose))
+        assert rel(to_np(ud), u) <= 1e-12, (it, rel(to_np(ud), u))
+    s.close()
+
+
+def test_galerkin_one_level_equals_rediscretised(cuda):
+    """With a single level there is no coarse operator: P and R solve the same way."""
+    from paper_2505_10168_amd import binding as B
+    rho = I.block_density(64, 8, seed=5)
+    prob = B.Problem(64, 64, k_ins=1e-3)
+    outs = []
+    for method in (B.STMG_REASSEMBLE_R, B.STMG_REASSEMBLE_P):
+        s = B.Solver(prob, to_dev(rho, cuda), max_levels=1, reassembly=method)
+        u, st = s.solve_forward()
+        outs.append(to_np(u))
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
