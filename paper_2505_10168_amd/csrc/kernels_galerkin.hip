@@ -1,13 +1,16 @@
 // Galerkin coarse operators (P reassembly, Section 5.1): J^(l+1) = R^(l) J^(l) P^(l).
 //
 // With the semi-coarsening transfers of Section 3.1 / 5.1 the product of two 3 x 3
-// space-time stencils stays 3 x 3, so every Galerkin level is stored as a 9-point
-// stencil: 9 arrays of (Nt+1) x P doubles in the level's vector layout, array
-// k = 3 (dt + 1) + (dx + 1) holding at (n, i) the coefficient of x(n + dt, i + dx) in
-// row (n, i).  Coefficients that would reach outside the grid are zero.  These levels
-// are smoothed, applied and restricted one thread per DOF; with the causal transfers
-// no row couples to a later time level, so the coarsest level is solved by time
-// stepping with one tridiagonal solve per time level.
+// space-time stencils stays 3 x 3, so every Galerkin level is a 9-point stencil: array
+// k = 3 (dt + 1) + (dx + 1) holds at (n, i) the coefficient of x(n + dt, i + dx) in row
+// (n, i); coefficients that would reach outside the grid are zero.  The operators do
+// not depend on the time level except near the first and last levels, so a level
+// stores only its R distinct stencil rows (R is 3 or 4 in practice) and a map from
+// time level to stored row; all time levels of a row class are built by the same
+// arithmetic from the same inputs and are therefore exactly equal.  These levels are
+// smoothed, applied and restricted one thread per DOF; with the causal transfers no
+// row couples to a later time level, so the coarsest level is solved by time stepping
+// with one tridiagonal solve per time level.
 #include <hip/hip_runtime.h>
 
 #include "stmg_launch.hpp"
@@ -68,15 +71,20 @@ __device__ __forceinline__ double rediscretised_entry(const LevelView<double>& V
 
 // Coarse stencil of row (J, I): s sum_a sum_b P_{a,(J,I)} J_{a,b} P_{b,(J',I')}, i.e.
 // R = s P^T applied to the fine rows a that (J, I) prolongs to.  The fine operator is
-// the rediscretised one (fs == nullptr) or a stored stencil.  All weights are powers
-// of two, so each term is exact and only the order of the sum is a choice: fine rows
-// in time-major order, then the fine stencil in array order, then the parents.
-__global__ void k_galerkin(LevelView<double> F, const double* __restrict__ fs, int kt, int kx,
-                           double s, int Nc, int Ntc, int64_t Pc, double* __restrict__ cs) {
+// the rediscretised one (fs == nullptr) or a stored stencil with row map frow and
+// array stride FE.  One stored coarse row r is formed from its representative time
+// level J = crep[r].  All weights are powers of two, so each term is exact and only
+// the order of the sum is a choice: fine rows in time-major order, then the fine
+// stencil in array order, then the parents.
+__global__ void k_galerkin(LevelView<double> F, const double* __restrict__ fs,
+                           const int* __restrict__ frow, int64_t FE, int kt, int kx, double s,
+                           int Nc, int Ntc, int64_t Pc, int Rc, const int* __restrict__ crep,
+                           double* __restrict__ cs) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I > Nc) return;
-    const int64_t FE = (int64_t)(F.Nt + 1) * F.P, CE = (int64_t)(Ntc + 1) * Pc;
-    for (int J = blockIdx.y; J <= Ntc; J += gridDim.y) {
+    const int64_t CE = (int64_t)Rc * Pc;
+    for (int r = blockIdx.y; r < Rc; r += gridDim.y) {
+        const int J = crep[r];
         double acc[9];
         for (int k = 0; k < 9; ++k) acc[k] = 0.0;
         const Tap ct = children(kt, J, F.Nt), cx = children(kx, I, F.N);
@@ -89,7 +97,7 @@ __global__ void k_galerkin(LevelView<double> F, const double* __restrict__ fs, i
                     const int dt = k / 3 - 1, dx = k % 3 - 1;
                     const int bt = ft + dt, bx = fx + dx;
                     if (bt < 0 || bt > F.Nt || bx < 0 || bx > F.N) continue;
-                    const double v = fs ? fs[k * FE + (int64_t)ft * F.P + fx]
+                    const double v = fs ? fs[k * FE + (int64_t)frow[ft] * F.P + fx]
                                         : rediscretised_entry(F, ft, fx, dt, dx);
                     if (v == 0.0) continue;
                     const Tap pt = parents(kt, bt), px = parents(kx, bx);
@@ -105,17 +113,19 @@ __global__ void k_galerkin(LevelView<double> F, const double* __restrict__ fs, i
                 }
             }
         }
-        for (int k = 0; k < 9; ++k) cs[k * CE + (int64_t)J * Pc + I] = acc[k];
+        for (int k = 0; k < 9; ++k) cs[k * CE + (int64_t)r * Pc + I] = acc[k];
     }
 }
 
-void launch_galerkin(const LevelView<double>& F, const double* fs, char dir, int interp,
-                     int Nc, int Ntc, int64_t Pc, double* cs, hipStream_t s) {
+void launch_galerkin(const LevelView<double>& F, const StencilView* fsv, char dir, int interp,
+                     const StencilView& C, const int* crep, double* cs, hipStream_t s) {
     const int kt = dir == 't' ? (interp == 1 ? 1 : 2) : 0;
     const int kx = dir == 'x' ? 1 : 0;
     const double sc = dir == 't' ? 0.5 : 1.0;
-    dim3 g(blocks_for(Nc + 1), rows_grid(Ntc + 1));
-    hipLaunchKernelGGL(k_galerkin, g, dim3(kBlock), 0, s, F, fs, kt, kx, sc, Nc, Ntc, Pc, cs);
+    dim3 g(blocks_for(C.N + 1), rows_grid(C.R));
+    hipLaunchKernelGGL(k_galerkin, g, dim3(kBlock), 0, s, F, fsv ? fsv->s : nullptr,
+                       fsv ? fsv->row : nullptr, fsv ? fsv->E : 0, kt, kx, sc, C.N, C.Nt, C.P,
+                       C.R, crep, cs);
 }
 
 // y = J x, b - J x or x + omega (b - J x) / J_ii with a stored stencil.  The transpose
@@ -128,13 +138,15 @@ __global__ void k_apply_stencil(StencilView S, int mode, double omega, const dou
     const int64_t P = S.P, E = S.E;
     for (int n = blockIdx.y; n <= S.Nt; n += gridDim.y) {
         const int64_t o = (int64_t)n * P + i;
+        const int64_t co = (int64_t)S.row[n] * P + i;   // this row's coefficients
         double Jx = 0.0;
         if (!zero_in) {
             for (int k = 0; k < 9; ++k) {
                 const int nn = n + k / 3 - 1, ii = i + k % 3 - 1;
                 if (nn < 0 || nn > S.Nt || ii < 0 || ii > S.N) continue;
                 const int64_t q = (int64_t)nn * P + ii;
-                const double c = TR ? S.s[(8 - k) * E + q] : S.s[k * E + o];
+                const double c = TR ? S.s[(8 - k) * E + (int64_t)S.row[nn] * P + ii]
+                                    : S.s[k * E + co];
                 Jx = __builtin_fma(c, x[q], Jx);
             }
         }
@@ -143,7 +155,7 @@ __global__ void k_apply_stencil(StencilView S, int mode, double omega, const dou
         } else {
             const double r = b[o] - Jx;
             if (mode == APPLY_RESIDUAL) y[o] = r;
-            else y[o] = (zero_in ? 0.0 : x[o]) + omega * r / S.s[4 * E + o];
+            else y[o] = (zero_in ? 0.0 : x[o]) + omega * r / S.s[4 * E + co];
         }
     }
 }
@@ -159,15 +171,124 @@ void launch_apply_stencil(const StencilView& S, int trans, int mode, double omeg
                            (int)zero_in);
 }
 
-// Thomas factors of the tridiagonal block of every time level (nodes 0..N), for J
+// ---- fused Jacobi passes on a stencil level ------------------------------------------
+// S damped Jacobi steps in one pass that streams through time (forward for J, backward
+// for J^T): step k at time level n needs step k-1 at levels n and n -/+ 1, both already
+// in registers.  One wave owns a strip of 64 - 2 S useful columns (one per lane, S halo
+// lanes per side: each step spoils one more column from the strip's edge) and a
+// segment of time levels, started S levels early (the warm-up rows: a step that lacks
+// its earlier-level input is wrong only on the first levels it sees).  Neighbouring
+// columns are exchanged between lanes.  The terms of J x are added in the order of
+// k_apply_stencil, so this pass and S one-step launches give the same values.
+constexpr int kStencilWave = 64;
+constexpr int kStencilWavesPerBlock = 4;
+
+__device__ __forceinline__ double lane_from_left(double v) {   // value of lane - 1, 0 at lane 0
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x138, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x138, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double lane_from_right(double v) {  // value of lane + 1, 0 at lane 63
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x130, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x130, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int TR, int S>
+__global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stencil_fused(
+    StencilView V, double omega, const double* __restrict__ u, const double* __restrict__ b,
+    double* __restrict__ out, int zero_in, int xw, int seg, int nwaves) {
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kStencilWavesPerBlock +
+                                                    (int)(threadIdx.x >> 6));
+    if (wave >= nwaves) return;
+    const int lane = threadIdx.x & (kStencilWave - 1);
+    const int U = kStencilWave - 2 * S;
+    const int wx = wave % xw, wt = wave / xw;
+    const int i = wx * U - S + lane;                  // this lane's column
+    const bool valid = i >= 0 && i <= V.N;
+    const bool useful = valid && lane >= S && lane < kStencilWave - S;
+    const int64_t P = V.P, E = V.E;
+    const int n0 = wt * seg, n1 = min(V.Nt + 1, n0 + seg);   // output levels [n0, n1)
+    const int first = TR ? min(V.Nt, n1 - 1 + S) : max(0, n0 - S);
+    const int count = TR ? first - n0 + 1 : n1 - first;
+
+    double prev[S + 1];
+#pragma unroll
+    for (int k = 0; k <= S; ++k) prev[k] = 0.0;
+    // coefficients of the current row class: J: (row n: dt = -1 at dx = -1, 0, 1, then
+    // dt = 0); J^T: (row n at columns i-1, i, i+1, then row n+1 at i-1, i, i+1)
+    double c[6] = {0, 0, 0, 0, 0, 0}, diag = 1.0;
+    int key = -1;
+    for (int it = 0; it < count; ++it) {
+        const int n = TR ? first - it : first + it;
+        const int rn = V.row[n];
+        const int rk = TR ? (n < V.Nt ? V.row[n + 1] : -1) : 0;
+        const int nk = rn * 64 + (rk + 1);
+        if (nk != key) {   // wave-uniform: the row class changes only near the ends
+            key = nk;
+            const int64_t cr = (int64_t)rn * P;
+            if (TR) {
+                const int64_t nr = (int64_t)(rk < 0 ? 0 : rk) * P;
+                const bool l = valid && i >= 1, r = valid && i + 1 <= V.N;
+                c[0] = l ? V.s[5 * E + cr + i - 1] : 0.0;
+                c[1] = valid ? V.s[4 * E + cr + i] : 0.0;
+                c[2] = r ? V.s[3 * E + cr + i + 1] : 0.0;
+                c[3] = (l && rk >= 0) ? V.s[2 * E + nr + i - 1] : 0.0;
+                c[4] = (valid && rk >= 0) ? V.s[1 * E + nr + i] : 0.0;
+                c[5] = (r && rk >= 0) ? V.s[0 * E + nr + i + 1] : 0.0;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) c[k] = valid ? V.s[k * E + cr + i] : 0.0;
+            }
+            diag = valid ? V.s[4 * E + cr + i] : 1.0;
+        }
+        const int64_t o = (int64_t)n * P + i;
+        double cur = (valid && !zero_in) ? u[o] : 0.0;
+        const double bb = valid ? b[o] : 0.0;
+        const double x0 = cur;
+#pragma unroll
+        for (int k = 1; k <= S; ++k) {
+            const double xm = lane_from_left(cur), xp = lane_from_right(cur);
+            const double pm = lane_from_left(prev[k - 1]), pp = lane_from_right(prev[k - 1]);
+            double acc = 0.0;
+            if (TR) {   // level n first, then level n + 1
+                acc = __builtin_fma(c[0], xm, acc);
+                acc = __builtin_fma(c[1], cur, acc);
+                acc = __builtin_fma(c[2], xp, acc);
+                acc = __builtin_fma(c[3], pm, acc);
+                acc = __builtin_fma(c[4], prev[k - 1], acc);
+                acc = __builtin_fma(c[5], pp, acc);
+            } else {    // level n - 1 first, then level n
+                acc = __builtin_fma(c[0], pm, acc);
+                acc = __builtin_fma(c[1], prev[k - 1], acc);
+                acc = __builtin_fma(c[2], pp, acc);
+                acc = __builtin_fma(c[3], xm, acc);
+                acc = __builtin_fma(c[4], cur, acc);
+                acc = __builtin_fma(c[5], xp, acc);
+            }
+            const double r = bb - acc;
+            const double y = valid ? cur + omega * r / diag : 0.0;
+            prev[k - 1] = cur;
+            cur = y;
+        }
+        prev[S] = cur;
+        (void)x0;
+        if (useful && n >= n0 && n < n1) out[o] = cur;
+    }
+}
+
+// Thomas factors of the tridiagonal block of every stored row (nodes 0..N), for J
 // (lo = array 3, up = array 5 of the row) and for J^T (lo_i = array 5 of row i - 1,
 // up_i = array 3 of row i + 1): cp_i = up_i / den_i, inv_i = 1 / den_i with
-// den_0 = di_0, den_i = di_i - lo_i cp_{i-1}.  One thread per time level and matrix.
+// den_0 = di_0, den_i = di_i - lo_i cp_{i-1}.  One thread per stored row and matrix;
+// factor arrays have the stencil's layout (row r at r P).
 __global__ void k_stencil_thomas(StencilView S, double* __restrict__ f) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n > 2 * S.Nt + 1) return;
-    const int tr = n > S.Nt;
-    const int m = tr ? n - S.Nt - 1 : n;
+    if (n >= 2 * S.R) return;
+    const int tr = n >= S.R;
+    const int m = tr ? n - S.R : n;
     const int64_t E = S.E, row = (int64_t)m * S.P;
     double* cp = f + (tr ? 2 : 0) * E + row;
     double* inv = f + (tr ? 3 : 1) * E + row;
@@ -186,9 +307,46 @@ __global__ void k_stencil_thomas(StencilView S, double* __restrict__ f) {
     }
 }
 
+template <int TR, int S>
+void launch_stencil_fused_s(const StencilView& V, double omega, const double* u, const double* b,
+                            double* out, bool zero_in, hipStream_t s) {
+    const int U = kStencilWave - 2 * S;
+    const int xw = (V.N + 1 + U - 1) / U;
+    const int64_t rows = V.Nt + 1;
+    // about 4096 waves, and segments of at least 4 S levels so that the warm-up rows
+    // stay a fraction of the work
+    int64_t seg = (rows * xw + 4095) / 4096;
+    if (seg < 4 * S) seg = 4 * S;
+    if (seg > rows) seg = rows;
+    const int nw = (int)(xw * ((rows + seg - 1) / seg));
+    const int blocks = (nw + kStencilWavesPerBlock - 1) / kStencilWavesPerBlock;
+    hipLaunchKernelGGL((k_stencil_fused<TR, S>), dim3(blocks),
+                       dim3(kStencilWave * kStencilWavesPerBlock), 0, s, V, omega, u, b, out,
+                       (int)zero_in, xw, (int)seg, nw);
+}
+
+template <int TR>
+void launch_stencil_fused_t(const StencilView& V, int sweeps, double omega, const double* u,
+                            const double* b, double* out, bool zero_in, hipStream_t s) {
+    switch (sweeps) {
+        case 1: launch_stencil_fused_s<TR, 1>(V, omega, u, b, out, zero_in, s); break;
+        case 2: launch_stencil_fused_s<TR, 2>(V, omega, u, b, out, zero_in, s); break;
+        case 3: launch_stencil_fused_s<TR, 3>(V, omega, u, b, out, zero_in, s); break;
+        case 4: launch_stencil_fused_s<TR, 4>(V, omega, u, b, out, zero_in, s); break;
+        case 5: launch_stencil_fused_s<TR, 5>(V, omega, u, b, out, zero_in, s); break;
+        default: launch_stencil_fused_s<TR, 6>(V, omega, u, b, out, zero_in, s); break;
+    }
+}
+
+void launch_stencil_fused(const StencilView& V, int trans, int sweeps, double omega, const double* u,
+                          const double* b, double* out, bool zero_in, hipStream_t s) {
+    if (trans) launch_stencil_fused_t<1>(V, sweeps, omega, u, b, out, zero_in, s);
+    else launch_stencil_fused_t<0>(V, sweeps, omega, u, b, out, zero_in, s);
+}
+
 void launch_stencil_thomas(const StencilView& S, double* factors, hipStream_t s) {
-    hipLaunchKernelGGL(k_stencil_thomas, dim3(blocks_for(2 * (int64_t)S.Nt + 2)), dim3(kBlock), 0,
-                       s, S, factors);
+    hipLaunchKernelGGL(k_stencil_thomas, dim3(blocks_for(2 * (int64_t)S.R)), dim3(kBlock), 0, s,
+                       S, factors);
 }
 
 // Exact solve on a stencil level whose rows couple only to their own and the previous
@@ -208,24 +366,26 @@ __global__ __launch_bounds__(kStencilSolveThreads) void k_stencil_coarsest(
     const double* finv = f + (trans ? 3 : 1) * E;
     for (int step = 0; step <= S.Nt; ++step) {
         const int n = trans ? S.Nt - step : step;
-        const int64_t row = (int64_t)n * P;
+        const int64_t row = (int64_t)n * P;                 // vectors
+        const int64_t crow = (int64_t)S.row[n] * P;         // coefficients and factors
         for (int i = threadIdx.x; i <= S.N; i += blockDim.x) {
             double v = b[row + i];
             if (!trans && n >= 1) {
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int j = i + dx;
-                    if (j >= 0 && j <= S.N) v -= S.s[(dx + 1) * E + row + i] * z[row - P + j];
+                    if (j >= 0 && j <= S.N) v -= S.s[(dx + 1) * E + crow + i] * z[row - P + j];
                 }
             } else if (trans && n < S.Nt) {
+                const int64_t nrow = (int64_t)S.row[n + 1] * P;
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int j = i + dx;
-                    if (j >= 0 && j <= S.N) v -= S.s[(1 - dx) * E + row + P + j] * z[row + P + j];
+                    if (j >= 0 && j <= S.N) v -= S.s[(1 - dx) * E + nrow + j] * z[row + P + j];
                 }
             }
             r[i] = v;
-            lo[i] = i == 0 ? 0.0 : (trans ? S.s[5 * E + row + i - 1] : S.s[3 * E + row + i]);
-            cp[i] = fcp[row + i];
-            inv[i] = finv[row + i];
+            lo[i] = i == 0 ? 0.0 : (trans ? S.s[5 * E + crow + i - 1] : S.s[3 * E + crow + i]);
+            cp[i] = fcp[crow + i];
+            inv[i] = finv[crow + i];
         }
         __syncthreads();
         if (threadIdx.x == 0) {

@@ -10,6 +10,7 @@
 #include <string>
 #include <type_traits>
 #include <utility>
+#include <array>
 #include <atomic>
 #include <vector>
 
@@ -41,6 +42,7 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr int kCoefArrays = 9;   // lo, di, up, mlo, mdi, mup, wd, kl, kr
+constexpr int kStencilRowsBound = 8;   // footprint bound of stored Galerkin stencil rows
 
 int64_t pitch_for(int N) { return ((int64_t)N + 4 + 31) / 32 * 32; }
 int64_t dofs_of(int N, int Nt) { return (int64_t)(N + 1) * (Nt + 1); }
@@ -58,8 +60,12 @@ struct Level {
     float* coef32 = nullptr;
     double* thomas = nullptr;  // coarsest: cp, inv, rhs scratch (3 (N+1))
     double* ainv = nullptr;    // coarsest with N <= kDenseCoarsestMax: A^{-1}, N x N
-    double* sten = nullptr;    // Galerkin levels: 9-point stencil, 9 elems()
-    double* sfac = nullptr;    // coarsest Galerkin level: Thomas factors, 4 elems()
+    double* sten = nullptr;    // Galerkin levels: 9-point stencil, 9 arrays of R rows of P
+    double* sfac = nullptr;    // coarsest Galerkin level: Thomas factors, 4 arrays of R P
+    int R = 0;                 // stored stencil rows
+    int* srow = nullptr;       // device: time level -> stored row (Nt+1)
+    int* srep = nullptr;       // device: stored row -> its representative time level (R)
+    std::vector<int> hrow, hrep;   // host copies
     double* u = nullptr;
     double* b = nullptr;
     double* t = nullptr;
@@ -72,7 +78,34 @@ struct Level {
 };
 
 StencilView stencil_view(const Level& l) {
-    return StencilView{l.N, l.Nt, l.P, l.elems(), l.sten};
+    return StencilView{l.N, l.Nt, l.P, l.R, (int64_t)l.R * l.P, l.srow, l.sten};
+}
+
+// Stored-row classes of a Galerkin level.  A coarse row's stencil is fixed by the
+// stored rows of the fine rows it is formed from and by which of its neighbours fall
+// outside the grid; time levels with the same such signature get exactly equal
+// stencils and share one stored row.  The rediscretised fine level has three classes:
+// time level 0 (Dirichlet), 1 (no coupling to level 0) and the rest.
+void stencil_rows(const std::vector<int>& frow, int Nt, char dir, std::vector<int>& row,
+                  std::vector<int>& rep) {
+    const int Ntc = dir == 't' ? Nt / 2 : Nt;
+    std::vector<std::array<int, 4>> sigs;
+    row.assign(Ntc + 1, 0);
+    rep.clear();
+    for (int J = 0; J <= Ntc; ++J) {
+        std::array<int, 4> sig;
+        if (dir == 't')
+            sig = {frow[2 * J], 2 * J + 1 <= Nt ? frow[2 * J + 1] : -1, J == 0, 2 * J + 2 > Nt};
+        else
+            sig = {frow[J], -1, J == 0, J == Ntc};
+        size_t r = 0;
+        while (r < sigs.size() && sigs[r] != sig) ++r;
+        if (r == sigs.size()) {
+            sigs.push_back(sig);
+            rep.push_back(J);
+        }
+        row[J] = (int)r;
+    }
 }
 
 template <typename T> T*& U(Level& l);
@@ -229,7 +262,10 @@ size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest, bool 
                    bool galerkin) {
     const int64_t P = pitch_for(N), E = (int64_t)(Nt + 1) * P;
     size_t b = 3 * (size_t)N * 8 + kCoefArrays * (size_t)(N + 1) * 8;
-    if (galerkin && !fine) b += (9 + (coarsest ? 4 : 0)) * (size_t)E * 8;
+    // stored stencil rows: at most kStencilRowsBound (3 or 4 in practice)
+    if (galerkin && !fine)
+        b += (9 + (coarsest ? 4 : 0)) * (size_t)std::min(Nt + 1, kStencilRowsBound) * P * 8 +
+             (size_t)(Nt + 1 + kStencilRowsBound) * 4;
     if (precision == STMG_MIXED) b += kCoefArrays * (size_t)(N + 1) * 4;
     if (coarsest) b += 3 * (size_t)(N + 1) * 8 + (N <= kDenseCoarsestMax ? (size_t)N * N * 8 : 0);
     if (precision == STMG_FP64 || fine) b += 3 * (size_t)E * 8;
@@ -432,8 +468,9 @@ int galerkin_levels(stmg_ctx* h) {
     for (size_t i = 0; i + 1 < nl; ++i) {
         const Level& f = h->L[i];
         Level& c = h->L[i + 1];
-        launch_galerkin(view<double>(f, h->o.omega), i == 0 ? nullptr : f.sten, f.dir, h->o.interp,
-                        c.N, c.Nt, c.P, c.sten, h->s);
+        const StencilView fs = stencil_view(f);
+        launch_galerkin(view<double>(f, h->o.omega), i == 0 ? nullptr : &fs, f.dir, h->o.interp,
+                        stencil_view(c), c.srep, c.sten, h->s);
     }
     if (nl > 1) launch_stencil_thomas(stencil_view(h->L[nl - 1]), h->L[nl - 1].sfac, h->s);
     HIPCHK(hipGetLastError());
@@ -487,13 +524,27 @@ int build(stmg_ctx* h, const double* d_q) {
         if (h->o.precision == STMG_MIXED) CHK(h->alloc(&l.coef32, kCoefArrays * (int64_t)(l.N + 1)));
         if (last) CHK(h->alloc(&l.thomas, 3 * (int64_t)(l.N + 1)));
         if (last && l.N <= kDenseCoarsestMax) CHK(h->alloc(&l.ainv, (int64_t)l.N * l.N));
+        if (h->o.reassembly == STMG_REASSEMBLE_P && fine) {
+            l.hrow.assign(l.Nt + 1, 2);
+            l.hrow[0] = 0;
+            if (l.Nt >= 1) l.hrow[1] = 1;
+        }
         if (h->o.reassembly == STMG_REASSEMBLE_P && !fine) {
             if (last && l.N + 1 > kStencilCoarsestMaxNodes)
                 return fail(STMG_EUNSUPPORTED, "Galerkin coarsest level wider than " +
                                                    std::to_string(kStencilCoarsestMaxNodes) +
                                                    " nodes (allow more levels)");
-            CHK(h->alloc(&l.sten, 9 * l.elems()));
-            if (last) CHK(h->alloc(&l.sfac, 4 * l.elems()));
+            const Level& f = h->L[i - 1];
+            stencil_rows(f.hrow, f.Nt, f.dir, l.hrow, l.hrep);
+            l.R = (int)l.hrep.size();
+            CHK(h->alloc(&l.sten, 9 * (int64_t)l.R * l.P));
+            if (last) CHK(h->alloc(&l.sfac, 4 * (int64_t)l.R * l.P));
+            CHK(h->alloc(&l.srow, (int64_t)l.Nt + 1));
+            CHK(h->alloc(&l.srep, (int64_t)l.R));
+            HIPCHK(hipMemcpyAsync(l.srow, l.hrow.data(), l.hrow.size() * sizeof(int),
+                                  hipMemcpyHostToDevice, h->s));
+            HIPCHK(hipMemcpyAsync(l.srep, l.hrep.data(), l.hrep.size() * sizeof(int),
+                                  hipMemcpyHostToDevice, h->s));
         }
         if (h->o.precision == STMG_FP64 || fine) {
             CHK(h->alloc(&l.u, l.elems()));
@@ -562,13 +613,22 @@ std::vector<int> chunks_of(int nu) {
     return c;
 }
 
-// nu damped Jacobi steps on a Galerkin level (stored stencil), in place
+// nu damped Jacobi steps on a Galerkin level (stored stencil), in place: streaming
+// passes of up to kStencilMaxFused steps with the fused kernels, else one launch per step
 void stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu) {
     const StencilView S = stencil_view(lv);
-    for (int k = 0; k < nu; ++k) {
-        launch_apply_stencil(S, trans, APPLY_JACOBI, h->o.omega, lv.u, lv.b, lv.t,
-                             zero_start && k == 0, h->s);
+    bool zero = zero_start;
+    int left = nu;
+    while (left > 0) {
+        const int passes = (left + kStencilMaxFused - 1) / kStencilMaxFused;
+        const int k = h->o.fused ? (left + passes - 1) / passes : 1;
+        if (h->o.fused)
+            launch_stencil_fused(S, trans, k, h->o.omega, lv.u, lv.b, lv.t, zero, h->s);
+        else
+            launch_apply_stencil(S, trans, APPLY_JACOBI, h->o.omega, lv.u, lv.b, lv.t, zero, h->s);
         std::swap(lv.u, lv.t);
+        zero = false;
+        left -= k;
     }
     if (nu == 0 && zero_start) launch_fill<double>(lv.u, lv.elems(), 0.0, h->s);
 }

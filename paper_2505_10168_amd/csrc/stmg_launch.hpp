@@ -94,24 +94,32 @@ void launch_oc_update(const double* chi, const double* grad, int n, double volum
                       double eta, double chi_min, double* chi_new, hipStream_t s);
 
 // ---- Galerkin levels (P reassembly): stored 9-point stencils ---------------------------
-// 9 arrays of E = (Nt+1) P doubles; array 3 (dt+1) + (dx+1) holds the coefficient of
-// x(n+dt, i+dx) in row (n, i)
+// 9 arrays of E = R P doubles (R stored rows of P); array 3 (dt+1) + (dx+1) holds at
+// (row[n], i) the coefficient of x(n+dt, i+dx) in row (n, i)
 struct StencilView {
     int N;
     int Nt;
     int64_t P;
-    int64_t E;
+    int R;           // stored rows
+    int64_t E;       // R P
+    const int* row;  // Nt+1 entries: time level -> stored row
     const double* s;
 };
 // widest coarsest stencil level the time-stepping solve takes (nodes per time level)
 constexpr int kStencilCoarsestMaxNodes = 1536;
-// cs = stencil of R J P for the level below F: F's rediscretised operator when fs is
-// null, else F's stored stencil fs
-void launch_galerkin(const LevelView<double>& F, const double* fs, char dir, int interp,
-                     int Nc, int Ntc, int64_t Pc, double* cs, hipStream_t s);
+// cs = stored rows of R J P for the level below F (shape C, representative time level
+// crep[r] for stored row r): from F's rediscretised operator when fsv is null, else from
+// F's stored stencil
+void launch_galerkin(const LevelView<double>& F, const StencilView* fsv, char dir, int interp,
+                     const StencilView& C, const int* crep, double* cs, hipStream_t s);
 void launch_apply_stencil(const StencilView& S, int trans, int mode, double omega, const double* x,
                           const double* b, double* y, bool zero_in, hipStream_t s);
-// factors: 4 arrays of E doubles (cp, inv of J's blocks, then of J^T's)
+// `sweeps` (1..kStencilMaxFused) damped Jacobi steps in one streaming pass, u -> out
+// (distinct buffers); the same values as `sweeps` launches of launch_apply_stencil
+constexpr int kStencilMaxFused = 6;
+void launch_stencil_fused(const StencilView& V, int trans, int sweeps, double omega, const double* u,
+                          const double* b, double* out, bool zero_in, hipStream_t s);
+// factors: 4 arrays of E doubles (cp, inv of J's blocks, then of J^T's), per stored row
 void launch_stencil_thomas(const StencilView& S, double* factors, hipStream_t s);
 void launch_stencil_coarsest(const StencilView& S, const double* factors, int trans,
                              const double* b, double* z, hipStream_t s);
