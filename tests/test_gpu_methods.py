@@ -49,3 +49,44 @@ def test_rediscretisation_methods_on_problem7(cuda):
         for i in "CB":
             v = [f[i + r, nl] for r in ("RKDP" if i == "C" else "RKD")]
             assert max(v) - min(v) < 0.02
+
+
+def small_feature_factors(cuda, methods, exps, Ms):
+    from paper_2505_10168_amd import binding as B
+    n, L = 256, 0.1
+    prob = B.Problem(n, n, length=L, t_final=100.0, k_ins=0.197, k_con=214.0, c_ins=1.67e6,
+                     c_con=2.41e6, theta_ref=1e6)
+    q = to_dev(I.paper_heat_load(n, n, L, 100.0), cuda)
+    out = {}
+    for m in methods:
+        for e in exps:
+            rho = to_dev(I.thin_insulator_design(n, L, 2.0 ** (-e / 3)), cuda)
+            for M in Ms:
+                s = B.Solver(prob, rho, q=q, nu=20, lambda_crit=0.25, max_levels=6,
+                             M_min_elems=M, tol=1e-9, max_cycles=100,
+                             reassembly="RKDP".index(m[1]))
+                _, st = s.solve_forward()
+                out[m, e, M] = (st.conv_factor, s.info()["path"])
+                s.close()
+    return out
+
+
+def test_small_feature_coarsening_on_problem8(cuda):
+    """Section 6: problem 8 with insulator fraction F = 2^(-e/3), Algorithm 4 with
+    M in {8, 16, 32, 64, 128} (M = 8 is Algorithm 3 here), nu = 20, six levels."""
+    exps, Ms = [12, 15, 18, 21, 22], [8, 16, 32, 64, 128]
+    f = small_feature_factors(cuda, ["CK", "CR"], exps, Ms)
+    for m in ("CK", "CR"):
+        for e in exps:
+            print(m, e, [round(f[m, e, M][0], 3) for M in Ms], [f[m, e, M][1] for M in Ms])
+    for e in exps:
+        # CR: M = 16 takes the same path as M <= 8, so the results are equal
+        assert f["CR", e, 16] == f["CR", e, 8]
+        # CR: M = 128 is markedly worse for every F
+        assert f["CR", e, 128][0] > f["CR", e, 8][0] + 0.2
+    # F <= 1/128: CR converges much faster than CK
+    for e in (21, 22):
+        assert f["CR", e, 8][0] < f["CK", e, 8][0] - 0.3
+    # CK: M near 1/F helps (F = 1/32 with M = 32, F = 1/64 with M = 64)
+    assert f["CK", 15, 32][0] < f["CK", 15, 8][0] - 0.05
+    assert f["CK", 18, 64][0] < f["CK", 18, 8][0] - 0.05
