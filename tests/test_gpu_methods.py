@@ -90,3 +90,39 @@ def test_small_feature_coarsening_on_problem8(cuda):
     # CK: M near 1/F helps (F = 1/32 with M = 32, F = 1/64 with M = 64)
     assert f["CK", 15, 32][0] < f["CK", 15, 8][0] - 0.05
     assert f["CK", 18, 64][0] < f["CK", 18, 8][0] - 0.05
+
+
+# Table 1: (k_ins, c_ins, x_offset) with k_con = c_con = 1, alpha = 10, N = 256
+PROBLEMS_1_6 = {1: (1e-2, 1.0, 0.5), 2: (1e-4, 1.0, 0.5), 3: (1e-4, 1.0, 0.15),
+                4: (1e-4, 1.0, 0.85), 5: (1.0, 1e-4, 0.5), 6: (1e-4, 1e-4, 0.5)}
+
+
+def test_two_grid_crossover_of_lambda_eff_problems_1_to_6(cuda):
+    """Section 4 (Figure 5): for all six problems the two-grid x- and t-coarsening curves
+    cross between lambda_eff = 2^-3 and 2^-1, so t wins just below that window and x
+    just above it.  The direction is forced through lambda_crit (0: always x; huge:
+    always t)."""
+    import math
+    from paper_2505_10168_amd import binding as B
+    n = 256
+    for p, (kins, cins, xoff) in PROBLEMS_1_6.items():
+        rho_np = I.ramp_design(n, 1.0, 10.0, xoff)
+        d = (kins + (1 - kins) * rho_np ** 3) / (cins + (1 - cins) * rho_np ** 2)
+        deff = math.sqrt(d.min() * d.max())
+        rho = to_dev(rho_np, cuda)
+        res = {}
+        for log2lam in (-3.25, -0.75):
+            t_final = 2.0 ** log2lam / (n * deff)     # lambda_eff = D_eff (t_T / N) N^2
+            prob = B.Problem(n, n, length=1.0, t_final=t_final, k_ins=kins, k_con=1.0,
+                             c_ins=cins, c_con=1.0)
+            q = to_dev(I.paper_heat_load(n, n, 1.0, t_final), cuda)
+            for lc, d_ in ((0.0, "x"), (1e30, "t")):
+                s = B.Solver(prob, rho, q=q, nu=5, lambda_crit=lc, max_levels=2, tol=1e-9,
+                             max_cycles=100)
+                assert s.info()["path"] == d_
+                _, st = s.solve_forward()
+                res[log2lam, d_] = st.conv_factor
+                s.close()
+        print(p, {k: round(v, 3) for k, v in res.items()})
+        assert res[-3.25, "t"] < res[-3.25, "x"]
+        assert res[-0.75, "x"] < res[-0.75, "t"]
