@@ -8,9 +8,10 @@
 // stores only its R distinct stencil rows (R is 3 or 4 in practice) and a map from
 // time level to stored row; all time levels of a row class are built by the same
 // arithmetic from the same inputs and are therefore exactly equal.  These levels are
-// smoothed, applied and restricted one thread per DOF; with the causal transfers no
-// row couples to a later time level, so the coarsest level is solved by time stepping
-// with one tridiagonal solve per time level.
+// smoothed by streaming passes (k_stencil_fused) or one step per launch, and applied
+// one thread per DOF; with the causal transfers no row couples to a later time level,
+// so the coarsest level is solved by time stepping with one tridiagonal solve per time
+// level.
 #include <hip/hip_runtime.h>
 
 #include "stmg_launch.hpp"
