@@ -126,3 +126,25 @@ def test_two_grid_crossover_of_lambda_eff_problems_1_to_6(cuda):
         print(p, {k: round(v, 3) for k, v in res.items()})
         assert res[-3.25, "t"] < res[-3.25, "x"]
         assert res[-0.75, "x"] < res[-0.75, "t"]
+
+
+def test_two_grid_crossover_uniform_material(cuda):
+    """Section 3.2 (Figure 3): with k = c = 1 the two-grid x- and t-coarsening factors
+    cross near lambda = 0.1 (about 2^-3.3): t wins at 2^-4.5, x at 2^-2."""
+    from paper_2505_10168_amd import binding as B
+    n = 256
+    rho = to_dev(np.ones(n), cuda)
+    for log2lam, winner in ((-4.5, "t"), (-2.0, "x")):
+        t_final = 2.0 ** log2lam / n          # lambda = (t_T / N) N^2 with L = 1, D = 1
+        prob = B.Problem(n, n, length=1.0, t_final=t_final, k_ins=1.0, k_con=1.0,
+                         c_ins=1.0, c_con=1.0)
+        q = to_dev(I.paper_heat_load(n, n, 1.0, t_final), cuda)
+        f = {}
+        for lc, d in ((0.0, "x"), (1e30, "t")):
+            s = B.Solver(prob, rho, q=q, nu=5, lambda_crit=lc, max_levels=2, tol=1e-9,
+                         max_cycles=100)
+            _, st = s.solve_forward()
+            f[d] = st.conv_factor
+            s.close()
+        print(log2lam, {k: round(v, 3) for k, v in f.items()})
+        assert f[winner] < f["t" if winner == "x" else "x"]
