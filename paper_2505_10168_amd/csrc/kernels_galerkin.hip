@@ -5,7 +5,8 @@
 // k = 3 (dt + 1) + (dx + 1) holds at (n, i) the coefficient of x(n + dt, i + dx) in row
 // (n, i); coefficients that would reach outside the grid are zero.  The operators do
 // not depend on the time level except near the first and last levels, so a level
-// stores only its R distinct stencil rows (R is 3 or 4 in practice) and a map from
+// stores only its R distinct stencil rows (R is 3 or 4 in practice; array 9 holds the
+// Jacobi scale omega / J_ii of each) and a map from
 // time level to stored row; all time levels of a row class are built by the same
 // arithmetic from the same inputs and are therefore exactly equal.  These levels are
 // smoothed by streaming passes (k_stencil_fused) or one step per launch, and applied
@@ -80,7 +81,7 @@ __device__ __forceinline__ double rediscretised_entry(const LevelView<double>& V
 __global__ void k_galerkin(LevelView<double> F, const double* __restrict__ fs,
                            const int* __restrict__ frow, int64_t FE, int kt, int kx, double s,
                            int Nc, int Ntc, int64_t Pc, int Rc, const int* __restrict__ crep,
-                           double* __restrict__ cs) {
+                           double omega, double* __restrict__ cs) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I > Nc) return;
     const int64_t CE = (int64_t)Rc * Pc;
@@ -115,24 +116,27 @@ __global__ void k_galerkin(LevelView<double> F, const double* __restrict__ fs,
             }
         }
         for (int k = 0; k < 9; ++k) cs[k * CE + (int64_t)r * Pc + I] = acc[k];
+        cs[9 * CE + (int64_t)r * Pc + I] = omega / acc[4];   // Jacobi scale omega / J_ii
     }
 }
 
 void launch_galerkin(const LevelView<double>& F, const StencilView* fsv, char dir, int interp,
-                     const StencilView& C, const int* crep, double* cs, hipStream_t s) {
+                     const StencilView& C, const int* crep, double omega, double* cs,
+                     hipStream_t s) {
     const int kt = dir == 't' ? (interp == 1 ? 1 : 2) : 0;
     const int kx = dir == 'x' ? 1 : 0;
     const double sc = dir == 't' ? 0.5 : 1.0;
     dim3 g(blocks_for(C.N + 1), rows_grid(C.R));
     hipLaunchKernelGGL(k_galerkin, g, dim3(kBlock), 0, s, F, fsv ? fsv->s : nullptr,
                        fsv ? fsv->row : nullptr, fsv ? fsv->E : 0, kt, kx, sc, C.N, C.Nt, C.P,
-                       C.R, crep, cs);
+                       C.R, crep, omega, cs);
 }
 
-// y = J x, b - J x or x + omega (b - J x) / J_ii with a stored stencil.  The transpose
+// y = J x, b - J x or x + (omega / J_ii) (b - J x) with a stored stencil (the scale is
+// the stencil's array 9).  The transpose
 // reads row (n + dt, i + dx)'s coefficient of (n, i), i.e. array 8 - k there.
 template <int TR>
-__global__ void k_apply_stencil(StencilView S, int mode, double omega, const double* __restrict__ x,
+__global__ void k_apply_stencil(StencilView S, int mode, const double* __restrict__ x,
                                 const double* __restrict__ b, double* __restrict__ y, int zero_in) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > S.N) return;
@@ -156,19 +160,19 @@ __global__ void k_apply_stencil(StencilView S, int mode, double omega, const dou
         } else {
             const double r = b[o] - Jx;
             if (mode == APPLY_RESIDUAL) y[o] = r;
-            else y[o] = (zero_in ? 0.0 : x[o]) + omega * r / S.s[4 * E + co];
+            else y[o] = __builtin_fma(S.s[9 * E + co], r, zero_in ? 0.0 : x[o]);
         }
     }
 }
 
-void launch_apply_stencil(const StencilView& S, int trans, int mode, double omega, const double* x,
+void launch_apply_stencil(const StencilView& S, int trans, int mode, const double* x,
                           const double* b, double* y, bool zero_in, hipStream_t s) {
     dim3 g(blocks_for(S.N + 1), rows_grid(S.Nt + 1));
     if (trans)
-        hipLaunchKernelGGL(k_apply_stencil<1>, g, dim3(kBlock), 0, s, S, mode, omega, x, b, y,
+        hipLaunchKernelGGL(k_apply_stencil<1>, g, dim3(kBlock), 0, s, S, mode, x, b, y,
                            (int)zero_in);
     else
-        hipLaunchKernelGGL(k_apply_stencil<0>, g, dim3(kBlock), 0, s, S, mode, omega, x, b, y,
+        hipLaunchKernelGGL(k_apply_stencil<0>, g, dim3(kBlock), 0, s, S, mode, x, b, y,
                            (int)zero_in);
 }
 
@@ -181,6 +185,9 @@ void launch_apply_stencil(const StencilView& S, int trans, int mode, double omeg
 // its earlier-level input is wrong only on the first levels it sees).  Neighbouring
 // columns are exchanged between lanes.  The terms of J x are added in the order of
 // k_apply_stencil, so this pass and S one-step launches give the same values.
+// HEAD 1 / 2 first adds the x / t prolongation of the coarse correction z (the
+// expressions of k_prolong_x / k_prolong_t); TAIL 1 also writes the residual
+// b - J y_S (one more warm-up row and halo lane: it needs y_S at the neighbours).
 constexpr int kStencilWave = 64;
 constexpr int kStencilWavesPerBlock = 4;
 
@@ -197,22 +204,24 @@ __device__ __forceinline__ double lane_from_right(double v) {  // value of lane 
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-template <int TR, int S>
+template <int TR, int S, int HEAD, int TAIL>
 __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stencil_fused(
-    StencilView V, double omega, const double* __restrict__ u, const double* __restrict__ b,
-    double* __restrict__ out, int zero_in, int xw, int seg, int nwaves) {
+    StencilView V, const double* __restrict__ u, const double* __restrict__ b,
+    double* __restrict__ out, int zero_in, const double* __restrict__ z, int64_t Pz,
+    double* __restrict__ rout, int xw, int seg, int nwaves) {
+    constexpr int H = S + (TAIL ? 1 : 0);             // halo lanes per side, warm-up rows
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kStencilWavesPerBlock +
                                                     (int)(threadIdx.x >> 6));
     if (wave >= nwaves) return;
     const int lane = threadIdx.x & (kStencilWave - 1);
-    const int U = kStencilWave - 2 * S;
+    const int U = kStencilWave - 2 * H;
     const int wx = wave % xw, wt = wave / xw;
-    const int i = wx * U - S + lane;                  // this lane's column
+    const int i = wx * U - H + lane;                  // this lane's column
     const bool valid = i >= 0 && i <= V.N;
-    const bool useful = valid && lane >= S && lane < kStencilWave - S;
+    const bool useful = valid && lane >= H && lane < kStencilWave - H;
     const int64_t P = V.P, E = V.E;
     const int n0 = wt * seg, n1 = min(V.Nt + 1, n0 + seg);   // output levels [n0, n1)
-    const int first = TR ? min(V.Nt, n1 - 1 + S) : max(0, n0 - S);
+    const int first = TR ? min(V.Nt, n1 - 1 + H) : max(0, n0 - H);
     const int count = TR ? first - n0 + 1 : n1 - first;
 
     double prev[S + 1];
@@ -220,12 +229,49 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
     for (int k = 0; k <= S; ++k) prev[k] = 0.0;
     // coefficients of the current row class: J: (row n: dt = -1 at dx = -1, 0, 1, then
     // dt = 0); J^T: (row n at columns i-1, i, i+1, then row n+1 at i-1, i, i+1)
-    double c[6] = {0, 0, 0, 0, 0, 0}, diag = 1.0;
+    double c[6] = {0, 0, 0, 0, 0, 0}, wd = 0.0;
     int key = -1;
+    // rows are loaded two levels ahead of use: the row classes (wave-uniform), u, b and
+    // the coarse values of the head
+    constexpr int NZ = HEAD == 1 ? 2 : (HEAD == 2 ? 1 : 0);
+    double ru[2] = {0, 0}, rb[2] = {0, 0}, rz[2][NZ > 0 ? NZ : 1] = {};
+    int rc[2] = {0, 0}, rc1[2] = {-1, -1};
+    auto fetch = [&](int it, int slot) {
+        ru[slot] = 0.0;
+        rb[slot] = 0.0;
+#pragma unroll
+        for (int q = 0; q < NZ; ++q) rz[slot][q] = 0.0;
+        if (it >= count) return;
+        const int n = TR ? first - it : first + it;
+        rc[slot] = V.row[n];
+        rc1[slot] = (TR && n < V.Nt) ? V.row[n + 1] : -1;
+        if (!valid) return;
+        const int64_t o = (int64_t)n * P + i;
+        if (!zero_in) ru[slot] = u[o];
+        rb[slot] = b[o];
+        if (HEAD == 1) {
+            const double* zr = z + (int64_t)n * Pz + (i >> 1);
+            rz[slot][0] = zr[0];
+            if (i & 1) rz[slot][NZ - 1] = zr[1];
+        } else if (HEAD == 2) {
+            rz[slot][0] = z[(int64_t)(n >> 1) * Pz + i];
+        }
+    };
+    fetch(0, 0);
+    fetch(1, 1);
     for (int it = 0; it < count; ++it) {
         const int n = TR ? first - it : first + it;
-        const int rn = V.row[n];
-        const int rk = TR ? (n < V.Nt ? V.row[n + 1] : -1) : 0;
+        const int slot = it & 1;
+        double cur = ru[slot];
+        const double bb = rb[slot];
+        const int rn = rc[slot];
+        const int rk = TR ? rc1[slot] : 0;
+        if (HEAD == 1 && valid)   // the expressions of k_prolong_x
+            cur = (i & 1) ? __builtin_fma(0.5, rz[slot][0] + rz[slot][NZ - 1], cur)
+                          : cur + rz[slot][0];
+        else if (HEAD == 2 && valid)
+            cur = cur + rz[slot][0];
+        fetch(it + 2, slot);
         const int nk = rn * 64 + (rk + 1);
         if (nk != key) {   // wave-uniform: the row class changes only near the ends
             key = nk;
@@ -243,12 +289,9 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
 #pragma unroll
                 for (int k = 0; k < 6; ++k) c[k] = valid ? V.s[k * E + cr + i] : 0.0;
             }
-            diag = valid ? V.s[4 * E + cr + i] : 1.0;
+            wd = valid ? V.s[9 * E + cr + i] : 0.0;
         }
         const int64_t o = (int64_t)n * P + i;
-        double cur = (valid && !zero_in) ? u[o] : 0.0;
-        const double bb = valid ? b[o] : 0.0;
-        const double x0 = cur;
 #pragma unroll
         for (int k = 1; k <= S; ++k) {
             const double xm = lane_from_left(cur), xp = lane_from_right(cur);
@@ -269,13 +312,33 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
                 acc = __builtin_fma(c[4], cur, acc);
                 acc = __builtin_fma(c[5], xp, acc);
             }
-            const double r = bb - acc;
-            const double y = valid ? cur + omega * r / diag : 0.0;
+            // invalid lanes have wd = 0 and zero data: they stay 0
+            const double y = __builtin_fma(wd, bb - acc, cur);
             prev[k - 1] = cur;
             cur = y;
         }
+        if (TAIL) {   // residual of y_S at this level, before prev[S] moves on
+            const double xm = lane_from_left(cur), xp = lane_from_right(cur);
+            const double pm = lane_from_left(prev[S]), pp = lane_from_right(prev[S]);
+            double acc = 0.0;
+            if (TR) {
+                acc = __builtin_fma(c[0], xm, acc);
+                acc = __builtin_fma(c[1], cur, acc);
+                acc = __builtin_fma(c[2], xp, acc);
+                acc = __builtin_fma(c[3], pm, acc);
+                acc = __builtin_fma(c[4], prev[S], acc);
+                acc = __builtin_fma(c[5], pp, acc);
+            } else {
+                acc = __builtin_fma(c[0], pm, acc);
+                acc = __builtin_fma(c[1], prev[S], acc);
+                acc = __builtin_fma(c[2], pp, acc);
+                acc = __builtin_fma(c[3], xm, acc);
+                acc = __builtin_fma(c[4], cur, acc);
+                acc = __builtin_fma(c[5], xp, acc);
+            }
+            if (useful && n >= n0 && n < n1) rout[o] = bb - acc;
+        }
         prev[S] = cur;
-        (void)x0;
         if (useful && n >= n0 && n < n1) out[o] = cur;
     }
 }
@@ -308,41 +371,53 @@ __global__ void k_stencil_thomas(StencilView S, double* __restrict__ f) {
     }
 }
 
-template <int TR, int S>
-void launch_stencil_fused_s(const StencilView& V, double omega, const double* u, const double* b,
-                            double* out, bool zero_in, hipStream_t s) {
-    const int U = kStencilWave - 2 * S;
+template <int TR, int S, int HEAD, int TAIL>
+void launch_stencil_fused_s(const StencilView& V, const StencilPass& p, hipStream_t s) {
+    constexpr int H = S + (TAIL ? 1 : 0);
+    const int U = kStencilWave - 2 * H;
     const int xw = (V.N + 1 + U - 1) / U;
     const int64_t rows = V.Nt + 1;
-    // about 4096 waves, and segments of at least 4 S levels so that the warm-up rows
-    // stay a fraction of the work
-    int64_t seg = (rows * xw + 4095) / 4096;
-    if (seg < 4 * S) seg = 4 * S;
-    if (seg > rows) seg = rows;
+    // Short time segments: a wave's levels are a serial chain, so small levels need
+    // many segments even though each recomputes H warm-up levels (the policy of the
+    // rediscretised fused passes: fewer, longer segments when S >= 4 makes the pass
+    // arithmetic-bound on large levels).
+    const int64_t target = S >= 4 ? 3072 : 16384;
+    int64_t seg = (rows * xw + target - 1) / target;
+    if (seg < 2) seg = 2;
+    if (seg > 1024) seg = 1024;
+    if (seg & 1) ++seg;
     const int nw = (int)(xw * ((rows + seg - 1) / seg));
     const int blocks = (nw + kStencilWavesPerBlock - 1) / kStencilWavesPerBlock;
-    hipLaunchKernelGGL((k_stencil_fused<TR, S>), dim3(blocks),
-                       dim3(kStencilWave * kStencilWavesPerBlock), 0, s, V, omega, u, b, out,
-                       (int)zero_in, xw, (int)seg, nw);
+    hipLaunchKernelGGL((k_stencil_fused<TR, S, HEAD, TAIL>), dim3(blocks),
+                       dim3(kStencilWave * kStencilWavesPerBlock), 0, s, V, p.u, p.b, p.out,
+                       (int)p.zero_in, p.z, p.Pz, p.r, xw, (int)seg, nw);
+}
+
+template <int TR, int S>
+void launch_stencil_fused_ht(const StencilView& V, const StencilPass& p, hipStream_t s) {
+    if (p.r) launch_stencil_fused_s<TR, S, 0, 1>(V, p, s);
+    else if (p.head == 'x') launch_stencil_fused_s<TR, S, 1, 0>(V, p, s);
+    else if (p.head == 't') launch_stencil_fused_s<TR, S, 2, 0>(V, p, s);
+    else launch_stencil_fused_s<TR, S, 0, 0>(V, p, s);
 }
 
 template <int TR>
-void launch_stencil_fused_t(const StencilView& V, int sweeps, double omega, const double* u,
-                            const double* b, double* out, bool zero_in, hipStream_t s) {
-    switch (sweeps) {
-        case 1: launch_stencil_fused_s<TR, 1>(V, omega, u, b, out, zero_in, s); break;
-        case 2: launch_stencil_fused_s<TR, 2>(V, omega, u, b, out, zero_in, s); break;
-        case 3: launch_stencil_fused_s<TR, 3>(V, omega, u, b, out, zero_in, s); break;
-        case 4: launch_stencil_fused_s<TR, 4>(V, omega, u, b, out, zero_in, s); break;
-        case 5: launch_stencil_fused_s<TR, 5>(V, omega, u, b, out, zero_in, s); break;
-        default: launch_stencil_fused_s<TR, 6>(V, omega, u, b, out, zero_in, s); break;
+void launch_stencil_fused_t(const StencilView& V, const StencilPass& p, hipStream_t s) {
+    switch (p.sweeps) {
+        case 1: launch_stencil_fused_ht<TR, 1>(V, p, s); break;
+        case 2: launch_stencil_fused_ht<TR, 2>(V, p, s); break;
+        case 3: launch_stencil_fused_ht<TR, 3>(V, p, s); break;
+        case 4: launch_stencil_fused_ht<TR, 4>(V, p, s); break;
+        case 5: launch_stencil_fused_ht<TR, 5>(V, p, s); break;
+        default: launch_stencil_fused_ht<TR, 6>(V, p, s); break;
     }
 }
 
-void launch_stencil_fused(const StencilView& V, int trans, int sweeps, double omega, const double* u,
-                          const double* b, double* out, bool zero_in, hipStream_t s) {
-    if (trans) launch_stencil_fused_t<1>(V, sweeps, omega, u, b, out, zero_in, s);
-    else launch_stencil_fused_t<0>(V, sweeps, omega, u, b, out, zero_in, s);
+int launch_stencil_fused(const StencilView& V, const StencilPass& p, hipStream_t s) {
+    if (p.sweeps < 1 || p.sweeps > kStencilMaxFused || (p.r && p.head)) return -1;
+    if (p.trans) launch_stencil_fused_t<1>(V, p, s);
+    else launch_stencil_fused_t<0>(V, p, s);
+    return 0;
 }
 
 void launch_stencil_thomas(const StencilView& S, double* factors, hipStream_t s) {

@@ -60,7 +60,7 @@ struct Level {
     float* coef32 = nullptr;
     double* thomas = nullptr;  // coarsest: cp, inv, rhs scratch (3 (N+1))
     double* ainv = nullptr;    // coarsest with N <= kDenseCoarsestMax: A^{-1}, N x N
-    double* sten = nullptr;    // Galerkin levels: 9-point stencil, 9 arrays of R rows of P
+    double* sten = nullptr;    // Galerkin levels: 9-point stencil and Jacobi scale, 10 arrays of R rows of P
     double* sfac = nullptr;    // coarsest Galerkin level: Thomas factors, 4 arrays of R P
     int R = 0;                 // stored stencil rows
     int* srow = nullptr;       // device: time level -> stored row (Nt+1)
@@ -69,7 +69,8 @@ struct Level {
     double* u = nullptr;
     double* b = nullptr;
     double* t = nullptr;
-    double* w = nullptr;     // fine level, pipelined solves: keeps the previous iterate
+    double* w = nullptr;     // fine level, pipelined solves: keeps the previous iterate;
+                             // Galerkin levels: residual of the fused pre-smoothing pass
     float* u32 = nullptr;
     float* b32 = nullptr;
     float* t32 = nullptr;
@@ -264,8 +265,8 @@ size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest, bool 
     size_t b = 3 * (size_t)N * 8 + kCoefArrays * (size_t)(N + 1) * 8;
     // stored stencil rows: at most kStencilRowsBound (3 or 4 in practice)
     if (galerkin && !fine)
-        b += (9 + (coarsest ? 4 : 0)) * (size_t)std::min(Nt + 1, kStencilRowsBound) * P * 8 +
-             (size_t)(Nt + 1 + kStencilRowsBound) * 4;
+        b += (10 + (coarsest ? 4 : 0)) * (size_t)std::min(Nt + 1, kStencilRowsBound) * P * 8 +
+             (size_t)(Nt + 1 + kStencilRowsBound) * 4 + (size_t)E * 8;
     if (precision == STMG_MIXED) b += kCoefArrays * (size_t)(N + 1) * 4;
     if (coarsest) b += 3 * (size_t)(N + 1) * 8 + (N <= kDenseCoarsestMax ? (size_t)N * N * 8 : 0);
     if (precision == STMG_FP64 || fine) b += 3 * (size_t)E * 8;
@@ -470,7 +471,7 @@ int galerkin_levels(stmg_ctx* h) {
         Level& c = h->L[i + 1];
         const StencilView fs = stencil_view(f);
         launch_galerkin(view<double>(f, h->o.omega), i == 0 ? nullptr : &fs, f.dir, h->o.interp,
-                        stencil_view(c), c.srep, c.sten, h->s);
+                        stencil_view(c), c.srep, h->o.omega, c.sten, h->s);
     }
     if (nl > 1) launch_stencil_thomas(stencil_view(h->L[nl - 1]), h->L[nl - 1].sfac, h->s);
     HIPCHK(hipGetLastError());
@@ -537,8 +538,9 @@ int build(stmg_ctx* h, const double* d_q) {
             const Level& f = h->L[i - 1];
             stencil_rows(f.hrow, f.Nt, f.dir, l.hrow, l.hrep);
             l.R = (int)l.hrep.size();
-            CHK(h->alloc(&l.sten, 9 * (int64_t)l.R * l.P));
+            CHK(h->alloc(&l.sten, 10 * (int64_t)l.R * l.P));
             if (last) CHK(h->alloc(&l.sfac, 4 * (int64_t)l.R * l.P));
+            CHK(h->alloc(&l.w, l.elems()));   // residual of the fused pre-smoothing pass
             CHK(h->alloc(&l.srow, (int64_t)l.Nt + 1));
             CHK(h->alloc(&l.srep, (int64_t)l.R));
             HIPCHK(hipMemcpyAsync(l.srow, l.hrow.data(), l.hrow.size() * sizeof(int),
@@ -614,23 +616,31 @@ std::vector<int> chunks_of(int nu) {
 }
 
 // nu damped Jacobi steps on a Galerkin level (stored stencil), in place: streaming
-// passes of up to kStencilMaxFused steps with the fused kernels, else one launch per step
-void stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu) {
+// passes of up to kStencilMaxFused steps with the fused kernels, else one launch per
+// step.  head ('x' / 't'): the first pass adds the prolongation of z (pitch Pz) first;
+// r: the last pass also writes the residual there (both only with the fused kernels,
+// which the caller checks).
+int stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu, char head = 0,
+                   const double* z = nullptr, int64_t Pz = 0, double* r = nullptr) {
     const StencilView S = stencil_view(lv);
     bool zero = zero_start;
     int left = nu;
     while (left > 0) {
         const int passes = (left + kStencilMaxFused - 1) / kStencilMaxFused;
         const int k = h->o.fused ? (left + passes - 1) / passes : 1;
-        if (h->o.fused)
-            launch_stencil_fused(S, trans, k, h->o.omega, lv.u, lv.b, lv.t, zero, h->s);
-        else
-            launch_apply_stencil(S, trans, APPLY_JACOBI, h->o.omega, lv.u, lv.b, lv.t, zero, h->s);
+        if (h->o.fused) {
+            StencilPass p{trans, k, lv.u, lv.b, lv.t, zero, head, z, Pz, left == k ? r : nullptr};
+            if (launch_stencil_fused(S, p, h->s) != 0) return fail(STMG_EINVAL, "bad stencil pass");
+            head = 0;
+        } else {
+            launch_apply_stencil(S, trans, APPLY_JACOBI, lv.u, lv.b, lv.t, zero, h->s);
+        }
         std::swap(lv.u, lv.t);
         zero = false;
         left -= k;
     }
     if (nu == 0 && zero_start) launch_fill<double>(lv.u, lv.elems(), 0.0, h->s);
+    return 0;
 }
 
 template <typename T>
@@ -640,10 +650,16 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
     const auto V = view<T>(lv, h->o.omega);
     if constexpr (std::is_same<T, double>::value) {
         if (lv.sten) {
-            stencil_smooth(h, lv, trans, zero_start, nu);
-            launch_apply_stencil(stencil_view(lv), trans, APPLY_RESIDUAL, h->o.omega, lv.u, lv.b,
-                                 lv.t, false, h->s);
-            launch_restrict<double>(lv.dir, V, lv.t, cl.b, cl.P, h->s, h->o.interp);
+            if (h->o.fused && nu > 0) {
+                // the last smoothing pass writes the residual into the third vector
+                CHK(stencil_smooth(h, lv, trans, zero_start, nu, 0, nullptr, 0, lv.w));
+                launch_restrict<double>(lv.dir, V, lv.w, cl.b, cl.P, h->s, h->o.interp);
+            } else {
+                CHK(stencil_smooth(h, lv, trans, zero_start, nu));
+                launch_apply_stencil(stencil_view(lv), trans, APPLY_RESIDUAL, lv.u, lv.b, lv.t,
+                                     false, h->s);
+                launch_restrict<double>(lv.dir, V, lv.t, cl.b, cl.P, h->s, h->o.interp);
+            }
             HIPCHK(hipGetLastError());
             return 0;
         }
@@ -717,8 +733,12 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
     if constexpr (std::is_same<T, double>::value) {
         if (lv.sten) {
             // norms are taken on the finest level only, which is never a stencil level
-            launch_prolong_add<double>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
-            stencil_smooth(h, lv, trans, false, nu);
+            if (h->o.fused && nu > 0) {
+                CHK(stencil_smooth(h, lv, trans, false, nu, lv.dir, z, cl.P));
+            } else {
+                launch_prolong_add<double>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
+                CHK(stencil_smooth(h, lv, trans, false, nu));
+            }
             HIPCHK(hipGetLastError());
             return 0;
         }
@@ -1336,8 +1356,7 @@ int stmg_level_apply(stmg_t h, int level, int transpose, const double* d_x, doub
     Level& l = h->L[level];
     CHK(copy_in(h, l, d_x, l.u));
     if (l.sten)
-        launch_apply_stencil(stencil_view(l), transpose, APPLY_J, h->o.omega, l.u, l.b, l.t, false,
-                             h->s);
+        launch_apply_stencil(stencil_view(l), transpose, APPLY_J, l.u, l.b, l.t, false, h->s);
     else
         launch_apply<double>(view<double>(l, h->o.omega), transpose, APPLY_J, l.u, l.b, l.t, false,
                              h->s);
@@ -1354,7 +1373,7 @@ int stmg_level_smooth(stmg_t h, int level, int transpose, int nu, const double* 
     CHK(copy_in(h, l, d_u, l.u));
     const auto V = view<double>(l, h->o.omega);
     if (l.sten) {
-        stencil_smooth(h, l, transpose, false, nu);
+        CHK(stencil_smooth(h, l, transpose, false, nu));
     } else if (h->o.fused) {
         for (int S : chunks_of(nu)) {
             FusedPass fp{};

@@ -94,8 +94,9 @@ void launch_oc_update(const double* chi, const double* grad, int n, double volum
                       double eta, double chi_min, double* chi_new, hipStream_t s);
 
 // ---- Galerkin levels (P reassembly): stored 9-point stencils ---------------------------
-// 9 arrays of E = R P doubles (R stored rows of P); array 3 (dt+1) + (dx+1) holds at
-// (row[n], i) the coefficient of x(n+dt, i+dx) in row (n, i)
+// 10 arrays of E = R P doubles (R stored rows of P); array 3 (dt+1) + (dx+1) holds at
+// (row[n], i) the coefficient of x(n+dt, i+dx) in row (n, i), array 9 the Jacobi scale
+// omega / J_ii
 struct StencilView {
     int N;
     int Nt;
@@ -111,14 +112,28 @@ constexpr int kStencilCoarsestMaxNodes = 1536;
 // crep[r] for stored row r): from F's rediscretised operator when fsv is null, else from
 // F's stored stencil
 void launch_galerkin(const LevelView<double>& F, const StencilView* fsv, char dir, int interp,
-                     const StencilView& C, const int* crep, double* cs, hipStream_t s);
-void launch_apply_stencil(const StencilView& S, int trans, int mode, double omega, const double* x,
+                     const StencilView& C, const int* crep, double omega, double* cs,
+                     hipStream_t s);
+void launch_apply_stencil(const StencilView& S, int trans, int mode, const double* x,
                           const double* b, double* y, bool zero_in, hipStream_t s);
 // `sweeps` (1..kStencilMaxFused) damped Jacobi steps in one streaming pass, u -> out
-// (distinct buffers); the same values as `sweeps` launches of launch_apply_stencil
+// (distinct buffers); the same values as the prolongation, `sweeps` launches of
+// launch_apply_stencil and the residual launched one after the other
 constexpr int kStencilMaxFused = 6;
-void launch_stencil_fused(const StencilView& V, int trans, int sweeps, double omega, const double* u,
-                          const double* b, double* out, bool zero_in, hipStream_t s);
+struct StencilPass {
+    int trans;
+    int sweeps;
+    const double* u;
+    const double* b;
+    double* out;
+    int zero_in;
+    char head;          // 0, 'x' or 't': add P z (coarse pitch Pz) to u first
+    const double* z;
+    int64_t Pz;
+    double* r;          // non-null: also write b - J out here (not with a head)
+};
+// -1 (nothing launched) for sweeps outside 1..kStencilMaxFused or a head with a residual
+int launch_stencil_fused(const StencilView& V, const StencilPass& p, hipStream_t s);
 // factors: 4 arrays of E doubles (cp, inv of J's blocks, then of J^T's), per stored row
 void launch_stencil_thomas(const StencilView& S, double* factors, hipStream_t s);
 void launch_stencil_coarsest(const StencilView& S, const double* factors, int trans,
