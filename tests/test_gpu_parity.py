@@ -61,7 +61,7 @@ def test_apply_every_level(name, transpose, cuda):
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("transpose", [0, 1])
 @pytest.mark.parametrize("fused", [1, 0])
-@pytest.mark.parametrize("nu", [1, 2, 5])
+@pytest.mark.parametrize("nu", [1, 2, 5, 10, 20])
 def test_smooth(name, transpose, fused, nu, cuda):
     from paper_2505_10168_amd import binding as B
     s, _, _, h = make_pair(name, cuda, fused=fused)
@@ -388,5 +388,25 @@ def test_galerkin_one_level_equals_rediscretised(cuda):
         s = B.Solver(prob, to_dev(rho, cuda), max_levels=1, reassembly=method)
         u, st = s.solve_forward()
         outs.append(to_np(u))
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("nu", [7, 10, 20])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_long_fused_passes_identical_to_reference(nu, transpose, cuda):
+    """nu > 6: the fused path smooths with passes of up to 10 steps; its V-cycle iterates
+    equal those of the one-kernel-per-step path bit for bit."""
+    from paper_2505_10168_amd import binding as B
+    outs = []
+    for fused in (1, 0):
+        s, _, lv, h = make_pair("block_256x600", cuda, fused=fused, nu=nu)
+        b = O.load_vector(lv, 1.0)
+        if transpose:
+            b = O.adjoint_rhs(lv, b)
+        bd, ud = to_dev(b, cuda), to_dev(np.zeros(lv.shape), cuda)
+        for _ in range(2):
+            B.stmg_vcycle(s.handle, transpose, bd, ud)
+        outs.append(to_np(ud))
         s.close()
     assert np.array_equal(outs[0], outs[1])
