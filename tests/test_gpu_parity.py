@@ -394,9 +394,9 @@ def test_galerkin_one_level_equals_rediscretised(cuda):
 
 @pytest.mark.parametrize("nu", [7, 10, 20])
 @pytest.mark.parametrize("transpose", [0, 1])
-def test_long_fused_passes_identical_to_reference(nu, transpose, cuda):
-    """nu > 6: the fused path smooths with passes of up to 10 steps; its V-cycle iterates
-    equal those of the one-kernel-per-step path bit for bit."""
+def test_multi_pass_smoothing_identical_to_reference(nu, transpose, cuda):
+    """nu > 6: the fused path smooths in several passes per side (at most 6 steps each);
+    its V-cycle iterates equal those of the one-kernel-per-step path bit for bit."""
     from paper_2505_10168_amd import binding as B
     outs = []
     for fused in (1, 0):
