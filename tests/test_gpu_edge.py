@@ -1,0 +1,53 @@
+"""Degenerate and ragged grids on the main (rediscretised) path: a single level, one
+element, one time step, sizes that cannot halve, hierarchies forced onto tiny levels.
+Path, V-cycle iterates and the converged solve against the oracle, for the streaming,
+streaming-without-tail and reference kernels."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from tests.helpers import I, O, oracle_setup, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+EDGE = [
+    # (id, rho, n_t, kappa_min, options)
+    ("1x1", np.array([0.6]), 1, 1e-2, {}),
+    ("1x2_two_levels", np.array([0.6]), 2, 1e-2, {"max_levels": 2}),
+    ("2x1_two_levels", np.array([0.2, 0.9]), 1, 1e-2, {"max_levels": 2}),
+    ("2x2_three_levels", np.array([0.2, 0.9]), 2, 1e-2, {"max_levels": 3}),
+    ("1x8_four_levels", np.array([0.7]), 8, 1e-2, {"max_levels": 4}),
+    ("8x1_four_levels", I.block_density(8, 2, seed=9), 1, 1e-3, {"max_levels": 4}),
+    ("3x5_cannot_halve", I.block_density(3, 1, seed=4), 5, 1e-2, {"max_levels": 3}),
+    ("7x128_x_cannot_halve", I.block_density(7, 1, seed=6), 128, 1e-3, {}),
+    ("128x7_t_cannot_halve", I.block_density(128, 8, seed=8), 7, 1e-3, {}),
+    ("62x66_ragged", I.block_density(62, 2, seed=10), 66, 1e-3, {"max_levels": 5}),
+]
+
+
+@pytest.mark.parametrize("case", EDGE, ids=[c[0] for c in EDGE])
+@pytest.mark.parametrize("fused", [1, 2, 0])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_edge_grids_match_oracle(case, fused, transpose, cuda):
+    from paper_2505_10168_amd import binding as B
+    _, rho, n_t, kmin, extra = case
+    prob = B.Problem(len(rho), n_t, k_ins=kmin)
+    s = B.Solver(prob, to_dev(rho, cuda), nu=2, fused=fused, max_cycles=400, **extra)
+    oextra = {k: v for k, v in extra.items() if k != "max_cycles"}
+    mat, lv, h = oracle_setup(rho, n_t, kmin, nu=2, **oextra)
+    assert s.info()["path"] == h.path
+    b = O.load_vector(lv, 1.0)
+    if transpose:
+        b = O.adjoint_rhs(lv, b)
+    u = np.zeros(lv.shape)
+    ud, bd = to_dev(u, cuda), to_dev(b, cuda)
+    for it in range(3):
+        B.stmg_vcycle(s.handle, transpose, bd, ud)
+        u = O.vcycle(h, 0, u, b, bool(transpose))
+        assert rel(to_np(ud), u) <= 1e-12, (it, rel(to_np(ud), u))
+    x, st = (s.solve_adjoint if transpose else s.solve_forward)(bd)
+    ref = O.direct_solve(lv, b, transpose=bool(transpose))
+    assert st.status == 0 and st.rel_residual < 1e-10
+    assert rel(to_np(x), ref) <= 1e-8
+    s.close()
