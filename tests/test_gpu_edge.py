@@ -51,3 +51,23 @@ def test_edge_grids_match_oracle(case, fused, transpose, cuda):
     assert st.status == 0 and st.rel_residual < 1e-10
     assert rel(to_np(x), ref) <= 1e-8
     s.close()
+
+
+@pytest.mark.parametrize("case", EDGE, ids=[c[0] for c in EDGE])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_edge_grids_mixed_precision(case, transpose, cuda):
+    """FP32 inner V-cycles in FP64 defect correction reach the same 1e-10 residual and
+    the direct solution on the same grids."""
+    from paper_2505_10168_amd import binding as B
+    _, rho, n_t, kmin, extra = case
+    prob = B.Problem(len(rho), n_t, k_ins=kmin)
+    s = B.Solver(prob, to_dev(rho, cuda), nu=2, precision=B.STMG_MIXED, max_cycles=400, **extra)
+    mat, lv, h = oracle_setup(rho, n_t, kmin, nu=2, **extra)
+    b = O.load_vector(lv, 1.0)
+    if transpose:
+        b = O.adjoint_rhs(lv, b)
+    x, st = (s.solve_adjoint if transpose else s.solve_forward)(to_dev(b, cuda))
+    ref = O.direct_solve(lv, b, transpose=bool(transpose))
+    assert st.status == 0 and st.rel_residual < 1e-10
+    assert rel(to_np(x), ref) <= 1e-8
+    s.close()
