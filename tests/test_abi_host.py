@@ -99,3 +99,44 @@ def test_galerkin_needs_causal_interpolation_and_fp64():
         rc = B.lib.stmg_create(C.byref(h), C.byref(p), C.byref(o), C.c_void_p(1), None, None)
         assert rc == B.STMG_EINVAL
         assert b"Galerkin" in B.lib.stmg_last_error()
+
+
+C_CONSUMER = r"""
+#include "stmg.h"
+#include <stdio.h>
+#include <string.h>
+int main(void) {
+    stmg_options o;
+    stmg_problem p;
+    size_t bytes = 0;
+    if (stmg_default_options(&o) != STMG_OK) return 1;
+    if (stmg_default_options(NULL) != STMG_EINVAL) return 2;
+    memset(&p, 0, sizeof p);
+    p.n_el = 64; p.n_t = 64; p.length = 1.0; p.t_final = 0.1;
+    p.k_ins = 1e-3; p.k_con = 1.0; p.c_ins = 1.0; p.c_con = 1.0; p.p_k = 3.0; p.p_c = 2.0;
+    p.theta_ref = 1.0; p.q_uniform = 1.0;
+    if (stmg_footprint(&p, &o, &bytes) != STMG_OK || bytes == 0) return 3;
+    if (stmg_create(NULL, &p, &o, NULL, NULL, NULL) != STMG_EINVAL) return 4;
+    printf("%s %zu %d\n", stmg_status_string(STMG_DIVERGED), bytes, o.nu);
+    return 0;
+}
+"""
+
+
+def test_header_compiles_as_c99_and_links(tmp_path):
+    """A plain C99 program compiles against include/stmg.h with warnings as errors,
+    links against libstmg.so and calls the entry points that need no GPU."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "consumer.c"
+    src.write_text(C_CONSUMER)
+    exe = tmp_path / "consumer"
+    lib = B.LIB_PATH.parent
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                    f"-I{HEADER.parent}", str(src), f"-L{lib}", "-lstmg",
+                    f"-Wl,-rpath,{lib}", "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert out[0] == "diverged" and int(out[1]) > 0 and int(out[2]) == 2
