@@ -50,8 +50,9 @@ extern "C" {
 #define STMG_REASSEMBLE_K     1   /* average conductivity                           */
 #define STMG_REASSEMBLE_D     2   /* average the design field, then apply SIMP      */
 #define STMG_REASSEMBLE_P     3   /* Galerkin: J^(l+1) = R J^(l) P (K-averaged k, c
-                                     still steer the coarsening decision); FP64 and
-                                     causal interpolation only                        */
+                                     still steer the coarsening decision); FP64 only;
+                                     with bilinear interpolation the coarsest level
+                                     must have at most 16384 DOFs                     */
 
 /* precision of the solve */
 #define STMG_FP64             0   /* everything in FP64                             */

@@ -488,4 +488,137 @@ void launch_stencil_coarsest(const StencilView& S, const double* factors, int tr
                        trans, b, z);
 }
 
+// ---- exact solve of a level whose rows also couple to the next time level ------------
+// (bilinear interpolation with Galerkin operators).  The operator is assembled as a
+// dense n x n matrix, n = (N+1)(Nt+1), DOF (t, i) at index t (N+1) + i, and factored by
+// LU with partial pivoting.  Its bandwidth is N + 2 each side, so with row pivoting L
+// keeps that band and U at most twice it: the factorization and the solves only touch
+// those bands.
+
+// row r of J (trans = 0) or J^T (trans = 1); A zeroed before
+__global__ void k_stencil_dense(StencilView S, int trans, double* __restrict__ A) {
+    const int W = S.N + 1;
+    const int64_t n = (int64_t)W * (S.Nt + 1);
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int t = (int)(r / W), i = (int)(r % W);
+    for (int k = 0; k < 9; ++k) {
+        const int tt = t + k / 3 - 1, ii = i + k % 3 - 1;
+        if (tt < 0 || tt > S.Nt || ii < 0 || ii > S.N) continue;
+        const double c = trans ? S.s[(8 - k) * S.E + (int64_t)S.row[tt] * S.P + ii]
+                               : S.s[k * S.E + (int64_t)S.row[t] * S.P + i];
+        A[r * n + (int64_t)tt * W + ii] = c;
+    }
+}
+
+constexpr int kLuThreads = 1024;
+
+// column k: pivot row p = argmax_{k <= r <= k + bl} |A[r][k]| (the first on ties), swap
+// rows k and p over the columns [k, k + bl + bu], then the multipliers A[r][k] /= A[k][k]
+__global__ __launch_bounds__(kLuThreads) void k_lu_pivot(double* __restrict__ A, int n, int k, int bl,
+                                                      int bu, int* __restrict__ piv) {
+    __shared__ double sv[kLuThreads / 64];
+    __shared__ int si[kLuThreads / 64];
+    __shared__ int sp;
+    const int rend = min(n - 1, k + bl);
+    double best = -1.0;
+    int bi = k;
+    for (int r = k + threadIdx.x; r <= rend; r += kLuThreads) {
+        const double v = fabs(A[(int64_t)r * n + k]);
+        if (v > best) { best = v; bi = r; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if ((threadIdx.x & 63) == 0) { sv[threadIdx.x >> 6] = best; si[threadIdx.x >> 6] = bi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = sv[0];
+        int p = si[0];
+        for (int w = 1; w < kLuThreads / 64; ++w)
+            if (sv[w] > b || (sv[w] == b && si[w] < p)) { b = sv[w]; p = si[w]; }
+        sp = p;
+        piv[k] = p;
+    }
+    __syncthreads();
+    const int p = sp;
+    const int cend = min(n - 1, k + bl + bu);
+    if (p != k) {
+        for (int c = k + threadIdx.x; c <= cend; c += kLuThreads) {
+            const double a = A[(int64_t)k * n + c];
+            A[(int64_t)k * n + c] = A[(int64_t)p * n + c];
+            A[(int64_t)p * n + c] = a;
+        }
+    }
+    __syncthreads();
+    const double d = A[(int64_t)k * n + k];
+    for (int r = k + 1 + threadIdx.x; r <= rend; r += kLuThreads) A[(int64_t)r * n + k] /= d;
+}
+
+// trailing update A[r][c] -= A[r][k] A[k][c], k < r <= k + bl, k < c <= k + bl + bu
+__global__ void k_lu_update(double* __restrict__ A, int n, int k, int bl, int bu) {
+    const int c = k + 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = k + 1 + blockIdx.y;
+    if (c > min(n - 1, k + bl + bu) || r > min(n - 1, k + bl)) return;
+    A[(int64_t)r * n + c] -= A[(int64_t)r * n + k] * A[(int64_t)k * n + c];
+}
+
+void launch_stencil_lu(const StencilView& S, int trans, double* A, int* piv, hipStream_t s) {
+    const int W = S.N + 1;
+    const int n = W * (S.Nt + 1);
+    const int b = S.N + 2;   // bandwidth of the 9-point operator in this ordering
+    launch_fill<double>(A, (int64_t)n * n, 0.0, s);
+    hipLaunchKernelGGL(k_stencil_dense, dim3(blocks_for(n)), dim3(kBlock), 0, s, S, trans, A);
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(kLuThreads), 0, s, A, n, k, b, b, piv);
+        const int rows = min(n - 1, k + b) - k, cols = min(n - 1, k + 2 * b) - k;
+        if (rows > 0 && cols > 0)
+            hipLaunchKernelGGL(k_lu_update, dim3(blocks_for(cols), rows), dim3(kBlock), 0, s, A,
+                               n, k, b, b);
+    }
+}
+
+// z = A^-1 b from the factors: L (unit, band b, with the interchanges) forward and U
+// (band 2b) backward, one workgroup; x: n doubles of scratch in global memory
+__global__ __launch_bounds__(kLuThreads) void k_lu_solve(StencilView S, const double* __restrict__ A,
+                                                      const int* __restrict__ piv,
+                                                      const double* __restrict__ bv,
+                                                      double* __restrict__ z, double* x) {
+    const int W = S.N + 1;
+    const int n = W * (S.Nt + 1);
+    const int b = S.N + 2;
+    for (int r = threadIdx.x; r < n; r += kLuThreads) x[r] = bv[(int64_t)(r / W) * S.P + r % W];
+    __syncthreads();
+    // the factorization swapped rows from the pivot column on only (earlier multipliers
+    // stay in place), so each interchange is applied just before its elimination step
+    for (int k = 0; k < n; ++k) {
+        if (threadIdx.x == 0) {
+            const int p = piv[k];
+            if (p != k) { const double a = x[k]; x[k] = x[p]; x[p] = a; }
+        }
+        __syncthreads();
+        const double xk = x[k];
+        const int rend = min(n - 1, k + b);
+        for (int r = k + 1 + threadIdx.x; r <= rend; r += kLuThreads)
+            x[r] -= A[(int64_t)r * n + k] * xk;
+        __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        const double xk = x[k] / A[(int64_t)k * n + k];
+        const int r0 = max(0, k - 2 * b);
+        __syncthreads();
+        for (int r = r0 + threadIdx.x; r < k; r += kLuThreads) x[r] -= A[(int64_t)r * n + k] * xk;
+        if (threadIdx.x == 0) x[k] = xk;
+        __syncthreads();
+    }
+    for (int r = threadIdx.x; r < n; r += kLuThreads) z[(int64_t)(r / W) * S.P + r % W] = x[r];
+}
+
+void launch_stencil_lu_solve(const StencilView& S, const double* A, const int* piv, const double* b,
+                             double* z, double* scratch, hipStream_t s) {
+    hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(kLuThreads), 0, s, S, A, piv, b, z, scratch);
+}
+
 }  // namespace stmg

@@ -62,6 +62,8 @@ struct Level {
     double* ainv = nullptr;    // coarsest with N <= kDenseCoarsestMax: A^{-1}, N x N
     double* sten = nullptr;    // Galerkin levels: 9-point stencil and Jacobi scale, 10 arrays of R rows of P
     double* sfac = nullptr;    // coarsest Galerkin level: Thomas factors, 4 arrays of R P
+    double* lu = nullptr;      // coarsest bilinear Galerkin level: LU factors of J, J^T (2 n^2)
+    int* piv = nullptr;        // and their interchanges (2 n)
     int R = 0;                 // stored stencil rows
     int* srow = nullptr;       // device: time level -> stored row (Nt+1)
     int* srep = nullptr;       // device: stored row -> its representative time level (R)
@@ -87,18 +89,21 @@ StencilView stencil_view(const Level& l) {
 // outside the grid; time levels with the same such signature get exactly equal
 // stencils and share one stored row.  The rediscretised fine level has three classes:
 // time level 0 (Dirichlet), 1 (no coupling to level 0) and the rest.
-void stencil_rows(const std::vector<int>& frow, int Nt, char dir, std::vector<int>& row,
+void stencil_rows(const std::vector<int>& frow, int Nt, char dir, int interp, std::vector<int>& row,
                   std::vector<int>& rep) {
     const int Ntc = dir == 't' ? Nt / 2 : Nt;
-    std::vector<std::array<int, 4>> sigs;
+    std::vector<std::array<int, 6>> sigs;
     row.assign(Ntc + 1, 0);
     rep.clear();
     for (int J = 0; J <= Ntc; ++J) {
-        std::array<int, 4> sig;
-        if (dir == 't')
-            sig = {frow[2 * J], 2 * J + 1 <= Nt ? frow[2 * J + 1] : -1, J == 0, 2 * J + 2 > Nt};
+        std::array<int, 6> sig;
+        if (dir == 't' && interp == STMG_INTERP_B)   // fine rows 2J-1, 2J, 2J+1
+            sig = {J >= 1 ? frow[2 * J - 1] : -1, frow[2 * J], 2 * J + 1 <= Nt ? frow[2 * J + 1] : -1,
+                   J == 0, 2 * J + 1 > Nt, 2 * J + 2 > Nt};
+        else if (dir == 't')                         // fine rows 2J, 2J+1
+            sig = {frow[2 * J], 2 * J + 1 <= Nt ? frow[2 * J + 1] : -1, -1, J == 0, 2 * J + 2 > Nt, 0};
         else
-            sig = {frow[J], -1, J == 0, J == Ntc};
+            sig = {frow[J], -1, -1, J == 0, J == Ntc, 0};
         size_t r = 0;
         while (r < sigs.size() && sigs[r] != sig) ++r;
         if (r == sigs.size()) {
@@ -237,9 +242,8 @@ int validate(const stmg_problem* p, const stmg_options* o) {
     if (o->max_cycles < 1 || o->max_cycles > STMG_MAX_HISTORY)
         return fail(STMG_EINVAL, "max_cycles must be in [1, STMG_MAX_HISTORY]");
     if (o->reassembly < 0 || o->reassembly > 3) return fail(STMG_EINVAL, "unknown reassembly method");
-    if (o->reassembly == STMG_REASSEMBLE_P &&
-        (o->interp != STMG_INTERP_C || o->precision != STMG_FP64))
-        return fail(STMG_EINVAL, "Galerkin reassembly needs causal interpolation and FP64");
+    if (o->reassembly == STMG_REASSEMBLE_P && o->precision != STMG_FP64)
+        return fail(STMG_EINVAL, "Galerkin reassembly needs FP64");
     if (o->deff_mode < 0 || o->deff_mode > 1) return fail(STMG_EINVAL, "unknown deff_mode");
     if (o->precision != STMG_FP64 && o->precision != STMG_MIXED)
         return fail(STMG_EINVAL, "unknown precision");
@@ -260,13 +264,17 @@ bool can_t(int Nt) { return Nt % 2 == 0 && Nt >= 2; }
 bool pipelined_options(const stmg_options* o) { return o->precision == STMG_FP64 && o->fused != 0; }
 
 size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest, bool pipelined,
-                   bool galerkin) {
+                   bool galerkin, bool bilinear = false) {
     const int64_t P = pitch_for(N), E = (int64_t)(Nt + 1) * P;
     size_t b = 3 * (size_t)N * 8 + kCoefArrays * (size_t)(N + 1) * 8;
     // stored stencil rows: at most kStencilRowsBound (3 or 4 in practice)
     if (galerkin && !fine)
         b += (10 + (coarsest ? 4 : 0)) * (size_t)std::min(Nt + 1, kStencilRowsBound) * P * 8 +
              (size_t)(Nt + 1 + kStencilRowsBound) * 4 + (size_t)E * 8;
+    if (galerkin && bilinear && coarsest && !fine) {
+        const size_t n = (size_t)(N + 1) * (Nt + 1);
+        if (n <= (size_t)kStencilLuMax) b += 2 * n * n * 8 + 2 * n * 4;
+    }
     if (precision == STMG_MIXED) b += kCoefArrays * (size_t)(N + 1) * 4;
     if (coarsest) b += 3 * (size_t)(N + 1) * 8 + (N <= kDenseCoarsestMax ? (size_t)N * N * 8 : 0);
     if (precision == STMG_FP64 || fine) b += 3 * (size_t)E * 8;
@@ -302,7 +310,7 @@ size_t footprint_of(const stmg_problem* p, const stmg_options* o) {
                 if (!want) last = true;
             }
             total += level_bytes(N, Nt, o->precision, lev == 1, last, pipelined_options(o),
-                                 o->reassembly == STMG_REASSEMBLE_P);
+                                 o->reassembly == STMG_REASSEMBLE_P, o->interp == STMG_INTERP_B);
             if (last) break;
             if (want == 'x') { N /= 2; h *= 2; } else { Nt /= 2; tau *= 2; }
             ++lev;
@@ -322,7 +330,8 @@ size_t footprint_of(const stmg_problem* p, const stmg_options* o) {
             if (!last && !can_x(f.N) && !can_t(f.Nt)) last = true;
             worst = std::max(worst, level_bytes(f.N, f.Nt, o->precision, lev == 1, true,
                                                 pipelined_options(o),
-                                                o->reassembly == STMG_REASSEMBLE_P));
+                                                o->reassembly == STMG_REASSEMBLE_P,
+                                                o->interp == STMG_INTERP_B));
             if (!last) {
                 any_continue = true;
                 if (can_x(f.N)) next.push_back({f.N / 2, f.Nt});
@@ -473,7 +482,16 @@ int galerkin_levels(stmg_ctx* h) {
         launch_galerkin(view<double>(f, h->o.omega), i == 0 ? nullptr : &fs, f.dir, h->o.interp,
                         stencil_view(c), c.srep, h->o.omega, c.sten, h->s);
     }
-    if (nl > 1) launch_stencil_thomas(stencil_view(h->L[nl - 1]), h->L[nl - 1].sfac, h->s);
+    if (nl > 1) {
+        Level& c = h->L[nl - 1];
+        if (c.lu) {
+            const int64_t n = c.dofs();
+            launch_stencil_lu(stencil_view(c), 0, c.lu, c.piv, h->s);
+            launch_stencil_lu(stencil_view(c), 1, c.lu + n * n, c.piv + n, h->s);
+        } else {
+            launch_stencil_thomas(stencil_view(c), c.sfac, h->s);
+        }
+    }
     HIPCHK(hipGetLastError());
     return 0;
 }
@@ -536,10 +554,20 @@ int build(stmg_ctx* h, const double* d_q) {
                                                    std::to_string(kStencilCoarsestMaxNodes) +
                                                    " nodes (allow more levels)");
             const Level& f = h->L[i - 1];
-            stencil_rows(f.hrow, f.Nt, f.dir, l.hrow, l.hrep);
+            stencil_rows(f.hrow, f.Nt, f.dir, h->o.interp, l.hrow, l.hrep);
             l.R = (int)l.hrep.size();
             CHK(h->alloc(&l.sten, 10 * (int64_t)l.R * l.P));
-            if (last) CHK(h->alloc(&l.sfac, 4 * (int64_t)l.R * l.P));
+            if (last && h->o.interp == STMG_INTERP_B) {
+                const int64_t n = l.dofs();
+                if (n > kStencilLuMax)
+                    return fail(STMG_EUNSUPPORTED, "bilinear Galerkin coarsest level above " +
+                                                       std::to_string(kStencilLuMax) +
+                                                       " DOFs (allow more levels)");
+                CHK(h->alloc(&l.lu, 2 * n * n));
+                CHK(h->alloc(&l.piv, 2 * n));
+            } else if (last) {
+                CHK(h->alloc(&l.sfac, 4 * (int64_t)l.R * l.P));
+            }
             CHK(h->alloc(&l.w, l.elems()));   // residual of the fused pre-smoothing pass
             CHK(h->alloc(&l.srow, (int64_t)l.Nt + 1));
             CHK(h->alloc(&l.srep, (int64_t)l.R));
@@ -615,9 +643,14 @@ std::vector<int> chunks_of(int nu) {
     return c;
 }
 
+// Galerkin levels run the streaming passes with the fused kernels and causal
+// interpolation; bilinear Galerkin levels couple to the next time level as well.
+bool stencil_streams(const stmg_ctx* h) { return h->o.fused && h->o.interp == STMG_INTERP_C; }
+
 // nu damped Jacobi steps on a Galerkin level (stored stencil), in place: streaming
-// passes of up to kStencilMaxFused steps with the fused kernels, else one launch per
-// step.  head ('x' / 't'): the first pass adds the prolongation of z (pitch Pz) first;
+// passes of up to kStencilMaxFused steps with the fused kernels and causal
+// interpolation (the stencil then couples to earlier time levels only), else one
+// launch per step.  head ('x' / 't'): the first pass adds the prolongation of z (pitch Pz) first;
 // r: the last pass also writes the residual there (both only with the fused kernels,
 // which the caller checks).
 int stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu, char head = 0,
@@ -625,10 +658,11 @@ int stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu, c
     const StencilView S = stencil_view(lv);
     bool zero = zero_start;
     int left = nu;
+    const bool stream = stencil_streams(h);
     while (left > 0) {
         const int passes = (left + kStencilMaxFused - 1) / kStencilMaxFused;
-        const int k = h->o.fused ? (left + passes - 1) / passes : 1;
-        if (h->o.fused) {
+        const int k = stream ? (left + passes - 1) / passes : 1;
+        if (stream) {
             StencilPass p{trans, k, lv.u, lv.b, lv.t, zero, head, z, Pz, left == k ? r : nullptr};
             if (launch_stencil_fused(S, p, h->s) != 0) return fail(STMG_EINVAL, "bad stencil pass");
             head = 0;
@@ -650,7 +684,7 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
     const auto V = view<T>(lv, h->o.omega);
     if constexpr (std::is_same<T, double>::value) {
         if (lv.sten) {
-            if (h->o.fused && nu > 0) {
+            if (stencil_streams(h) && nu > 0) {
                 // the last smoothing pass writes the residual into the third vector
                 CHK(stencil_smooth(h, lv, trans, zero_start, nu, 0, nullptr, 0, lv.w));
                 launch_restrict<double>(lv.dir, V, lv.w, cl.b, cl.P, h->s, h->o.interp);
@@ -733,7 +767,7 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
     if constexpr (std::is_same<T, double>::value) {
         if (lv.sten) {
             // norms are taken on the finest level only, which is never a stencil level
-            if (h->o.fused && nu > 0) {
+            if (stencil_streams(h) && nu > 0) {
                 CHK(stencil_smooth(h, lv, trans, false, nu, lv.dir, z, cl.P));
             } else {
                 launch_prolong_add<double>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
@@ -785,6 +819,13 @@ int coarsest_solve(stmg_ctx* h, int l, int trans) {
     Level& lv = h->L[l];
     const auto V = view<double>(lv, h->o.omega);
     if constexpr (std::is_same<T, double>::value) {
+        if (lv.sten && lv.lu) {
+            const int64_t n = lv.dofs();
+            launch_stencil_lu_solve(stencil_view(lv), lv.lu + trans * n * n, lv.piv + trans * n, lv.b,
+                                    lv.u, lv.t, h->s);
+            HIPCHK(hipGetLastError());
+            return 0;
+        }
         if (lv.sten) {
             launch_stencil_coarsest(stencil_view(lv), lv.sfac, trans, lv.b, lv.u, h->s);
             HIPCHK(hipGetLastError());

@@ -134,6 +134,13 @@ struct StencilPass {
 };
 // -1 (nothing launched) for sweeps outside 1..kStencilMaxFused or a head with a residual
 int launch_stencil_fused(const StencilView& V, const StencilPass& p, hipStream_t s);
+// exact solve of a stencil level with couplings to the next time level (bilinear
+// interpolation): band LU with partial pivoting of the dense n x n operator,
+// n = (N+1)(Nt+1) <= kStencilLuMax; A: n*n doubles, piv: n ints, scratch: n doubles
+constexpr int kStencilLuMax = 16384;
+void launch_stencil_lu(const StencilView& S, int trans, double* A, int* piv, hipStream_t s);
+void launch_stencil_lu_solve(const StencilView& S, const double* A, const int* piv, const double* b,
+                             double* z, double* scratch, hipStream_t s);
 // factors: 4 arrays of E doubles (cp, inv of J's blocks, then of J^T's), per stored row
 void launch_stencil_thomas(const StencilView& S, double* factors, hipStream_t s);
 void launch_stencil_coarsest(const StencilView& S, const double* factors, int trans,

@@ -91,14 +91,25 @@ def test_null_arguments():
     assert B.lib.stmg_status_string(B.STMG_DIVERGED) == b"diverged"
 
 
-def test_galerkin_needs_causal_interpolation_and_fp64():
+def test_galerkin_needs_fp64():
     p = B.Problem(16, 16).c_struct()
-    for extra in ({"interp": B.STMG_INTERP_B}, {"precision": B.STMG_MIXED}):
-        o = B.make_options(reassembly=B.STMG_REASSEMBLE_P, **extra)
-        h = C.c_void_p()
-        rc = B.lib.stmg_create(C.byref(h), C.byref(p), C.byref(o), C.c_void_p(1), None, None)
-        assert rc == B.STMG_EINVAL
-        assert b"Galerkin" in B.lib.stmg_last_error()
+    o = B.make_options(reassembly=B.STMG_REASSEMBLE_P, precision=B.STMG_MIXED)
+    h = C.c_void_p()
+    rc = B.lib.stmg_create(C.byref(h), C.byref(p), C.byref(o), C.c_void_p(1), None, None)
+    assert rc == B.STMG_EINVAL
+    assert b"Galerkin" in B.lib.stmg_last_error()
+
+
+def test_footprint_counts_the_bilinear_galerkin_coarsest_factors():
+    p = B.Problem(64, 64).c_struct()
+    sizes = {}
+    for interp in (B.STMG_INTERP_C, B.STMG_INTERP_B):
+        o = B.make_options(reassembly=B.STMG_REASSEMBLE_P, interp=interp, deff_mode=1,
+                           max_levels=2)
+        n = C.c_size_t()
+        assert B.lib.stmg_footprint(C.byref(p), C.byref(o), C.byref(n)) == 0
+        sizes[interp] = n.value
+    assert sizes[B.STMG_INTERP_B] > sizes[B.STMG_INTERP_C] + 2 * (33 * 65) ** 2 * 8 - 1
 
 
 C_CONSUMER = r"""

@@ -148,3 +148,26 @@ def test_two_grid_crossover_uniform_material(cuda):
             s.close()
         print(log2lam, {k: round(v, 3) for k, v in f.items()})
         assert f[winner] < f["t" if winner == "x" else "x"]
+
+
+def test_bp_method_blows_up_on_problem7(cuda):
+    """Section 5.2: bilinear interpolation with Galerkin coarse operators (BP) is stable
+    up to 4 levels on problem 7 and diverges beyond; its estimated factor reaches about
+    4e31 at 10 levels (the oracle gives the same)."""
+    from paper_2505_10168_amd import binding as B
+    n, L = 256, 0.1
+    prob = B.Problem(n, n, length=L, t_final=10.0, k_ins=0.197, k_con=214.0, c_ins=1.67e6,
+                     c_con=2.41e6, theta_ref=1e6)
+    rho = to_dev(I.ramp_design(n, L, 5.0 / L, L / 2), cuda)
+    q = to_dev(I.paper_heat_load(n, n, L, 10.0), cuda)
+    st = {}
+    for nl in (4, 5, 10):
+        s = B.Solver(prob, rho, q=q, nu=5, lambda_crit=0.25, max_levels=nl, tol=1e-9,
+                     max_cycles=100, reassembly=B.STMG_REASSEMBLE_P, interp=B.STMG_INTERP_B)
+        _, st[nl] = s.solve_forward()
+        s.close()
+        print(nl, st[nl].status, st[nl].cycles, f"{st[nl].conv_factor:.4g}")
+    assert st[4].status == 0 and st[4].conv_factor < 0.6
+    assert st[5].status == B.STMG_DIVERGED
+    assert st[10].status == B.STMG_DIVERGED
+    assert st[10].conv_factor == pytest.approx(4e31, rel=0.15)

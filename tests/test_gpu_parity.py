@@ -236,6 +236,8 @@ VARIANTS = [
     ("B_ramp", "ramp_300x256", {"interp": 1}, {"interp": "B"}),
     ("P_block", "block_256x600", {"reassembly": 3}, {"reassembly": "P"}),
     ("P_ramp", "ramp_300x256", {"reassembly": 3}, {"reassembly": "P"}),
+    ("BP_block", "block_256x600", {"reassembly": 3, "interp": 1}, {"reassembly": "P", "interp": "B"}),
+    ("BP_ramp", "ramp_300x256", {"reassembly": 3, "interp": 1}, {"reassembly": "P", "interp": "B"}),
 ]
 
 
@@ -287,14 +289,18 @@ def test_bilinear_fused_and_reference_identical(transpose, cuda):
 
 @pytest.mark.parametrize("name", ["block_256x600", "ramp_300x256"])
 @pytest.mark.parametrize("transpose", [0, 1])
-def test_galerkin_levels_match_oracle(name, transpose, cuda):
+@pytest.mark.parametrize("interp", ["C", "B"])
+def test_galerkin_levels_match_oracle(name, transpose, interp, cuda):
     """P reassembly: every coarse operator R J P (stored stencil) applied, and the
-    coarsest level solved by time stepping, against the oracle's sparse products."""
+    coarsest level solved exactly (time stepping for C, band LU for B), against the
+    oracle's sparse products."""
     import scipy.sparse.linalg as spla
 
     from paper_2505_10168_amd import binding as B
-    s, _, lv, h = make_pair(name, cuda, reassembly=B.STMG_REASSEMBLE_P)
-    h = O.build_hierarchy(lv, O.Options(material=h.opts.material, nu=h.opts.nu, reassembly="P"))
+    s, _, lv, h = make_pair(name, cuda, reassembly=B.STMG_REASSEMBLE_P,
+                            interp=B.STMG_INTERP_B if interp == "B" else B.STMG_INTERP_C)
+    h = O.build_hierarchy(lv, O.Options(material=h.opts.material, nu=h.opts.nu, reassembly="P",
+                                        interp=interp))
     info = s.info()
     assert info["path"] == h.path and info["tail_level"] == -1
     rng = np.random.default_rng(4)
