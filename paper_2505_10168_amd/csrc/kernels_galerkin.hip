@@ -426,59 +426,81 @@ void launch_stencil_thomas(const StencilView& S, double* factors, hipStream_t s)
 }
 
 // Exact solve on a stencil level whose rows couple only to their own and the previous
-// time level (J; for J^T: the next one, stepping backwards).  One workgroup: the
-// right-hand side of a time level is formed in parallel, then thread 0 runs the
-// Thomas recurrence from LDS.
-constexpr int kStencilSolveThreads = 1024;
+// time level (J; for J^T: the next one, stepping backwards).  One workgroup, one node
+// per thread: the right-hand side of a time level is formed in parallel from the
+// previous level's solution in LDS (the next level's b is already loading), then
+// thread 0 runs the Thomas recurrence from LDS.
+constexpr int kStencilSolveThreads = kStencilCoarsestMaxNodes;   // one node per thread
 __global__ __launch_bounds__(kStencilSolveThreads) void k_stencil_coarsest(
     StencilView S, const double* __restrict__ f, int trans, const double* __restrict__ b,
     double* __restrict__ z) {
-    __shared__ double r[kStencilCoarsestMaxNodes];
+    // solutions of the current and the previous time level, and the Thomas factors
+    // of the current row class
+    __shared__ double xs[2][kStencilCoarsestMaxNodes];
     __shared__ double lo[kStencilCoarsestMaxNodes];
     __shared__ double cp[kStencilCoarsestMaxNodes];
     __shared__ double inv[kStencilCoarsestMaxNodes];
+    const int i = threadIdx.x;
+    const bool act = i <= S.N;
     const int64_t E = S.E, P = S.P;
     const double* fcp = f + (trans ? 2 : 0) * E;
     const double* finv = f + (trans ? 3 : 1) * E;
+    // coupling of node i to the previous (J) or next (J^T) level at columns i-1, i, i+1
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+    int key = -1;
+    double bnext = act ? b[(int64_t)(trans ? S.Nt : 0) * P + i] : 0.0;
     for (int step = 0; step <= S.Nt; ++step) {
         const int n = trans ? S.Nt - step : step;
-        const int64_t row = (int64_t)n * P;                 // vectors
-        const int64_t crow = (int64_t)S.row[n] * P;         // coefficients and factors
-        for (int i = threadIdx.x; i <= S.N; i += blockDim.x) {
-            double v = b[row + i];
-            if (!trans && n >= 1) {
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int j = i + dx;
-                    if (j >= 0 && j <= S.N) v -= S.s[(dx + 1) * E + crow + i] * z[row - P + j];
-                }
-            } else if (trans && n < S.Nt) {
-                const int64_t nrow = (int64_t)S.row[n + 1] * P;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int j = i + dx;
-                    if (j >= 0 && j <= S.N) v -= S.s[(1 - dx) * E + nrow + j] * z[row + P + j];
+        const int cur = step & 1, prv = cur ^ 1;
+        const int rn = S.row[n];
+        const int rk = trans ? (n < S.Nt ? S.row[n + 1] : -1) : rn;
+        const int nk = rn * 64 + (rk + 1);
+        if (nk != key) {   // wave-uniform: the row class changes only near the ends
+            key = nk;
+            if (act) {
+                const int64_t cr = (int64_t)rn * P;
+                lo[i] = i == 0 ? 0.0 : (trans ? S.s[5 * E + cr + i - 1] : S.s[3 * E + cr + i]);
+                cp[i] = fcp[cr + i];
+                inv[i] = finv[cr + i];
+                if (trans) {
+                    const int64_t nr = (int64_t)(rk < 0 ? 0 : rk) * P;
+                    c0 = (rk >= 0 && i >= 1) ? S.s[2 * E + nr + i - 1] : 0.0;
+                    c1 = rk >= 0 ? S.s[1 * E + nr + i] : 0.0;
+                    c2 = (rk >= 0 && i + 1 <= S.N) ? S.s[0 * E + nr + i + 1] : 0.0;
+                } else {
+                    c0 = S.s[0 * E + cr + i];
+                    c1 = S.s[1 * E + cr + i];
+                    c2 = S.s[2 * E + cr + i];
                 }
             }
-            r[i] = v;
-            lo[i] = i == 0 ? 0.0 : (trans ? S.s[5 * E + crow + i - 1] : S.s[3 * E + crow + i]);
-            cp[i] = fcp[crow + i];
-            inv[i] = finv[crow + i];
+            __syncthreads();
+        }
+        if (act) {
+            double v = bnext;
+            if (trans ? n < S.Nt : n >= 1) {   // terms in the order dx = -1, 0, 1
+                if (i >= 1) v -= c0 * xs[prv][i - 1];
+                v -= c1 * xs[prv][i];
+                if (i + 1 <= S.N) v -= c2 * xs[prv][i + 1];
+            }
+            xs[cur][i] = v;
+            if (step < S.Nt) bnext = b[(int64_t)(trans ? n - 1 : n + 1) * P + i];
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (i == 0) {
+            double* x = xs[cur];
             double d = 0.0;
-            for (int i = 0; i <= S.N; ++i) {
-                d = (r[i] - lo[i] * d) * inv[i];
-                r[i] = d;
+            for (int k = 0; k <= S.N; ++k) {
+                d = (x[k] - lo[k] * d) * inv[k];
+                x[k] = d;
             }
-            double x = 0.0;
-            for (int i = S.N; i >= 0; --i) {
-                x = r[i] - cp[i] * x;
-                r[i] = x;
+            double y = 0.0;
+            for (int k = S.N; k >= 0; --k) {
+                y = x[k] - cp[k] * y;
+                x[k] = y;
             }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i <= S.N; i += blockDim.x) z[row + i] = r[i];
-        __syncthreads();
+        if (act) z[(int64_t)n * P + i] = xs[cur][i];
     }
 }
 

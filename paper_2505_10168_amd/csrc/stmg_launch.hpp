@@ -107,7 +107,7 @@ struct StencilView {
     const double* s;
 };
 // widest coarsest stencil level the time-stepping solve takes (nodes per time level)
-constexpr int kStencilCoarsestMaxNodes = 1536;
+constexpr int kStencilCoarsestMaxNodes = 1024;
 // cs = stored rows of R J P for the level below F (shape C, representative time level
 // crep[r] for stored row r): from F's rediscretised operator when fsv is null, else from
 // F's stored stencil
