@@ -71,3 +71,26 @@ def test_edge_grids_mixed_precision(case, transpose, cuda):
     assert st.status == 0 and st.rel_residual < 1e-10
     assert rel(to_np(x), ref) <= 1e-8
     s.close()
+
+
+@pytest.mark.parametrize("extra", [{"interp": 1}, {"reassembly": 1}, {"reassembly": 2},
+                                   {"M_min_elems": 100}],
+                         ids=["B", "K", "D", "M_guard"])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_variants_in_mixed_precision(extra, transpose, cuda):
+    """The method variants with FP32 inner cycles reach the FP64 residual 1e-10 and the
+    direct solution."""
+    from paper_2505_10168_amd import binding as B
+    rho, n_t, kmin = I.block_density(256, 16, seed=7), 600, 1e-3
+    prob = B.Problem(len(rho), n_t, k_ins=kmin)
+    s = B.Solver(prob, to_dev(rho, cuda), nu=5, precision=B.STMG_MIXED, max_cycles=400, **extra)
+    mat, lv, h = oracle_setup(rho, n_t, kmin, nu=5)
+    b = O.load_vector(lv, 1.0)
+    if transpose:
+        b = O.adjoint_rhs(lv, b)
+    x, st = (s.solve_adjoint if transpose else s.solve_forward)(to_dev(b, cuda))
+    ref = O.direct_solve(lv, b, transpose=bool(transpose))
+    print(extra, st.cycles, f"{st.rel_residual:.2e}", f"{rel(to_np(x), ref):.1e}")
+    assert st.status == 0 and st.rel_residual < 1e-10
+    assert rel(to_np(x), ref) <= 1e-8
+    s.close()
