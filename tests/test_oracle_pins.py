@@ -549,3 +549,27 @@ def test_bp_method_blows_up_on_problem7_as_printed():
     # the causal Galerkin method (CP) stays stable on the same path
     cp = factor(10, interp="C")
     assert cp.status == "converged" and cp.conv_factor < 0.6
+
+
+@pytest.mark.parametrize("interp", ["C", "B"])
+@pytest.mark.parametrize("direction", ["x", "t"])
+def test_galerkin_two_grid_removes_prolonged_errors(interp, direction):
+    """With J_c = R J P the coarse-grid correction u + P J_c^-1 R (b - J u) removes every
+    error of the form P z exactly (it is the oblique projection along range(P)); the
+    rediscretised coarse operators do not.  A cycle without smoothing is that correction."""
+    rng = np.random.default_rng(21)
+    lv = random_level(8, 12, seed=5)
+    b = O.load_vector(lv, 1.0)
+    x = O.direct_solve(lv, b)
+    Pt, Px, s = O.transfer_pair(lv, direction, interp)
+    zshape = (Pt.shape[1], Px.shape[1])
+    z = rng.standard_normal(zshape)
+    u0 = x + O.prolong(lv, direction, z, interp)
+    errs = {}
+    for method in ("P", "R"):
+        h = O.build_hierarchy(lv, O.Options(nu=0, reassembly=method, interp=interp,
+                                            force_path=direction))
+        u1 = O.vcycle(h, 0, u0.copy(), b)
+        errs[method] = np.abs(u1 - x).max() / np.abs(x).max()
+    assert errs["P"] <= 1e-12
+    assert errs["R"] > 1e-6
