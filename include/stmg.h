@@ -50,7 +50,9 @@ extern "C" {
 #define STMG_REASSEMBLE_K     1   /* average conductivity                           */
 #define STMG_REASSEMBLE_D     2   /* average the design field, then apply SIMP      */
 #define STMG_REASSEMBLE_P     3   /* Galerkin: J^(l+1) = R J^(l) P (K-averaged k, c
-                                     still steer the coarsening decision); FP64 only;
+                                     still steer the coarsening decision); in mixed
+                                     precision the FP32 cycles use an FP32 copy of the
+                                     FP64 products and the coarsest solve stays FP64;
                                      with bilinear interpolation the coarsest level
                                      must have at most 16384 DOFs                     */
 

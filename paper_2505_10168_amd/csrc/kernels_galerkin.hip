@@ -135,44 +135,44 @@ void launch_galerkin(const LevelView<double>& F, const StencilView* fsv, char di
 // y = J x, b - J x or x + (omega / J_ii) (b - J x) with a stored stencil (the scale is
 // the stencil's array 9).  The transpose
 // reads row (n + dt, i + dx)'s coefficient of (n, i), i.e. array 8 - k there.
-template <int TR>
-__global__ void k_apply_stencil(StencilView S, int mode, const double* __restrict__ x,
-                                const double* __restrict__ b, double* __restrict__ y, int zero_in) {
+template <typename T, int TR>
+__global__ void k_apply_stencil(StencilViewT<T> S, int mode, const T* __restrict__ x,
+                                const T* __restrict__ b, T* __restrict__ y, int zero_in) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > S.N) return;
     const int64_t P = S.P, E = S.E;
     for (int n = blockIdx.y; n <= S.Nt; n += gridDim.y) {
         const int64_t o = (int64_t)n * P + i;
         const int64_t co = (int64_t)S.row[n] * P + i;   // this row's coefficients
-        double Jx = 0.0;
+        T Jx = T(0);
         if (!zero_in) {
             for (int k = 0; k < 9; ++k) {
                 const int nn = n + k / 3 - 1, ii = i + k % 3 - 1;
                 if (nn < 0 || nn > S.Nt || ii < 0 || ii > S.N) continue;
                 const int64_t q = (int64_t)nn * P + ii;
-                const double c = TR ? S.s[(8 - k) * E + (int64_t)S.row[nn] * P + ii]
-                                    : S.s[k * E + co];
-                Jx = __builtin_fma(c, x[q], Jx);
+                const T c = TR ? S.s[(8 - k) * E + (int64_t)S.row[nn] * P + ii] : S.s[k * E + co];
+                Jx = fmaT(c, x[q], Jx);
             }
         }
         if (mode == APPLY_J) {
             y[o] = Jx;
         } else {
-            const double r = b[o] - Jx;
+            const T r = b[o] - Jx;
             if (mode == APPLY_RESIDUAL) y[o] = r;
-            else y[o] = __builtin_fma(S.s[9 * E + co], r, zero_in ? 0.0 : x[o]);
+            else y[o] = fmaT(S.s[9 * E + co], r, zero_in ? T(0) : x[o]);
         }
     }
 }
 
-void launch_apply_stencil(const StencilView& S, int trans, int mode, const double* x,
-                          const double* b, double* y, bool zero_in, hipStream_t s) {
+template <typename T>
+void launch_apply_stencil(const StencilViewT<T>& S, int trans, int mode, const T* x, const T* b,
+                          T* y, bool zero_in, hipStream_t s) {
     dim3 g(blocks_for(S.N + 1), rows_grid(S.Nt + 1));
     if (trans)
-        hipLaunchKernelGGL(k_apply_stencil<1>, g, dim3(kBlock), 0, s, S, mode, x, b, y,
+        hipLaunchKernelGGL((k_apply_stencil<T, 1>), g, dim3(kBlock), 0, s, S, mode, x, b, y,
                            (int)zero_in);
     else
-        hipLaunchKernelGGL(k_apply_stencil<0>, g, dim3(kBlock), 0, s, S, mode, x, b, y,
+        hipLaunchKernelGGL((k_apply_stencil<T, 0>), g, dim3(kBlock), 0, s, S, mode, x, b, y,
                            (int)zero_in);
 }
 
@@ -197,6 +197,12 @@ __device__ __forceinline__ double lane_from_left(double v) {   // value of lane 
     const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x138, 0xF, 0xF, true);
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
+__device__ __forceinline__ float lane_from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
 __device__ __forceinline__ double lane_from_right(double v) {  // value of lane + 1, 0 at lane 63
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
     const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x130, 0xF, 0xF, true);
@@ -204,11 +210,11 @@ __device__ __forceinline__ double lane_from_right(double v) {  // value of lane 
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-template <int TR, int S, int HEAD, int TAIL>
+template <typename T, int TR, int S, int HEAD, int TAIL>
 __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stencil_fused(
-    StencilView V, const double* __restrict__ u, const double* __restrict__ b,
-    double* __restrict__ out, int zero_in, const double* __restrict__ z, int64_t Pz,
-    double* __restrict__ rout, int xw, int seg, int nwaves) {
+    StencilViewT<T> V, const T* __restrict__ u, const T* __restrict__ b, T* __restrict__ out,
+    int zero_in, const T* __restrict__ z, int64_t Pz, T* __restrict__ rout, int xw, int seg,
+    int nwaves) {
     constexpr int H = S + (TAIL ? 1 : 0);             // halo lanes per side, warm-up rows
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kStencilWavesPerBlock +
                                                     (int)(threadIdx.x >> 6));
@@ -224,23 +230,23 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
     const int first = TR ? min(V.Nt, n1 - 1 + H) : max(0, n0 - H);
     const int count = TR ? first - n0 + 1 : n1 - first;
 
-    double prev[S + 1];
+    T prev[S + 1];
 #pragma unroll
-    for (int k = 0; k <= S; ++k) prev[k] = 0.0;
+    for (int k = 0; k <= S; ++k) prev[k] = T(0);
     // coefficients of the current row class: J: (row n: dt = -1 at dx = -1, 0, 1, then
     // dt = 0); J^T: (row n at columns i-1, i, i+1, then row n+1 at i-1, i, i+1)
-    double c[6] = {0, 0, 0, 0, 0, 0}, wd = 0.0;
+    T c[6] = {T(0), T(0), T(0), T(0), T(0), T(0)}, wd = T(0);
     int key = -1;
     // rows are loaded two levels ahead of use: the row classes (wave-uniform), u, b and
     // the coarse values of the head
     constexpr int NZ = HEAD == 1 ? 2 : (HEAD == 2 ? 1 : 0);
-    double ru[2] = {0, 0}, rb[2] = {0, 0}, rz[2][NZ > 0 ? NZ : 1] = {};
+    T ru[2] = {T(0), T(0)}, rb[2] = {T(0), T(0)}, rz[2][NZ > 0 ? NZ : 1] = {};
     int rc[2] = {0, 0}, rc1[2] = {-1, -1};
     auto fetch = [&](int it, int slot) {
-        ru[slot] = 0.0;
-        rb[slot] = 0.0;
+        ru[slot] = T(0);
+        rb[slot] = T(0);
 #pragma unroll
-        for (int q = 0; q < NZ; ++q) rz[slot][q] = 0.0;
+        for (int q = 0; q < NZ; ++q) rz[slot][q] = T(0);
         if (it >= count) return;
         const int n = TR ? first - it : first + it;
         rc[slot] = V.row[n];
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
         if (!zero_in) ru[slot] = u[o];
         rb[slot] = b[o];
         if (HEAD == 1) {
-            const double* zr = z + (int64_t)n * Pz + (i >> 1);
+            const T* zr = z + (int64_t)n * Pz + (i >> 1);
             rz[slot][0] = zr[0];
             if (i & 1) rz[slot][NZ - 1] = zr[1];
         } else if (HEAD == 2) {
@@ -262,12 +268,12 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
     for (int it = 0; it < count; ++it) {
         const int n = TR ? first - it : first + it;
         const int slot = it & 1;
-        double cur = ru[slot];
-        const double bb = rb[slot];
+        T cur = ru[slot];
+        const T bb = rb[slot];
         const int rn = rc[slot];
         const int rk = TR ? rc1[slot] : 0;
         if (HEAD == 1 && valid)   // the expressions of k_prolong_x
-            cur = (i & 1) ? __builtin_fma(0.5, rz[slot][0] + rz[slot][NZ - 1], cur)
+            cur = (i & 1) ? fmaT(T(0.5), rz[slot][0] + rz[slot][NZ - 1], cur)
                           : cur + rz[slot][0];
         else if (HEAD == 2 && valid)
             cur = cur + rz[slot][0];
@@ -279,62 +285,62 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
             if (TR) {
                 const int64_t nr = (int64_t)(rk < 0 ? 0 : rk) * P;
                 const bool l = valid && i >= 1, r = valid && i + 1 <= V.N;
-                c[0] = l ? V.s[5 * E + cr + i - 1] : 0.0;
-                c[1] = valid ? V.s[4 * E + cr + i] : 0.0;
-                c[2] = r ? V.s[3 * E + cr + i + 1] : 0.0;
-                c[3] = (l && rk >= 0) ? V.s[2 * E + nr + i - 1] : 0.0;
-                c[4] = (valid && rk >= 0) ? V.s[1 * E + nr + i] : 0.0;
-                c[5] = (r && rk >= 0) ? V.s[0 * E + nr + i + 1] : 0.0;
+                c[0] = l ? V.s[5 * E + cr + i - 1] : T(0);
+                c[1] = valid ? V.s[4 * E + cr + i] : T(0);
+                c[2] = r ? V.s[3 * E + cr + i + 1] : T(0);
+                c[3] = (l && rk >= 0) ? V.s[2 * E + nr + i - 1] : T(0);
+                c[4] = (valid && rk >= 0) ? V.s[1 * E + nr + i] : T(0);
+                c[5] = (r && rk >= 0) ? V.s[0 * E + nr + i + 1] : T(0);
             } else {
 #pragma unroll
-                for (int k = 0; k < 6; ++k) c[k] = valid ? V.s[k * E + cr + i] : 0.0;
+                for (int k = 0; k < 6; ++k) c[k] = valid ? V.s[k * E + cr + i] : T(0);
             }
-            wd = valid ? V.s[9 * E + cr + i] : 0.0;
+            wd = valid ? V.s[9 * E + cr + i] : T(0);
         }
         const int64_t o = (int64_t)n * P + i;
 #pragma unroll
         for (int k = 1; k <= S; ++k) {
-            const double xm = lane_from_left(cur), xp = lane_from_right(cur);
-            const double pm = lane_from_left(prev[k - 1]), pp = lane_from_right(prev[k - 1]);
-            double acc = 0.0;
+            const T xm = lane_from_left(cur), xp = lane_from_right(cur);
+            const T pm = lane_from_left(prev[k - 1]), pp = lane_from_right(prev[k - 1]);
+            T acc = T(0);
             if (TR) {   // level n first, then level n + 1
-                acc = __builtin_fma(c[0], xm, acc);
-                acc = __builtin_fma(c[1], cur, acc);
-                acc = __builtin_fma(c[2], xp, acc);
-                acc = __builtin_fma(c[3], pm, acc);
-                acc = __builtin_fma(c[4], prev[k - 1], acc);
-                acc = __builtin_fma(c[5], pp, acc);
+                acc = fmaT(c[0], xm, acc);
+                acc = fmaT(c[1], cur, acc);
+                acc = fmaT(c[2], xp, acc);
+                acc = fmaT(c[3], pm, acc);
+                acc = fmaT(c[4], prev[k - 1], acc);
+                acc = fmaT(c[5], pp, acc);
             } else {    // level n - 1 first, then level n
-                acc = __builtin_fma(c[0], pm, acc);
-                acc = __builtin_fma(c[1], prev[k - 1], acc);
-                acc = __builtin_fma(c[2], pp, acc);
-                acc = __builtin_fma(c[3], xm, acc);
-                acc = __builtin_fma(c[4], cur, acc);
-                acc = __builtin_fma(c[5], xp, acc);
+                acc = fmaT(c[0], pm, acc);
+                acc = fmaT(c[1], prev[k - 1], acc);
+                acc = fmaT(c[2], pp, acc);
+                acc = fmaT(c[3], xm, acc);
+                acc = fmaT(c[4], cur, acc);
+                acc = fmaT(c[5], xp, acc);
             }
             // invalid lanes have wd = 0 and zero data: they stay 0
-            const double y = __builtin_fma(wd, bb - acc, cur);
+            const T y = fmaT(wd, bb - acc, cur);
             prev[k - 1] = cur;
             cur = y;
         }
         if (TAIL) {   // residual of y_S at this level, before prev[S] moves on
-            const double xm = lane_from_left(cur), xp = lane_from_right(cur);
-            const double pm = lane_from_left(prev[S]), pp = lane_from_right(prev[S]);
-            double acc = 0.0;
+            const T xm = lane_from_left(cur), xp = lane_from_right(cur);
+            const T pm = lane_from_left(prev[S]), pp = lane_from_right(prev[S]);
+            T acc = T(0);
             if (TR) {
-                acc = __builtin_fma(c[0], xm, acc);
-                acc = __builtin_fma(c[1], cur, acc);
-                acc = __builtin_fma(c[2], xp, acc);
-                acc = __builtin_fma(c[3], pm, acc);
-                acc = __builtin_fma(c[4], prev[S], acc);
-                acc = __builtin_fma(c[5], pp, acc);
+                acc = fmaT(c[0], xm, acc);
+                acc = fmaT(c[1], cur, acc);
+                acc = fmaT(c[2], xp, acc);
+                acc = fmaT(c[3], pm, acc);
+                acc = fmaT(c[4], prev[S], acc);
+                acc = fmaT(c[5], pp, acc);
             } else {
-                acc = __builtin_fma(c[0], pm, acc);
-                acc = __builtin_fma(c[1], prev[S], acc);
-                acc = __builtin_fma(c[2], pp, acc);
-                acc = __builtin_fma(c[3], xm, acc);
-                acc = __builtin_fma(c[4], cur, acc);
-                acc = __builtin_fma(c[5], xp, acc);
+                acc = fmaT(c[0], pm, acc);
+                acc = fmaT(c[1], prev[S], acc);
+                acc = fmaT(c[2], pp, acc);
+                acc = fmaT(c[3], xm, acc);
+                acc = fmaT(c[4], cur, acc);
+                acc = fmaT(c[5], xp, acc);
             }
             if (useful && n >= n0 && n < n1) rout[o] = bb - acc;
         }
@@ -371,8 +377,8 @@ __global__ void k_stencil_thomas(StencilView S, double* __restrict__ f) {
     }
 }
 
-template <int TR, int S, int HEAD, int TAIL>
-void launch_stencil_fused_s(const StencilView& V, const StencilPass& p, hipStream_t s) {
+template <typename T, int TR, int S, int HEAD, int TAIL>
+void launch_stencil_fused_s(const StencilViewT<T>& V, const StencilPass<T>& p, hipStream_t s) {
     constexpr int H = S + (TAIL ? 1 : 0);
     const int U = kStencilWave - 2 * H;
     const int xw = (V.N + 1 + U - 1) / U;
@@ -388,35 +394,36 @@ void launch_stencil_fused_s(const StencilView& V, const StencilPass& p, hipStrea
     if (seg & 1) ++seg;
     const int nw = (int)(xw * ((rows + seg - 1) / seg));
     const int blocks = (nw + kStencilWavesPerBlock - 1) / kStencilWavesPerBlock;
-    hipLaunchKernelGGL((k_stencil_fused<TR, S, HEAD, TAIL>), dim3(blocks),
+    hipLaunchKernelGGL((k_stencil_fused<T, TR, S, HEAD, TAIL>), dim3(blocks),
                        dim3(kStencilWave * kStencilWavesPerBlock), 0, s, V, p.u, p.b, p.out,
                        (int)p.zero_in, p.z, p.Pz, p.r, xw, (int)seg, nw);
 }
 
-template <int TR, int S>
-void launch_stencil_fused_ht(const StencilView& V, const StencilPass& p, hipStream_t s) {
-    if (p.r) launch_stencil_fused_s<TR, S, 0, 1>(V, p, s);
-    else if (p.head == 'x') launch_stencil_fused_s<TR, S, 1, 0>(V, p, s);
-    else if (p.head == 't') launch_stencil_fused_s<TR, S, 2, 0>(V, p, s);
-    else launch_stencil_fused_s<TR, S, 0, 0>(V, p, s);
+template <typename T, int TR, int S>
+void launch_stencil_fused_ht(const StencilViewT<T>& V, const StencilPass<T>& p, hipStream_t s) {
+    if (p.r) launch_stencil_fused_s<T, TR, S, 0, 1>(V, p, s);
+    else if (p.head == 'x') launch_stencil_fused_s<T, TR, S, 1, 0>(V, p, s);
+    else if (p.head == 't') launch_stencil_fused_s<T, TR, S, 2, 0>(V, p, s);
+    else launch_stencil_fused_s<T, TR, S, 0, 0>(V, p, s);
 }
 
-template <int TR>
-void launch_stencil_fused_t(const StencilView& V, const StencilPass& p, hipStream_t s) {
+template <typename T, int TR>
+void launch_stencil_fused_t(const StencilViewT<T>& V, const StencilPass<T>& p, hipStream_t s) {
     switch (p.sweeps) {
-        case 1: launch_stencil_fused_ht<TR, 1>(V, p, s); break;
-        case 2: launch_stencil_fused_ht<TR, 2>(V, p, s); break;
-        case 3: launch_stencil_fused_ht<TR, 3>(V, p, s); break;
-        case 4: launch_stencil_fused_ht<TR, 4>(V, p, s); break;
-        case 5: launch_stencil_fused_ht<TR, 5>(V, p, s); break;
-        default: launch_stencil_fused_ht<TR, 6>(V, p, s); break;
+        case 1: launch_stencil_fused_ht<T, TR, 1>(V, p, s); break;
+        case 2: launch_stencil_fused_ht<T, TR, 2>(V, p, s); break;
+        case 3: launch_stencil_fused_ht<T, TR, 3>(V, p, s); break;
+        case 4: launch_stencil_fused_ht<T, TR, 4>(V, p, s); break;
+        case 5: launch_stencil_fused_ht<T, TR, 5>(V, p, s); break;
+        default: launch_stencil_fused_ht<T, TR, 6>(V, p, s); break;
     }
 }
 
-int launch_stencil_fused(const StencilView& V, const StencilPass& p, hipStream_t s) {
+template <typename T>
+int launch_stencil_fused(const StencilViewT<T>& V, const StencilPass<T>& p, hipStream_t s) {
     if (p.sweeps < 1 || p.sweeps > kStencilMaxFused || (p.r && p.head)) return -1;
-    if (p.trans) launch_stencil_fused_t<1>(V, p, s);
-    else launch_stencil_fused_t<0>(V, p, s);
+    if (p.trans) launch_stencil_fused_t<T, 1>(V, p, s);
+    else launch_stencil_fused_t<T, 0>(V, p, s);
     return 0;
 }
 
@@ -429,11 +436,13 @@ void launch_stencil_thomas(const StencilView& S, double* factors, hipStream_t s)
 // time level (J; for J^T: the next one, stepping backwards).  One workgroup, one node
 // per thread: the right-hand side of a time level is formed in parallel from the
 // previous level's solution in LDS (the next level's b is already loading), then
-// thread 0 runs the Thomas recurrence from LDS.
+// thread 0 runs the Thomas recurrence from LDS.  The arithmetic is FP64 whatever the
+// vector type TV of b and z.
 constexpr int kStencilSolveThreads = kStencilCoarsestMaxNodes;   // one node per thread
+template <typename TV>
 __global__ __launch_bounds__(kStencilSolveThreads) void k_stencil_coarsest(
-    StencilView S, const double* __restrict__ f, int trans, const double* __restrict__ b,
-    double* __restrict__ z) {
+    StencilView S, const double* __restrict__ f, int trans, const TV* __restrict__ b,
+    TV* __restrict__ z) {
     // solutions of the current and the previous time level, and the Thomas factors
     // of the current row class
     __shared__ double xs[2][kStencilCoarsestMaxNodes];
@@ -448,7 +457,7 @@ __global__ __launch_bounds__(kStencilSolveThreads) void k_stencil_coarsest(
     // coupling of node i to the previous (J) or next (J^T) level at columns i-1, i, i+1
     double c0 = 0.0, c1 = 0.0, c2 = 0.0;
     int key = -1;
-    double bnext = act ? b[(int64_t)(trans ? S.Nt : 0) * P + i] : 0.0;
+    double bnext = act ? (double)b[(int64_t)(trans ? S.Nt : 0) * P + i] : 0.0;
     for (int step = 0; step <= S.Nt; ++step) {
         const int n = trans ? S.Nt - step : step;
         const int cur = step & 1, prv = cur ^ 1;
@@ -483,7 +492,7 @@ __global__ __launch_bounds__(kStencilSolveThreads) void k_stencil_coarsest(
                 if (i + 1 <= S.N) v -= c2 * xs[prv][i + 1];
             }
             xs[cur][i] = v;
-            if (step < S.Nt) bnext = b[(int64_t)(trans ? n - 1 : n + 1) * P + i];
+            if (step < S.Nt) bnext = (double)b[(int64_t)(trans ? n - 1 : n + 1) * P + i];
         }
         __syncthreads();
         if (i == 0) {
@@ -500,13 +509,14 @@ __global__ __launch_bounds__(kStencilSolveThreads) void k_stencil_coarsest(
             }
         }
         __syncthreads();
-        if (act) z[(int64_t)n * P + i] = xs[cur][i];
+        if (act) z[(int64_t)n * P + i] = (TV)xs[cur][i];
     }
 }
 
-void launch_stencil_coarsest(const StencilView& S, const double* factors, int trans,
-                             const double* b, double* z, hipStream_t s) {
-    hipLaunchKernelGGL(k_stencil_coarsest, dim3(1), dim3(kStencilSolveThreads), 0, s, S, factors,
+template <typename TV>
+void launch_stencil_coarsest(const StencilView& S, const double* factors, int trans, const TV* b,
+                             TV* z, hipStream_t s) {
+    hipLaunchKernelGGL(k_stencil_coarsest<TV>, dim3(1), dim3(kStencilSolveThreads), 0, s, S, factors,
                        trans, b, z);
 }
 
@@ -603,15 +613,18 @@ void launch_stencil_lu(const StencilView& S, int trans, double* A, int* piv, hip
 }
 
 // z = A^-1 b from the factors: L (unit, band b, with the interchanges) forward and U
-// (band 2b) backward, one workgroup; x: n doubles of scratch in global memory
+// (band 2b) backward, one workgroup; x: n doubles of scratch in global memory.  FP64
+// arithmetic whatever the vector type TV of b and z.
+template <typename TV>
 __global__ __launch_bounds__(kLuThreads) void k_lu_solve(StencilView S, const double* __restrict__ A,
                                                       const int* __restrict__ piv,
-                                                      const double* __restrict__ bv,
-                                                      double* __restrict__ z, double* x) {
+                                                      const TV* __restrict__ bv,
+                                                      TV* __restrict__ z, double* x) {
     const int W = S.N + 1;
     const int n = W * (S.Nt + 1);
     const int b = S.N + 2;
-    for (int r = threadIdx.x; r < n; r += kLuThreads) x[r] = bv[(int64_t)(r / W) * S.P + r % W];
+    for (int r = threadIdx.x; r < n; r += kLuThreads)
+        x[r] = (double)bv[(int64_t)(r / W) * S.P + r % W];
     __syncthreads();
     // the factorization swapped rows from the pivot column on only (earlier multipliers
     // stay in place), so each interchange is applied just before its elimination step
@@ -635,12 +648,30 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_solve(StencilView S, const do
         if (threadIdx.x == 0) x[k] = xk;
         __syncthreads();
     }
-    for (int r = threadIdx.x; r < n; r += kLuThreads) z[(int64_t)(r / W) * S.P + r % W] = x[r];
+    for (int r = threadIdx.x; r < n; r += kLuThreads) z[(int64_t)(r / W) * S.P + r % W] = (TV)x[r];
 }
 
-void launch_stencil_lu_solve(const StencilView& S, const double* A, const int* piv, const double* b,
-                             double* z, double* scratch, hipStream_t s) {
-    hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(kLuThreads), 0, s, S, A, piv, b, z, scratch);
+template <typename TV>
+void launch_stencil_lu_solve(const StencilView& S, const double* A, const int* piv, const TV* b,
+                             TV* z, double* scratch, hipStream_t s) {
+    hipLaunchKernelGGL(k_lu_solve<TV>, dim3(1), dim3(kLuThreads), 0, s, S, A, piv, b, z, scratch);
 }
+
+template void launch_apply_stencil<double>(const StencilViewT<double>&, int, int, const double*,
+                                           const double*, double*, bool, hipStream_t);
+template void launch_apply_stencil<float>(const StencilViewT<float>&, int, int, const float*,
+                                          const float*, float*, bool, hipStream_t);
+template int launch_stencil_fused<double>(const StencilViewT<double>&, const StencilPass<double>&,
+                                          hipStream_t);
+template int launch_stencil_fused<float>(const StencilViewT<float>&, const StencilPass<float>&,
+                                         hipStream_t);
+template void launch_stencil_coarsest<double>(const StencilView&, const double*, int,
+                                              const double*, double*, hipStream_t);
+template void launch_stencil_coarsest<float>(const StencilView&, const double*, int, const float*,
+                                             float*, hipStream_t);
+template void launch_stencil_lu_solve<double>(const StencilView&, const double*, const int*,
+                                              const double*, double*, double*, hipStream_t);
+template void launch_stencil_lu_solve<float>(const StencilView&, const double*, const int*,
+                                             const float*, float*, double*, hipStream_t);
 
 }  // namespace stmg

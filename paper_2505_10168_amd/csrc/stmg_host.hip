@@ -61,9 +61,11 @@ struct Level {
     double* thomas = nullptr;  // coarsest: cp, inv, rhs scratch (3 (N+1))
     double* ainv = nullptr;    // coarsest with N <= kDenseCoarsestMax: A^{-1}, N x N
     double* sten = nullptr;    // Galerkin levels: 9-point stencil and Jacobi scale, 10 arrays of R rows of P
+    float* sten32 = nullptr;   // and its FP32 copy for the FP32 inner cycles
     double* sfac = nullptr;    // coarsest Galerkin level: Thomas factors, 4 arrays of R P
     double* lu = nullptr;      // coarsest bilinear Galerkin level: LU factors of J, J^T (2 n^2)
     int* piv = nullptr;        // and their interchanges (2 n)
+    double* lux = nullptr;     // and the FP64 work vector of their solves (n)
     int R = 0;                 // stored stencil rows
     int* srow = nullptr;       // device: time level -> stored row (Nt+1)
     int* srep = nullptr;       // device: stored row -> its representative time level (R)
@@ -76,12 +78,19 @@ struct Level {
     float* u32 = nullptr;
     float* b32 = nullptr;
     float* t32 = nullptr;
+    float* w32 = nullptr;    // Galerkin levels, FP32 inner cycles: residual of the fused pre-smoothing pass
     int64_t elems() const { return (int64_t)(Nt + 1) * P; }
     int64_t dofs() const { return dofs_of(N, Nt); }
 };
 
 StencilView stencil_view(const Level& l) {
     return StencilView{l.N, l.Nt, l.P, l.R, (int64_t)l.R * l.P, l.srow, l.sten};
+}
+// the stored stencil in the vector type of a cycle
+template <typename T>
+StencilViewT<T> sview(const Level& l) {
+    if constexpr (std::is_same<T, double>::value) return stencil_view(l);
+    else return StencilViewT<float>{l.N, l.Nt, l.P, l.R, (int64_t)l.R * l.P, l.srow, l.sten32};
 }
 
 // Stored-row classes of a Galerkin level.  A coarse row's stencil is fixed by the
@@ -123,6 +132,11 @@ template <> double*& Tt<double>(Level& l) { return l.t; }
 template <> float*& U<float>(Level& l) { return l.u32; }
 template <> float*& B<float>(Level& l) { return l.b32; }
 template <> float*& Tt<float>(Level& l) { return l.t32; }
+// Galerkin levels: residual of the fused pre-smoothing pass
+template <typename T> T* Wr(Level& l) {
+    if constexpr (std::is_same<T, double>::value) return l.w;
+    else return l.w32;
+}
 
 template <typename T>
 LevelView<T> view(const Level& l, double omega);
@@ -242,8 +256,6 @@ int validate(const stmg_problem* p, const stmg_options* o) {
     if (o->max_cycles < 1 || o->max_cycles > STMG_MAX_HISTORY)
         return fail(STMG_EINVAL, "max_cycles must be in [1, STMG_MAX_HISTORY]");
     if (o->reassembly < 0 || o->reassembly > 3) return fail(STMG_EINVAL, "unknown reassembly method");
-    if (o->reassembly == STMG_REASSEMBLE_P && o->precision != STMG_FP64)
-        return fail(STMG_EINVAL, "Galerkin reassembly needs FP64");
     if (o->deff_mode < 0 || o->deff_mode > 1) return fail(STMG_EINVAL, "unknown deff_mode");
     if (o->precision != STMG_FP64 && o->precision != STMG_MIXED)
         return fail(STMG_EINVAL, "unknown precision");
@@ -268,12 +280,14 @@ size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest, bool 
     const int64_t P = pitch_for(N), E = (int64_t)(Nt + 1) * P;
     size_t b = 3 * (size_t)N * 8 + kCoefArrays * (size_t)(N + 1) * 8;
     // stored stencil rows: at most kStencilRowsBound (3 or 4 in practice)
-    if (galerkin && !fine)
-        b += (10 + (coarsest ? 4 : 0)) * (size_t)std::min(Nt + 1, kStencilRowsBound) * P * 8 +
-             (size_t)(Nt + 1 + kStencilRowsBound) * 4 + (size_t)E * 8;
+    if (galerkin && !fine) {
+        const size_t rows = (size_t)std::min(Nt + 1, kStencilRowsBound) * P;
+        b += (10 + (coarsest ? 4 : 0)) * rows * 8 + (size_t)(Nt + 1 + kStencilRowsBound) * 4;
+        b += precision == STMG_MIXED ? 10 * rows * 4 + (size_t)E * 4 : (size_t)E * 8;
+    }
     if (galerkin && bilinear && coarsest && !fine) {
         const size_t n = (size_t)(N + 1) * (Nt + 1);
-        if (n <= (size_t)kStencilLuMax) b += 2 * n * n * 8 + 2 * n * 4;
+        if (n <= (size_t)kStencilLuMax) b += 2 * n * n * 8 + 2 * n * 4 + n * 8;
     }
     if (precision == STMG_MIXED) b += kCoefArrays * (size_t)(N + 1) * 4;
     if (coarsest) b += 3 * (size_t)(N + 1) * 8 + (N <= kDenseCoarsestMax ? (size_t)N * N * 8 : 0);
@@ -481,6 +495,8 @@ int galerkin_levels(stmg_ctx* h) {
         const StencilView fs = stencil_view(f);
         launch_galerkin(view<double>(f, h->o.omega), i == 0 ? nullptr : &fs, f.dir, h->o.interp,
                         stencil_view(c), c.srep, h->o.omega, c.sten, h->s);
+        if (c.sten32)
+            launch_copy2d<double, float>(c.sten, c.P, c.sten32, c.P, 10 * c.R, c.N + 1, 1.0, h->s);
     }
     if (nl > 1) {
         Level& c = h->L[nl - 1];
@@ -557,6 +573,7 @@ int build(stmg_ctx* h, const double* d_q) {
             stencil_rows(f.hrow, f.Nt, f.dir, h->o.interp, l.hrow, l.hrep);
             l.R = (int)l.hrep.size();
             CHK(h->alloc(&l.sten, 10 * (int64_t)l.R * l.P));
+            if (h->o.precision == STMG_MIXED) CHK(h->alloc(&l.sten32, 10 * (int64_t)l.R * l.P));
             if (last && h->o.interp == STMG_INTERP_B) {
                 const int64_t n = l.dofs();
                 if (n > kStencilLuMax)
@@ -565,10 +582,13 @@ int build(stmg_ctx* h, const double* d_q) {
                                                        " DOFs (allow more levels)");
                 CHK(h->alloc(&l.lu, 2 * n * n));
                 CHK(h->alloc(&l.piv, 2 * n));
+                CHK(h->alloc(&l.lux, n));
             } else if (last) {
                 CHK(h->alloc(&l.sfac, 4 * (int64_t)l.R * l.P));
             }
-            CHK(h->alloc(&l.w, l.elems()));   // residual of the fused pre-smoothing pass
+            // residual of the fused pre-smoothing pass
+            if (h->o.precision == STMG_MIXED) CHK(h->alloc(&l.w32, l.elems()));
+            else CHK(h->alloc(&l.w, l.elems()));
             CHK(h->alloc(&l.srow, (int64_t)l.Nt + 1));
             CHK(h->alloc(&l.srep, (int64_t)l.R));
             HIPCHK(hipMemcpyAsync(l.srow, l.hrow.data(), l.hrow.size() * sizeof(int),
@@ -653,9 +673,13 @@ bool stencil_streams(const stmg_ctx* h) { return h->o.fused && h->o.interp == ST
 // launch per step.  head ('x' / 't'): the first pass adds the prolongation of z (pitch Pz) first;
 // r: the last pass also writes the residual there (both only with the fused kernels,
 // which the caller checks).
+template <typename T>
 int stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu, char head = 0,
-                   const double* z = nullptr, int64_t Pz = 0, double* r = nullptr) {
-    const StencilView S = stencil_view(lv);
+                   const T* z = nullptr, int64_t Pz = 0, T* r = nullptr) {
+    const StencilViewT<T> S = sview<T>(lv);
+    T*& u = U<T>(lv);
+    T* b = B<T>(lv);
+    T*& t = Tt<T>(lv);
     bool zero = zero_start;
     int left = nu;
     const bool stream = stencil_streams(h);
@@ -663,17 +687,17 @@ int stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu, c
         const int passes = (left + kStencilMaxFused - 1) / kStencilMaxFused;
         const int k = stream ? (left + passes - 1) / passes : 1;
         if (stream) {
-            StencilPass p{trans, k, lv.u, lv.b, lv.t, zero, head, z, Pz, left == k ? r : nullptr};
-            if (launch_stencil_fused(S, p, h->s) != 0) return fail(STMG_EINVAL, "bad stencil pass");
+            StencilPass<T> p{trans, k, u, b, t, zero, head, z, Pz, left == k ? r : nullptr};
+            if (launch_stencil_fused<T>(S, p, h->s) != 0) return fail(STMG_EINVAL, "bad stencil pass");
             head = 0;
         } else {
-            launch_apply_stencil(S, trans, APPLY_JACOBI, lv.u, lv.b, lv.t, zero, h->s);
+            launch_apply_stencil<T>(S, trans, APPLY_JACOBI, u, b, t, zero, h->s);
         }
-        std::swap(lv.u, lv.t);
+        std::swap(u, t);
         zero = false;
         left -= k;
     }
-    if (nu == 0 && zero_start) launch_fill<double>(lv.u, lv.elems(), 0.0, h->s);
+    if (nu == 0 && zero_start) launch_fill<T>(u, lv.elems(), T(0), h->s);
     return 0;
 }
 
@@ -682,21 +706,19 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
     Level& lv = h->L[l];
     Level& cl = h->L[l + 1];
     const auto V = view<T>(lv, h->o.omega);
-    if constexpr (std::is_same<T, double>::value) {
-        if (lv.sten) {
-            if (stencil_streams(h) && nu > 0) {
-                // the last smoothing pass writes the residual into the third vector
-                CHK(stencil_smooth(h, lv, trans, zero_start, nu, 0, nullptr, 0, lv.w));
-                launch_restrict<double>(lv.dir, V, lv.w, cl.b, cl.P, h->s, h->o.interp);
-            } else {
-                CHK(stencil_smooth(h, lv, trans, zero_start, nu));
-                launch_apply_stencil(stencil_view(lv), trans, APPLY_RESIDUAL, lv.u, lv.b, lv.t,
-                                     false, h->s);
-                launch_restrict<double>(lv.dir, V, lv.t, cl.b, cl.P, h->s, h->o.interp);
-            }
-            HIPCHK(hipGetLastError());
-            return 0;
+    if (lv.sten) {
+        if (stencil_streams(h) && nu > 0) {
+            // the last smoothing pass writes the residual into the third vector
+            CHK(stencil_smooth<T>(h, lv, trans, zero_start, nu, 0, nullptr, 0, Wr<T>(lv)));
+            launch_restrict<T>(lv.dir, V, Wr<T>(lv), B<T>(cl), cl.P, h->s, h->o.interp);
+        } else {
+            CHK(stencil_smooth<T>(h, lv, trans, zero_start, nu));
+            launch_apply_stencil<T>(sview<T>(lv), trans, APPLY_RESIDUAL, U<T>(lv), B<T>(lv),
+                                    Tt<T>(lv), false, h->s);
+            launch_restrict<T>(lv.dir, V, Tt<T>(lv), B<T>(cl), cl.P, h->s, h->o.interp);
         }
+        HIPCHK(hipGetLastError());
+        return 0;
     }
     T*& u = U<T>(lv);
     T* b = B<T>(lv);
@@ -764,18 +786,16 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
     const T* z = U<T>(cl);
     const bool timed = l == 0 && h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
     const bool split = lv.dir == 't' && h->o.interp == STMG_INTERP_B;
-    if constexpr (std::is_same<T, double>::value) {
-        if (lv.sten) {
-            // norms are taken on the finest level only, which is never a stencil level
-            if (stencil_streams(h) && nu > 0) {
-                CHK(stencil_smooth(h, lv, trans, false, nu, lv.dir, z, cl.P));
-            } else {
-                launch_prolong_add<double>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
-                CHK(stencil_smooth(h, lv, trans, false, nu));
-            }
-            HIPCHK(hipGetLastError());
-            return 0;
+    if (lv.sten) {
+        // norms are taken on the finest level only, which is never a stencil level
+        if (stencil_streams(h) && nu > 0) {
+            CHK(stencil_smooth<T>(h, lv, trans, false, nu, lv.dir, z, cl.P));
+        } else {
+            launch_prolong_add<T>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
+            CHK(stencil_smooth<T>(h, lv, trans, false, nu));
         }
+        HIPCHK(hipGetLastError());
+        return 0;
     }
     if (h->o.fused) {
         if (split) launch_prolong_add<T>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
@@ -818,19 +838,18 @@ template <typename T>
 int coarsest_solve(stmg_ctx* h, int l, int trans) {
     Level& lv = h->L[l];
     const auto V = view<double>(lv, h->o.omega);
-    if constexpr (std::is_same<T, double>::value) {
-        if (lv.sten && lv.lu) {
-            const int64_t n = lv.dofs();
-            launch_stencil_lu_solve(stencil_view(lv), lv.lu + trans * n * n, lv.piv + trans * n, lv.b,
-                                    lv.u, lv.t, h->s);
-            HIPCHK(hipGetLastError());
-            return 0;
-        }
-        if (lv.sten) {
-            launch_stencil_coarsest(stencil_view(lv), lv.sfac, trans, lv.b, lv.u, h->s);
-            HIPCHK(hipGetLastError());
-            return 0;
-        }
+    // FP64 arithmetic on the vectors of the cycle
+    if (lv.sten && lv.lu) {
+        const int64_t n = lv.dofs();
+        launch_stencil_lu_solve<T>(stencil_view(lv), lv.lu + trans * n * n, lv.piv + trans * n,
+                                   B<T>(lv), U<T>(lv), lv.lux, h->s);
+        HIPCHK(hipGetLastError());
+        return 0;
+    }
+    if (lv.sten) {
+        launch_stencil_coarsest<T>(stencil_view(lv), lv.sfac, trans, B<T>(lv), U<T>(lv), h->s);
+        HIPCHK(hipGetLastError());
+        return 0;
     }
     if (lv.ainv)
         launch_coarsest_dense<T>(V, lv.ainv, B<T>(lv), U<T>(lv), trans, h->s);
@@ -1397,7 +1416,7 @@ int stmg_level_apply(stmg_t h, int level, int transpose, const double* d_x, doub
     Level& l = h->L[level];
     CHK(copy_in(h, l, d_x, l.u));
     if (l.sten)
-        launch_apply_stencil(stencil_view(l), transpose, APPLY_J, l.u, l.b, l.t, false, h->s);
+        launch_apply_stencil<double>(stencil_view(l), transpose, APPLY_J, l.u, l.b, l.t, false, h->s);
     else
         launch_apply<double>(view<double>(l, h->o.omega), transpose, APPLY_J, l.u, l.b, l.t, false,
                              h->s);
@@ -1414,7 +1433,7 @@ int stmg_level_smooth(stmg_t h, int level, int transpose, int nu, const double* 
     CHK(copy_in(h, l, d_u, l.u));
     const auto V = view<double>(l, h->o.omega);
     if (l.sten) {
-        CHK(stencil_smooth(h, l, transpose, false, nu));
+        CHK(stencil_smooth<double>(h, l, transpose, false, nu));
     } else if (h->o.fused) {
         for (int S : chunks_of(nu)) {
             FusedPass fp{};

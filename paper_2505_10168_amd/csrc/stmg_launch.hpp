@@ -97,15 +97,17 @@ void launch_oc_update(const double* chi, const double* grad, int n, double volum
 // 10 arrays of E = R P doubles (R stored rows of P); array 3 (dt+1) + (dx+1) holds at
 // (row[n], i) the coefficient of x(n+dt, i+dx) in row (n, i), array 9 the Jacobi scale
 // omega / J_ii
-struct StencilView {
+template <typename C>
+struct StencilViewT {
     int N;
     int Nt;
     int64_t P;
     int R;           // stored rows
     int64_t E;       // R P
     const int* row;  // Nt+1 entries: time level -> stored row
-    const double* s;
+    const C* s;      // coefficients (FP64, or their FP32 copy for the FP32 inner cycles)
 };
+using StencilView = StencilViewT<double>;
 // widest coarsest stencil level the time-stepping solve takes (nodes per time level)
 constexpr int kStencilCoarsestMaxNodes = 1024;
 // cs = stored rows of R J P for the level below F (shape C, representative time level
@@ -114,37 +116,44 @@ constexpr int kStencilCoarsestMaxNodes = 1024;
 void launch_galerkin(const LevelView<double>& F, const StencilView* fsv, char dir, int interp,
                      const StencilView& C, const int* crep, double omega, double* cs,
                      hipStream_t s);
-void launch_apply_stencil(const StencilView& S, int trans, int mode, const double* x,
-                          const double* b, double* y, bool zero_in, hipStream_t s);
+template <typename T>
+void launch_apply_stencil(const StencilViewT<T>& S, int trans, int mode, const T* x, const T* b,
+                          T* y, bool zero_in, hipStream_t s);
 // `sweeps` (1..kStencilMaxFused) damped Jacobi steps in one streaming pass, u -> out
 // (distinct buffers); the same values as the prolongation, `sweeps` launches of
 // launch_apply_stencil and the residual launched one after the other
 constexpr int kStencilMaxFused = 6;
+template <typename T>
 struct StencilPass {
     int trans;
     int sweeps;
-    const double* u;
-    const double* b;
-    double* out;
+    const T* u;
+    const T* b;
+    T* out;
     int zero_in;
     char head;          // 0, 'x' or 't': add P z (coarse pitch Pz) to u first
-    const double* z;
+    const T* z;
     int64_t Pz;
-    double* r;          // non-null: also write b - J out here (not with a head)
+    T* r;               // non-null: also write b - J out here (not with a head)
 };
 // -1 (nothing launched) for sweeps outside 1..kStencilMaxFused or a head with a residual
-int launch_stencil_fused(const StencilView& V, const StencilPass& p, hipStream_t s);
+template <typename T>
+int launch_stencil_fused(const StencilViewT<T>& V, const StencilPass<T>& p, hipStream_t s);
 // exact solve of a stencil level with couplings to the next time level (bilinear
 // interpolation): band LU with partial pivoting of the dense n x n operator,
 // n = (N+1)(Nt+1) <= kStencilLuMax; A: n*n doubles, piv: n ints, scratch: n doubles
 constexpr int kStencilLuMax = 16384;
 void launch_stencil_lu(const StencilView& S, int trans, double* A, int* piv, hipStream_t s);
-void launch_stencil_lu_solve(const StencilView& S, const double* A, const int* piv, const double* b,
-                             double* z, double* scratch, hipStream_t s);
+// FP64 arithmetic; vectors of type TV
+template <typename TV>
+void launch_stencil_lu_solve(const StencilView& S, const double* A, const int* piv, const TV* b,
+                             TV* z, double* scratch, hipStream_t s);
 // factors: 4 arrays of E doubles (cp, inv of J's blocks, then of J^T's), per stored row
 void launch_stencil_thomas(const StencilView& S, double* factors, hipStream_t s);
-void launch_stencil_coarsest(const StencilView& S, const double* factors, int trans,
-                             const double* b, double* z, hipStream_t s);
+// FP64 arithmetic; vectors of type TV
+template <typename TV>
+void launch_stencil_coarsest(const StencilView& S, const double* factors, int trans, const TV* b,
+                             TV* z, hipStream_t s);
 
 // ---- fused streaming kernels ----------------------------------------------------------
 // Pass descriptor of one fused streaming launch on a level.

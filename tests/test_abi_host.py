@@ -91,13 +91,22 @@ def test_null_arguments():
     assert B.lib.stmg_status_string(B.STMG_DIVERGED) == b"diverged"
 
 
-def test_galerkin_needs_fp64():
-    p = B.Problem(16, 16).c_struct()
-    o = B.make_options(reassembly=B.STMG_REASSEMBLE_P, precision=B.STMG_MIXED)
-    h = C.c_void_p()
-    rc = B.lib.stmg_create(C.byref(h), C.byref(p), C.byref(o), C.c_void_p(1), None, None)
-    assert rc == B.STMG_EINVAL
-    assert b"Galerkin" in B.lib.stmg_last_error()
+def test_galerkin_footprint_in_mixed_precision():
+    """P in mixed precision is accepted; its footprint counts the FP32 copies of the stored
+    stencils and of the coarse vectors, and no FP64 coarse vectors."""
+    p = B.Problem(64, 64).c_struct()
+    sizes = {}
+    for reas in (B.STMG_REASSEMBLE_R, B.STMG_REASSEMBLE_P):
+        for prec in (B.STMG_FP64, B.STMG_MIXED):
+            o = B.make_options(reassembly=reas, precision=prec, deff_mode=1, max_levels=3)
+            n = C.c_size_t()
+            assert B.lib.stmg_footprint(C.byref(p), C.byref(o), C.byref(n)) == 0
+            sizes[reas, prec] = n.value
+    extra64 = sizes[B.STMG_REASSEMBLE_P, B.STMG_FP64] - sizes[B.STMG_REASSEMBLE_R, B.STMG_FP64]
+    extra32 = sizes[B.STMG_REASSEMBLE_P, B.STMG_MIXED] - sizes[B.STMG_REASSEMBLE_R, B.STMG_MIXED]
+    assert extra32 > 0 and extra64 > 0
+    # the FP64 stencils are kept in both; mixed adds their FP32 copy, FP64 a residual vector
+    assert extra32 != extra64
 
 
 def test_footprint_counts_the_bilinear_galerkin_coarsest_factors():

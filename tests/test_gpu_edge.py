@@ -74,8 +74,9 @@ def test_edge_grids_mixed_precision(case, transpose, cuda):
 
 
 @pytest.mark.parametrize("extra", [{"interp": 1}, {"reassembly": 1}, {"reassembly": 2},
-                                   {"M_min_elems": 100}],
-                         ids=["B", "K", "D", "M_guard"])
+                                   {"M_min_elems": 100}, {"reassembly": 3},
+                                   {"reassembly": 3, "fused": 0}],
+                         ids=["B", "K", "D", "M_guard", "P", "P_one_step"])
 @pytest.mark.parametrize("transpose", [0, 1])
 def test_variants_in_mixed_precision(extra, transpose, cuda):
     """The method variants with FP32 inner cycles reach the FP64 residual 1e-10 and the
@@ -93,4 +94,20 @@ def test_variants_in_mixed_precision(extra, transpose, cuda):
     print(extra, st.cycles, f"{st.rel_residual:.2e}", f"{rel(to_np(x), ref):.1e}")
     assert st.status == 0 and st.rel_residual < 1e-10
     assert rel(to_np(x), ref) <= 1e-8
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_bp_diverges_on_the_variant_case(precision, cuda):
+    """BP on the same case (path xttxtxxx) is unstable (Section 5.2): the oracle's FP64
+    cycles grow the error by about 1e28 per cycle, and both precisions stop with
+    'diverged'.  BP in mixed precision where it converges is covered on small grids."""
+    from paper_2505_10168_amd import binding as B
+    rho, n_t, kmin = I.block_density(256, 16, seed=7), 600, 1e-3
+    prob = B.Problem(len(rho), n_t, k_ins=kmin)
+    s = B.Solver(prob, to_dev(rho, cuda), nu=5, precision=precision, max_cycles=400,
+                 reassembly=B.STMG_REASSEMBLE_P, interp=B.STMG_INTERP_B)
+    assert s.info()["path"] == "xttxtxxx"
+    _, st = s.solve_forward()
+    assert st.status == B.STMG_DIVERGED and st.cycles <= 3
     s.close()

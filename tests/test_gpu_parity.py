@@ -384,6 +384,38 @@ def test_galerkin_edge_cases(case, transpose, cuda):
     s.close()
 
 
+@pytest.mark.parametrize("case", GALERKIN_EDGE, ids=[c[0] for c in GALERKIN_EDGE])
+@pytest.mark.parametrize("interp", [0, 1], ids=["C", "B"])
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_galerkin_edge_cases_mixed_precision(case, interp, transpose, cuda):
+    """P reassembly with FP32 inner cycles (FP32 copies of the stored stencils, FP64
+    coarsest solves) on the same grids: the FP64 residual reaches 1e-10 and the solution
+    the direct one.  On 75 x 64 (path ttt) BP diverges, as the FP64 oracle's cycles do
+    (Section 5.2): the solve must say so."""
+    from paper_2505_10168_amd import binding as B
+    name, rho, n_t, kmin, extra = case
+    prob = B.Problem(len(rho), n_t, k_ins=kmin)
+    # P converges slowly on 75 x 64 (about 0.93 per cycle in the oracle)
+    s = B.Solver(prob, to_dev(rho, cuda), nu=2, reassembly=B.STMG_REASSEMBLE_P,
+                 precision=B.STMG_MIXED, interp=interp, max_cycles=1000, **extra)
+    mat, lv, h = oracle_setup(rho, n_t, kmin, nu=2, reassembly="P",
+                              interp="B" if interp else "C", **extra)
+    assert s.info()["path"] == h.path
+    b = O.load_vector(lv, 1.0)
+    if transpose:
+        b = O.adjoint_rhs(lv, b)
+    x, st = (s.solve_adjoint if transpose else s.solve_forward)(to_dev(b, cuda))
+    print(name, interp, transpose, st.status, st.cycles, f"{st.rel_residual:.2e}")
+    if name == "odd_x_75x64" and interp == 1:
+        assert st.status == B.STMG_DIVERGED
+        s.close()
+        return
+    ref = O.direct_solve(lv, b, transpose=bool(transpose))
+    assert st.status == 0 and st.rel_residual < 1e-10
+    assert rel(to_np(x), ref) <= 1e-8
+    s.close()
+
+
 def test_galerkin_one_level_equals_rediscretised(cuda):
     """With a single level there is no coarse operator: P and R solve the same way."""
     from paper_2505_10168_amd import binding as B
