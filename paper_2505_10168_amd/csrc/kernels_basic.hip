@@ -528,7 +528,8 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 
 // Exact coarsest solve with a register-resident inverse (one wave, node i+1 in lane
 // i): each time step forms b_n + (C/dt) z_{n-1} (z_{n+1} for J^T) in parallel and
-// multiplies by A^{-1}, broadcasting the right-hand side lane by lane.
+// multiplies by A^{-1}, broadcasting the right-hand side lane by lane.  Lanes without a
+// node hold a zero right-hand side and zero rows of A^{-1}.
 template <typename TV, int NMAX>
 __global__ __launch_bounds__(64) void k_coarsest_dense(LevelView<double> L,
                                                        const double* __restrict__ ainv,
@@ -556,18 +557,20 @@ __global__ __launch_bounds__(64) void k_coarsest_dense(LevelView<double> L,
         const bool coupled = trans ? (n < Nt) : (n >= 2);
         double rhs = bn;
         if (s + 1 < Nt) bn = act ? (double)b[(int64_t)row(s + 1) * P + node] : 0.0;
-        const double zl = __shfl_up(zprev, 1, 64);
-        const double zr = __shfl_down(zprev, 1, 64);
+        const double zl = shfl_up1(zprev);   // 0 at lane 0 (node 1 has no coupled left node)
+        const double zr = shfl_dn1(zprev);
         if (coupled) {
             double w = mdi * zprev;
-            w = __builtin_fma(mlo, lane == 0 ? 0.0 : zl, w);
+            w = __builtin_fma(mlo, zl, w);
             w = __builtin_fma(mup, zr, w);
             rhs = rhs + w;
         }
+        if (!act) rhs = 0.0;   // also when a neighbour's value is not finite
+        // a[j] = 0 for j >= N and rhs = 0 on inactive lanes: the terms beyond N add an
+        // exact zero, and the product runs without a branch per term
         double z = 0.0;
 #pragma unroll
-        for (int j = 0; j < NMAX; ++j)
-            if (j < N) z = __builtin_fma(a[j], readlane_f64(rhs, j), z);
+        for (int j = 0; j < NMAX; ++j) z = __builtin_fma(a[j], readlane_f64(rhs, j), z);
         if (act) u[(int64_t)n * P + node] = (TV)z;
         zprev = act ? z : 0.0;
     }

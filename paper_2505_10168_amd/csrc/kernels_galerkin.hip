@@ -191,25 +191,6 @@ void launch_apply_stencil(const StencilViewT<T>& S, int trans, int mode, const T
 constexpr int kStencilWave = 64;
 constexpr int kStencilWavesPerBlock = 4;
 
-__device__ __forceinline__ double lane_from_left(double v) {   // value of lane - 1, 0 at lane 0
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x138, 0xF, 0xF, true);
-    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x138, 0xF, 0xF, true);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-__device__ __forceinline__ float lane_from_left(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
-}
-__device__ __forceinline__ float lane_from_right(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
-}
-__device__ __forceinline__ double lane_from_right(double v) {  // value of lane + 1, 0 at lane 63
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x130, 0xF, 0xF, true);
-    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x130, 0xF, 0xF, true);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 template <typename T, int TR, int S, int HEAD, int TAIL>
 __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stencil_fused(
     StencilViewT<T> V, const T* __restrict__ u, const T* __restrict__ b, T* __restrict__ out,
@@ -300,8 +281,8 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
         const int64_t o = (int64_t)n * P + i;
 #pragma unroll
         for (int k = 1; k <= S; ++k) {
-            const T xm = lane_from_left(cur), xp = lane_from_right(cur);
-            const T pm = lane_from_left(prev[k - 1]), pp = lane_from_right(prev[k - 1]);
+            const T xm = shfl_up1(cur), xp = shfl_dn1(cur);
+            const T pm = shfl_up1(prev[k - 1]), pp = shfl_dn1(prev[k - 1]);
             T acc = T(0);
             if (TR) {   // level n first, then level n + 1
                 acc = fmaT(c[0], xm, acc);
@@ -324,8 +305,8 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
             cur = y;
         }
         if (TAIL) {   // residual of y_S at this level, before prev[S] moves on
-            const T xm = lane_from_left(cur), xp = lane_from_right(cur);
-            const T pm = lane_from_left(prev[S]), pp = lane_from_right(prev[S]);
+            const T xm = shfl_up1(cur), xp = shfl_dn1(cur);
+            const T pm = shfl_up1(prev[S]), pp = shfl_dn1(prev[S]);
             T acc = T(0);
             if (TR) {
                 acc = fmaT(c[0], xm, acc);

@@ -303,22 +303,27 @@ __device__ void tail_coarsest(const LevelView<double>& L, const double* ainv, co
         const double mdi = act ? L.mdi[node] : 0.0;
         const double mup = act ? L.mup[node] : 0.0;
         double zprev = 0.0;
+        // the right-hand side of the next step is read one step ahead
+        double bn = (act && Nt > 0) ? (double)b[(TR ? Nt : 1) * W + node] : 0.0;
         for (int s = 0; s < Nt; ++s) {
             const int n = TR ? Nt - s : 1 + s;
             const bool coupled = TR ? (n < Nt) : (n >= 2);
-            double rhs = act ? (double)b[n * W + node] : 0.0;
-            const double zl = __shfl_up(zprev, 1, 64);
-            const double zr = __shfl_down(zprev, 1, 64);
+            double rhs = bn;
+            if (s + 1 < Nt) bn = act ? (double)b[(TR ? n - 1 : n + 1) * W + node] : 0.0;
+            const double zl = shfl_up1(zprev);   // 0 at lane 0 (node 1 has no coupled left node)
+            const double zr = shfl_dn1(zprev);
             if (coupled) {
                 double w = mdi * zprev;
-                w = __builtin_fma(mlo, lane == 0 ? 0.0 : zl, w);
+                w = __builtin_fma(mlo, zl, w);
                 w = __builtin_fma(mup, zr, w);
                 rhs = rhs + w;
             }
+            if (!act) rhs = 0.0;   // also when a neighbour's value is not finite
+            // a[j] = 0 for j >= N and rhs = 0 on lanes without a node: the terms beyond
+            // N add an exact zero, and the product runs without a branch per term
             double z = 0.0;
 #pragma unroll
-            for (int j = 0; j < NMAX; ++j)
-                if (j < N) z = __builtin_fma(a[j], lane_value(rhs, j), z);
+            for (int j = 0; j < NMAX; ++j) z = __builtin_fma(a[j], lane_value(rhs, j), z);
             if (act) u[n * W + node] = (T)z;
             zprev = act ? z : 0.0;
         }

@@ -42,6 +42,32 @@ struct LevelView {
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Neighbour exchange across the whole wave with DPP wave shifts (ALU latency, no LDS
+// round trip): shfl_up1 gives lane i the value of lane i-1, shfl_dn1 the value of
+// lane i+1; the edge lane (0, resp. 63) receives 0.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)dpp32<CTRL>((int)(unsigned)b);
+    const unsigned hi = (unsigned)dpp32<CTRL>((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double shfl_up1(double v) { return dpp64<kDppWaveShr1>(v); }
+__device__ __forceinline__ double shfl_dn1(double v) { return dpp64<kDppWaveShl1>(v); }
+__device__ __forceinline__ float shfl_up1(float v) {
+    return __int_as_float(dpp32<kDppWaveShr1>(__float_as_int(v)));
+}
+__device__ __forceinline__ float shfl_dn1(float v) {
+    return __int_as_float(dpp32<kDppWaveShl1>(__float_as_int(v)));
+}
+
 // (J x) at an interior DOF (i >= 1, n >= 1), evaluated in difference form
 //   sum_j (C/dt)_ij (x_{j,n} - x_{j,m}) + k_{i-1}/h (x_i - x_{i-1}) + k_i/h (x_i - x_{i+1})
 // which equals sum_j A_ij x_{j,n} - sum_j (C/dt)_ij x_{j,m} but keeps the large,
