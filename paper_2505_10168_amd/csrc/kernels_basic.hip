@@ -519,13 +519,6 @@ void launch_dense_inverse(const double* coef, int N, const double* cp, const dou
     hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(64), 0, s, coef, N, cp, inv, ainv);
 }
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, l);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), l);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // Exact coarsest solve with a register-resident inverse (one wave, node i+1 in lane
 // i): each time step forms b_n + (C/dt) z_{n-1} (z_{n+1} for J^T) in parallel and
 // multiplies by A^{-1}, broadcasting the right-hand side lane by lane.  Lanes without a

@@ -501,6 +501,123 @@ void launch_stencil_coarsest(const StencilView& S, const double* factors, int tr
                        trans, b, z);
 }
 
+// Inverse of the tridiagonal block of every stored row (the couplings of a time level to
+// itself), one thread per stored row and column j: the Thomas solve of J's block with the
+// right-hand side e_j, written as column j of the row-major inverse.
+__global__ void k_stencil_block_inverse(StencilView S, const double* __restrict__ f,
+                                        double* __restrict__ inv) {
+    const int W = S.N + 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S.R * W) return;
+    const int r = t / W, j = t - r * W;
+    const int64_t E = S.E, row = (int64_t)r * S.P;
+    const double* cp = f + row;
+    const double* iv = f + E + row;
+    const double* s3 = S.s + 3 * E + row;
+    double* A = inv + (int64_t)r * W * W;
+    double d = 0.0;
+    for (int k = 0; k <= S.N; ++k) {
+        const double lo = k == 0 ? 0.0 : s3[k];
+        d = ((k == j ? 1.0 : 0.0) - lo * d) * iv[k];
+        A[(int64_t)k * W + j] = d;
+    }
+    double y = 0.0;
+    for (int k = S.N; k >= 0; --k) {
+        y = A[(int64_t)k * W + j] - cp[k] * y;
+        A[(int64_t)k * W + j] = y;
+    }
+}
+
+void launch_stencil_block_inverse(const StencilView& S, const double* factors, double* inv,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(k_stencil_block_inverse, dim3(blocks_for((int64_t)S.R * (S.N + 1))),
+                       dim3(kBlock), 0, s, S, factors, inv);
+}
+
+// The time-stepping solve of k_stencil_coarsest in one wave, node i in lane i: the
+// right-hand side of a time level (the same expression as there, the previous level's
+// solution taken from the neighbour lanes) is multiplied by the inverse of the level's
+// block (its transpose for J^T), held in registers and broadcast lane by lane.  The
+// inverse is zero beyond N and lanes without a node carry a zero right-hand side, so the
+// product runs over NMAX terms without a branch per term.
+template <typename TV, int NMAX>
+__global__ __launch_bounds__(64) void k_stencil_coarsest_dense(StencilView S,
+                                                               const double* __restrict__ ainv,
+                                                               int trans,
+                                                               const TV* __restrict__ b,
+                                                               TV* __restrict__ z) {
+    const int i = threadIdx.x;
+    const int W = S.N + 1;
+    const bool act = i <= S.N;
+    const int64_t E = S.E, P = S.P;
+    double a[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) a[j] = 0.0;
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+    int key = -1;
+    double zprev = 0.0;
+    double bnext = act ? (double)b[(int64_t)(trans ? S.Nt : 0) * P + i] : 0.0;
+    for (int step = 0; step <= S.Nt; ++step) {
+        const int n = trans ? S.Nt - step : step;
+        const int rn = S.row[n];
+        const int rk = trans ? (n < S.Nt ? S.row[n + 1] : -1) : rn;
+        const int nk = rn * 64 + (rk + 1);
+        if (nk != key) {   // wave-uniform: the row class changes only near the ends
+            key = nk;
+            const double* A = ainv + (int64_t)rn * W * W;
+#pragma unroll
+            for (int j = 0; j < NMAX; ++j)
+                a[j] = (act && j < W) ? (trans ? A[(int64_t)j * W + i] : A[(int64_t)i * W + j]) : 0.0;
+            if (act) {
+                const int64_t cr = (int64_t)rn * P;
+                if (trans) {
+                    const int64_t nr = (int64_t)(rk < 0 ? 0 : rk) * P;
+                    c0 = (rk >= 0 && i >= 1) ? S.s[2 * E + nr + i - 1] : 0.0;
+                    c1 = rk >= 0 ? S.s[1 * E + nr + i] : 0.0;
+                    c2 = (rk >= 0 && i + 1 <= S.N) ? S.s[0 * E + nr + i + 1] : 0.0;
+                } else {
+                    c0 = S.s[0 * E + cr + i];
+                    c1 = S.s[1 * E + cr + i];
+                    c2 = S.s[2 * E + cr + i];
+                }
+            }
+        }
+        double v = bnext;
+        if (step < S.Nt) bnext = act ? (double)b[(int64_t)(trans ? n - 1 : n + 1) * P + i] : 0.0;
+        // the previous level's solution at i-1, i+1 (0 beyond the nodes)
+        const double zl = shfl_up1(zprev), zr = shfl_dn1(zprev);
+        if (trans ? n < S.Nt : n >= 1) {   // terms in the order dx = -1, 0, 1
+            v -= c0 * zl;
+            v -= c1 * zprev;
+            v -= c2 * zr;
+        }
+        if (!act) v = 0.0;
+        double y = 0.0;
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j) y = __builtin_fma(a[j], readlane_f64(v, j), y);
+        if (act) z[(int64_t)n * P + i] = (TV)y;
+        zprev = act ? y : 0.0;
+    }
+}
+
+template <typename TV>
+void launch_stencil_coarsest_dense(const StencilView& S, const double* inv, int trans,
+                                   const TV* b, TV* z, hipStream_t s) {
+    const int W = S.N + 1;
+    if (W <= 16)
+        hipLaunchKernelGGL((k_stencil_coarsest_dense<TV, 16>), dim3(1), dim3(64), 0, s, S, inv,
+                           trans, b, z);
+    else if (W <= 32)
+        hipLaunchKernelGGL((k_stencil_coarsest_dense<TV, 32>), dim3(1), dim3(64), 0, s, S, inv,
+                           trans, b, z);
+    else if (W <= 48)
+        hipLaunchKernelGGL((k_stencil_coarsest_dense<TV, 48>), dim3(1), dim3(64), 0, s, S, inv,
+                           trans, b, z);
+    else
+        hipLaunchKernelGGL((k_stencil_coarsest_dense<TV, 64>), dim3(1), dim3(64), 0, s, S, inv,
+                           trans, b, z);
+}
+
 // ---- exact solve of a level whose rows also couple to the next time level ------------
 // (bilinear interpolation with Galerkin operators).  The operator is assembled as a
 // dense n x n matrix, n = (N+1)(Nt+1), DOF (t, i) at index t (N+1) + i, and factored by
@@ -650,6 +767,10 @@ template void launch_stencil_coarsest<double>(const StencilView&, const double*,
                                               const double*, double*, hipStream_t);
 template void launch_stencil_coarsest<float>(const StencilView&, const double*, int, const float*,
                                              float*, hipStream_t);
+template void launch_stencil_coarsest_dense<double>(const StencilView&, const double*, int,
+                                                    const double*, double*, hipStream_t);
+template void launch_stencil_coarsest_dense<float>(const StencilView&, const double*, int,
+                                                   const float*, float*, hipStream_t);
 template void launch_stencil_lu_solve<double>(const StencilView&, const double*, const int*,
                                               const double*, double*, double*, hipStream_t);
 template void launch_stencil_lu_solve<float>(const StencilView&, const double*, const int*,

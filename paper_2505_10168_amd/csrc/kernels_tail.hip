@@ -276,13 +276,6 @@ __device__ void tail_up(const LevelView<T>& F, T* u, const T* b, int dir, const 
     tail_smooth<T, TR>(F, c, o, u, x, bb, nu);
 }
 
-__device__ __forceinline__ double lane_value(double v, int l) {
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, l);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), l);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // Exact coarsest solve (Algorithm 1, first branch) with the precomputed A^{-1}: the
 // Dirichlet DOFs take b / W_Diri, then wave 0 steps through time, lane i holding row
 // i+1 of A^{-1} and the right-hand side broadcast lane by lane.
@@ -323,7 +316,7 @@ __device__ void tail_coarsest(const LevelView<double>& L, const double* ainv, co
             // N add an exact zero, and the product runs without a branch per term
             double z = 0.0;
 #pragma unroll
-            for (int j = 0; j < NMAX; ++j) z = __builtin_fma(a[j], lane_value(rhs, j), z);
+            for (int j = 0; j < NMAX; ++j) z = __builtin_fma(a[j], readlane_f64(rhs, j), z);
             if (act) u[n * W + node] = (T)z;
             zprev = act ? z : 0.0;
         }

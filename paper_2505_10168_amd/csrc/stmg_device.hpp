@@ -59,6 +59,13 @@ __device__ __forceinline__ double dpp64(double v) {
     const unsigned hi = (unsigned)dpp32<CTRL>((int)(unsigned)(b >> 32));
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
+// value of lane l (wave-uniform l), broadcast to the whole wave
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 __device__ __forceinline__ double shfl_up1(double v) { return dpp64<kDppWaveShr1>(v); }
 __device__ __forceinline__ double shfl_dn1(double v) { return dpp64<kDppWaveShl1>(v); }
 __device__ __forceinline__ float shfl_up1(float v) {

@@ -63,6 +63,7 @@ struct Level {
     double* sten = nullptr;    // Galerkin levels: 9-point stencil and Jacobi scale, 10 arrays of R rows of P
     float* sten32 = nullptr;   // and its FP32 copy for the FP32 inner cycles
     double* sfac = nullptr;    // coarsest Galerkin level: Thomas factors, 4 arrays of R P
+    double* sinv = nullptr;    // and, up to kStencilDenseMaxNodes nodes, its blocks' inverses (R (N+1)^2)
     double* lu = nullptr;      // coarsest bilinear Galerkin level: LU factors of J, J^T (2 n^2)
     int* piv = nullptr;        // and their interchanges (2 n)
     double* lux = nullptr;     // and the FP64 work vector of their solves (n)
@@ -285,6 +286,8 @@ size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest, bool 
         b += (10 + (coarsest ? 4 : 0)) * rows * 8 + (size_t)(Nt + 1 + kStencilRowsBound) * 4;
         b += precision == STMG_MIXED ? 10 * rows * 4 + (size_t)E * 4 : (size_t)E * 8;
     }
+    if (galerkin && !bilinear && coarsest && !fine && N + 1 <= kStencilDenseMaxNodes)
+        b += (size_t)kStencilRowsBound * (N + 1) * (N + 1) * 8;   // block inverses
     if (galerkin && bilinear && coarsest && !fine) {
         const size_t n = (size_t)(N + 1) * (Nt + 1);
         if (n <= (size_t)kStencilLuMax) b += 2 * n * n * 8 + 2 * n * 4 + n * 8;
@@ -506,6 +509,7 @@ int galerkin_levels(stmg_ctx* h) {
             launch_stencil_lu(stencil_view(c), 1, c.lu + n * n, c.piv + n, h->s);
         } else {
             launch_stencil_thomas(stencil_view(c), c.sfac, h->s);
+            if (c.sinv) launch_stencil_block_inverse(stencil_view(c), c.sfac, c.sinv, h->s);
         }
     }
     HIPCHK(hipGetLastError());
@@ -585,6 +589,8 @@ int build(stmg_ctx* h, const double* d_q) {
                 CHK(h->alloc(&l.lux, n));
             } else if (last) {
                 CHK(h->alloc(&l.sfac, 4 * (int64_t)l.R * l.P));
+                if (l.N + 1 <= kStencilDenseMaxNodes)
+                    CHK(h->alloc(&l.sinv, (int64_t)l.R * (l.N + 1) * (l.N + 1)));
             }
             // residual of the fused pre-smoothing pass
             if (h->o.precision == STMG_MIXED) CHK(h->alloc(&l.w32, l.elems()));
@@ -843,6 +849,11 @@ int coarsest_solve(stmg_ctx* h, int l, int trans) {
         const int64_t n = lv.dofs();
         launch_stencil_lu_solve<T>(stencil_view(lv), lv.lu + trans * n * n, lv.piv + trans * n,
                                    B<T>(lv), U<T>(lv), lv.lux, h->s);
+        HIPCHK(hipGetLastError());
+        return 0;
+    }
+    if (lv.sten && lv.sinv) {
+        launch_stencil_coarsest_dense<T>(stencil_view(lv), lv.sinv, trans, B<T>(lv), U<T>(lv), h->s);
         HIPCHK(hipGetLastError());
         return 0;
     }

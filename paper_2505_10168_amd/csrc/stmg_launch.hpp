@@ -154,6 +154,17 @@ void launch_stencil_thomas(const StencilView& S, double* factors, hipStream_t s)
 template <typename TV>
 void launch_stencil_coarsest(const StencilView& S, const double* factors, int trans, const TV* b,
                              TV* z, hipStream_t s);
+// coarsest stencil levels of at most kStencilDenseMaxNodes nodes per time level: inv gets
+// the inverse of every stored row's tridiagonal block (R arrays of (N+1)^2 doubles,
+// row-major), formed column by column from the Thomas factors of J
+constexpr int kStencilDenseMaxNodes = 64;
+void launch_stencil_block_inverse(const StencilView& S, const double* factors, double* inv,
+                                  hipStream_t s);
+// the same exact solve as launch_stencil_coarsest with those inverses, in one wave;
+// FP64 arithmetic, vectors of type TV
+template <typename TV>
+void launch_stencil_coarsest_dense(const StencilView& S, const double* inv, int trans,
+                                   const TV* b, TV* z, hipStream_t s);
 
 // ---- fused streaming kernels ----------------------------------------------------------
 // Pass descriptor of one fused streaming launch on a level.
