@@ -20,6 +20,7 @@
 // The arithmetic of each DOF goes through stencil_interior/jacobi_update in the
 // same order as the reference kernels, so both paths give identical bits.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <type_traits>
 
@@ -480,10 +481,22 @@ Geometry geometry(int N, int Nt, int sweeps) {
     return G;
 }
 
+// Launch options: the finest level has kernels of its own; non-null events are recorded
+// at the kernel's own start and end (the dispatch timestamps a profiler reads), so a
+// timing excludes the wait for compute units held by other streams' kernels.
+struct LaunchCfg {
+    bool fine;
+    hipEvent_t start;
+    hipEvent_t stop;
+};
+
 template <typename T, int TR, int S, int TAIL, int HEAD>
-void launch_one(const LevelView<T>& L, const FusedArgs<T>& a, bool fine, hipStream_t s) {
+void launch_one(const LevelView<T>& L, const FusedArgs<T>& a, const LaunchCfg& lc, hipStream_t s) {
     const int blocks = (a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (fine)
+    if (lc.fine && lc.start)
+        hipExtLaunchKernelGGL((k_fused_fine<T, TR, S, TAIL, HEAD>), dim3(blocks),
+                              dim3(kWave * kWavesPerBlock), 0, s, lc.start, lc.stop, 0, L, a);
+    else if (lc.fine)
         hipLaunchKernelGGL((k_fused_fine<T, TR, S, TAIL, HEAD>), dim3(blocks),
                            dim3(kWave * kWavesPerBlock), 0, s, L, a);
     else
@@ -494,41 +507,41 @@ void launch_one(const LevelView<T>& L, const FusedArgs<T>& a, bool fine, hipStre
 // Instantiated combinations: pre-smoothing passes (no head; restriction, norm or no
 // tail) and post-smoothing passes (prolongation head; norm or no tail).
 template <typename T, int TR, int S>
-void dispatch_tail(int tail, const LevelView<T>& L, const FusedArgs<T>& a, bool fine,
+void dispatch_tail(int tail, const LevelView<T>& L, const FusedArgs<T>& a, const LaunchCfg& lc,
                    hipStream_t s) {
     if (a.head == 1) {
         if (tail == TAIL_NORM)
-            launch_one<T, TR, S, TAIL_NORM, 1>(L, a, fine, s);
+            launch_one<T, TR, S, TAIL_NORM, 1>(L, a, lc, s);
         else
-            launch_one<T, TR, S, TAIL_NONE, 1>(L, a, fine, s);
+            launch_one<T, TR, S, TAIL_NONE, 1>(L, a, lc, s);
         return;
     }
     if (a.head == 2) {
         if (tail == TAIL_NORM)
-            launch_one<T, TR, S, TAIL_NORM, 2>(L, a, fine, s);
+            launch_one<T, TR, S, TAIL_NORM, 2>(L, a, lc, s);
         else
-            launch_one<T, TR, S, TAIL_NONE, 2>(L, a, fine, s);
+            launch_one<T, TR, S, TAIL_NONE, 2>(L, a, lc, s);
         return;
     }
     switch (tail) {
-        case TAIL_NONE: launch_one<T, TR, S, TAIL_NONE, 0>(L, a, fine, s); break;
-        case TAIL_RX: launch_one<T, TR, S, TAIL_RX, 0>(L, a, fine, s); break;
-        case TAIL_RT: launch_one<T, TR, S, TAIL_RT, 0>(L, a, fine, s); break;
-        default: launch_one<T, TR, S, TAIL_NORM, 0>(L, a, fine, s); break;
+        case TAIL_NONE: launch_one<T, TR, S, TAIL_NONE, 0>(L, a, lc, s); break;
+        case TAIL_RX: launch_one<T, TR, S, TAIL_RX, 0>(L, a, lc, s); break;
+        case TAIL_RT: launch_one<T, TR, S, TAIL_RT, 0>(L, a, lc, s); break;
+        default: launch_one<T, TR, S, TAIL_NORM, 0>(L, a, lc, s); break;
     }
 }
 
 template <typename T, int TR>
-void dispatch_sweeps(int S, int tail, const LevelView<T>& L, const FusedArgs<T>& a, bool fine,
-                     hipStream_t s) {
+void dispatch_sweeps(int S, int tail, const LevelView<T>& L, const FusedArgs<T>& a,
+                     const LaunchCfg& lc, hipStream_t s) {
     switch (S) {
-        case 0: dispatch_tail<T, TR, 0>(tail, L, a, fine, s); break;
-        case 1: dispatch_tail<T, TR, 1>(tail, L, a, fine, s); break;
-        case 2: dispatch_tail<T, TR, 2>(tail, L, a, fine, s); break;
-        case 3: dispatch_tail<T, TR, 3>(tail, L, a, fine, s); break;
-        case 4: dispatch_tail<T, TR, 4>(tail, L, a, fine, s); break;
-        case 5: dispatch_tail<T, TR, 5>(tail, L, a, fine, s); break;
-        default: dispatch_tail<T, TR, 6>(tail, L, a, fine, s); break;
+        case 0: dispatch_tail<T, TR, 0>(tail, L, a, lc, s); break;
+        case 1: dispatch_tail<T, TR, 1>(tail, L, a, lc, s); break;
+        case 2: dispatch_tail<T, TR, 2>(tail, L, a, lc, s); break;
+        case 3: dispatch_tail<T, TR, 3>(tail, L, a, lc, s); break;
+        case 4: dispatch_tail<T, TR, 4>(tail, L, a, lc, s); break;
+        case 5: dispatch_tail<T, TR, 5>(tail, L, a, lc, s); break;
+        default: dispatch_tail<T, TR, 6>(tail, L, a, lc, s); break;
     }
 }
 
@@ -566,6 +579,7 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
     a.xw = G.xw;
     a.seg = G.seg;
     a.nwaves = G.nwaves;
+    const LaunchCfg lc{fp.fine != 0, fp.ev_start, fp.ev_stop};
     const int tail = fp.tail == 'x' ? TAIL_RX
                      : (fp.tail == 't' ? TAIL_RT : (fp.tail == 'n' ? TAIL_NORM : TAIL_NONE));
     if (fp.tail == 'c' || fp.prolong == 'c') {
@@ -573,18 +587,18 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
         if constexpr (std::is_same<T, double>::value) {
             if (fp.sweeps != 0 || fp.tail != 'c' || fp.prolong != 'c') return -1;
             if (fp.trans)
-                launch_one<T, 1, 0, TAIL_DEFECT, 3>(L, a, fp.fine != 0, s);
+                launch_one<T, 1, 0, TAIL_DEFECT, 3>(L, a, lc, s);
             else
-                launch_one<T, 0, 0, TAIL_DEFECT, 3>(L, a, fp.fine != 0, s);
+                launch_one<T, 0, 0, TAIL_DEFECT, 3>(L, a, lc, s);
             return G.nwaves;
         } else {
             return -1;
         }
     }
     if (fp.trans)
-        dispatch_sweeps<T, 1>(fp.sweeps, tail, L, a, fp.fine != 0, s);
+        dispatch_sweeps<T, 1>(fp.sweeps, tail, L, a, lc, s);
     else
-        dispatch_sweeps<T, 0>(fp.sweeps, tail, L, a, fp.fine != 0, s);
+        dispatch_sweeps<T, 0>(fp.sweeps, tail, L, a, lc, s);
     return G.nwaves;
 }
 

@@ -439,11 +439,19 @@ __global__ __launch_bounds__(kStencilSolveThreads) void k_stencil_coarsest(
     double c0 = 0.0, c1 = 0.0, c2 = 0.0;
     int key = -1;
     double bnext = act ? (double)b[(int64_t)(trans ? S.Nt : 0) * P + i] : 0.0;
+    // row classes of the next time level, read one step ahead
+    auto classes = [&](int step, int& rn, int& rk) {
+        const int n = trans ? S.Nt - step : step;
+        rn = S.row[n];
+        rk = trans ? (n < S.Nt ? S.row[n + 1] : -1) : rn;
+    };
+    int rn_next, rk_next;
+    classes(0, rn_next, rk_next);
     for (int step = 0; step <= S.Nt; ++step) {
         const int n = trans ? S.Nt - step : step;
         const int cur = step & 1, prv = cur ^ 1;
-        const int rn = S.row[n];
-        const int rk = trans ? (n < S.Nt ? S.row[n + 1] : -1) : rn;
+        const int rn = rn_next, rk = rk_next;
+        if (step < S.Nt) classes(step + 1, rn_next, rk_next);
         const int nk = rn * 64 + (rk + 1);
         if (nk != key) {   // wave-uniform: the row class changes only near the ends
             key = nk;
@@ -537,15 +545,17 @@ void launch_stencil_block_inverse(const StencilView& S, const double* factors, d
 // The time-stepping solve of k_stencil_coarsest in one wave, node i in lane i: the
 // right-hand side of a time level (the same expression as there, the previous level's
 // solution taken from the neighbour lanes) is multiplied by the inverse of the level's
-// block (its transpose for J^T), held in registers and broadcast lane by lane.  The
-// inverse is zero beyond N and lanes without a node carry a zero right-hand side, so the
-// product runs over NMAX terms without a branch per term.
+// block (its transpose for J^T), held in registers, with the right-hand side broadcast
+// from LDS.  The inverse is zero beyond N and lanes without a node carry a zero
+// right-hand side, so the product runs over NMAX terms without a branch per term.
 template <typename TV, int NMAX>
 __global__ __launch_bounds__(64) void k_stencil_coarsest_dense(StencilView S,
                                                                const double* __restrict__ ainv,
                                                                int trans,
                                                                const TV* __restrict__ b,
                                                                TV* __restrict__ z) {
+    __shared__ double rs[2][64];
+    __shared__ double bs[64][64];   // [time level within the chunk][lane]
     const int i = threadIdx.x;
     const int W = S.N + 1;
     const bool act = i <= S.N;
@@ -556,11 +566,32 @@ __global__ __launch_bounds__(64) void k_stencil_coarsest_dense(StencilView S,
     double c0 = 0.0, c1 = 0.0, c2 = 0.0;
     int key = -1;
     double zprev = 0.0;
-    double bnext = act ? (double)b[(int64_t)(trans ? S.Nt : 0) * P + i] : 0.0;
+    // Every 64 time levels, one round trip to memory fetches what the next 64 steps read:
+    // each lane's right-hand side column into LDS (only the lane itself reads it back),
+    // and the row classes, one per lane, picked with readlane.  No step then waits on
+    // memory.  J^T couples level n to n + 1, the previous step's.
+    int chunk = 0, rprev = -1;
     for (int step = 0; step <= S.Nt; ++step) {
         const int n = trans ? S.Nt - step : step;
-        const int rn = S.row[n];
-        const int rk = trans ? (n < S.Nt ? S.row[n + 1] : -1) : rn;
+        if ((step & 63) == 0) {
+            const int st = step + i;
+            chunk = st <= S.Nt ? S.row[trans ? S.Nt - st : st] : 0;
+#pragma unroll
+            for (int k0 = 0; k0 < 64; k0 += 16) {
+                double t[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int sk = step + k0 + k;
+                    t[k] = (act && sk <= S.Nt) ? (double)b[(int64_t)(trans ? S.Nt - sk : sk) * P + i]
+                                               : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 16; ++k) bs[k0 + k][i] = t[k];
+            }
+        }
+        const int rn = __builtin_amdgcn_readlane(chunk, step & 63);
+        const int rk = trans ? rprev : rn;
+        rprev = rn;
         const int nk = rn * 64 + (rk + 1);
         if (nk != key) {   // wave-uniform: the row class changes only near the ends
             key = nk;
@@ -582,8 +613,7 @@ __global__ __launch_bounds__(64) void k_stencil_coarsest_dense(StencilView S,
                 }
             }
         }
-        double v = bnext;
-        if (step < S.Nt) bnext = act ? (double)b[(int64_t)(trans ? n - 1 : n + 1) * P + i] : 0.0;
+        double v = bs[step & 63][i];
         // the previous level's solution at i-1, i+1 (0 beyond the nodes)
         const double zl = shfl_up1(zprev), zr = shfl_dn1(zprev);
         if (trans ? n < S.Nt : n >= 1) {   // terms in the order dx = -1, 0, 1
@@ -592,9 +622,16 @@ __global__ __launch_bounds__(64) void k_stencil_coarsest_dense(StencilView S,
             v -= c2 * zr;
         }
         if (!act) v = 0.0;
+        // broadcast through LDS (one wave: its LDS accesses complete in order; two buffers
+        // keep the next level's writes clear of this level's reads); lane-by-lane reads
+        // into scalar registers would need 2 NMAX of them
+        double* rv = rs[step & 1];
+        rv[i] = v;
+        __builtin_amdgcn_wave_barrier();
         double y = 0.0;
 #pragma unroll
-        for (int j = 0; j < NMAX; ++j) y = __builtin_fma(a[j], readlane_f64(v, j), y);
+        for (int j = 0; j < NMAX; ++j) y = __builtin_fma(a[j], rv[j], y);
+        __builtin_amdgcn_wave_barrier();
         if (act) z[(int64_t)n * P + i] = (TV)y;
         zprev = act ? y : 0.0;
     }

@@ -639,7 +639,9 @@ double level_pass_bytes(const Level& l, int sizeofT, bool read_u) {
     return (double)l.dofs() * sizeofT * (read_u ? 3.0 : 2.0);
 }
 
-void timer_begin(stmg_ctx* h, bool on) {
+// The next fine pass records its start and end in a fresh event pair (events recorded by
+// the kernel launch itself: see FusedPass::ev_start).
+void timer_begin(stmg_ctx* h, bool on, FusedPass& fp) {
     if (!on) return;
     KernelTimer& T = h->timer;
     if (T.used == T.ev.size()) {
@@ -649,13 +651,13 @@ void timer_begin(stmg_ctx* h, bool on) {
         T.ev.push_back({a, b});
         T.bytes.push_back(0);
     }
-    (void)hipEventRecord(T.ev[T.used].first, h->s);
+    fp.ev_start = T.ev[T.used].first;
+    fp.ev_stop = T.ev[T.used].second;
 }
 
 void timer_end(stmg_ctx* h, bool on, double bytes) {
     if (!on) return;
     KernelTimer& T = h->timer;
-    (void)hipEventRecord(T.ev[T.used].second, h->s);
     T.bytes[T.used] = bytes;
     ++T.used;
 }
@@ -747,7 +749,7 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
             fp.Nc = cl.N;
             fp.Ntc = cl.Nt;
             fp.fine = l == 0;
-            timer_begin(h, timed);
+            timer_begin(h, timed, fp);
             launch_fused<T>(V, fp, u, b, t, h->s);
             timer_end(h, timed, level_pass_bytes(lv, sizeof(T), !zero) + (lastc ? (double)cl.dofs() * sizeof(T) : 0.0));
             if constexpr (std::is_same<T, double>::value) {
@@ -819,7 +821,7 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
             fp.tail = (lastc && norm) ? 'n' : 0;
             fp.parts = h->parts;
             fp.fine = l == 0;
-            timer_begin(h, timed);
+            timer_begin(h, timed, fp);
             int nw = launch_fused<T>(V, fp, u, b, t, h->s);
             timer_end(h, timed, level_pass_bytes(lv, sizeof(T), true) + (k == 0 ? (double)cl.dofs() * sizeof(T) : 0.0));
             if (lastc && norm) h->norm_parts = nw;
@@ -1124,7 +1126,7 @@ int defect_step(stmg_ctx* h, int trans, double s_e, double s_f, double* norm) {
         fp.parts = h->parts;
         fp.fine = 1;
         const bool timed = h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
-        timer_begin(h, timed);
+        timer_begin(h, timed, fp);
         const int nw = launch_fused<double>(V64, fp, f.u, f.b, f.t, h->s);
         // u, e, b read; u, f written
         timer_end(h, timed, (double)f.dofs() * (8 + 4 + 8 + 8 + 4));

@@ -187,6 +187,8 @@ struct FusedPass {
     double s_old;       // 'c': its scale
     float* f32;         // 'c': FP32 scaled residual output
     double inv_s_new;
+    hipEvent_t ev_start;  // finest level, non-null: recorded at the kernel's own start and end
+    hipEvent_t ev_stop;
 };
 template <typename T>
 int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T* b, T* out,
