@@ -186,17 +186,22 @@ void launch_apply_stencil(const StencilViewT<T>& S, int trans, int mode, const T
 // columns are exchanged between lanes.  The terms of J x are added in the order of
 // k_apply_stencil, so this pass and S one-step launches give the same values.
 // HEAD 1 / 2 first adds the x / t prolongation of the coarse correction z (the
-// expressions of k_prolong_x / k_prolong_t); TAIL 1 also writes the residual
-// b - J y_S (one more warm-up row and halo lane: it needs y_S at the neighbours).
+// expressions of k_prolong_x / k_prolong_t); TAIL 2 / 3 also form the residual
+// b - J y_S (one more warm-up row and halo lane: it needs y_S at the neighbours) and
+// write its t / x restriction, with the expressions of k_restrict_t / k_restrict_x
+// (causal interpolation): t pairs the levels 2J, 2J+1 of one segment (segments start at
+// even levels and have even lengths), x takes the neighbour columns' residuals from the
+// adjacent lanes (one more halo lane).
 constexpr int kStencilWave = 64;
 constexpr int kStencilWavesPerBlock = 4;
 
 template <typename T, int TR, int S, int HEAD, int TAIL>
 __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stencil_fused(
     StencilViewT<T> V, const T* __restrict__ u, const T* __restrict__ b, T* __restrict__ out,
-    int zero_in, const T* __restrict__ z, int64_t Pz, T* __restrict__ rout, int xw, int seg,
-    int nwaves) {
-    constexpr int H = S + (TAIL ? 1 : 0);             // halo lanes per side, warm-up rows
+    int zero_in, const T* __restrict__ z, int64_t Pz, T* __restrict__ bc, int64_t Pbc, int Nc,
+    int xw, int seg, int nwaves) {
+    // halo lanes per side, warm-up rows
+    constexpr int H = S + (TAIL ? 1 : 0) + (TAIL == 3 ? 1 : 0);
     const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * kStencilWavesPerBlock +
                                                     (int)(threadIdx.x >> 6));
     if (wave >= nwaves) return;
@@ -214,6 +219,7 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
     T prev[S + 1];
 #pragma unroll
     for (int k = 0; k <= S; ++k) prev[k] = T(0);
+    T r_pair = T(0);   // TAIL 2: the residual of the level met first in a pair
     // coefficients of the current row class: J: (row n: dt = -1 at dx = -1, 0, 1, then
     // dt = 0); J^T: (row n at columns i-1, i, i+1, then row n+1 at i-1, i, i+1)
     T c[6] = {T(0), T(0), T(0), T(0), T(0), T(0)}, wd = T(0);
@@ -323,7 +329,43 @@ __global__ __launch_bounds__(kStencilWave * kStencilWavesPerBlock) void k_stenci
                 acc = fmaT(c[4], cur, acc);
                 acc = fmaT(c[5], xp, acc);
             }
-            if (useful && n >= n0 && n < n1) rout[o] = bb - acc;
+            const T res = bb - acc;
+            const bool out_row = n >= n0 && n < n1;   // wave-uniform
+            if (TAIL == 2) {
+                if (out_row) {
+                    // pairs (2J, 2J+1) -> J: 1/2 (r_2J + r_2J+1 [2J+1 <= Nt]); the
+                    // transposed stream meets 2J+1 first
+                    T* dst = bc + (int64_t)(n >> 1) * Pbc + i;
+                    const bool odd = (n & 1) != 0;
+                    if (!TR) {
+                        if (odd) {
+                            if (useful) *dst = T(0.5) * (r_pair + res);
+                        } else if (n == V.Nt) {
+                            if (useful) *dst = T(0.5) * res;
+                        } else {
+                            r_pair = res;
+                        }
+                    } else {
+                        if (odd) {
+                            r_pair = res;
+                        } else if (n == V.Nt) {
+                            if (useful) *dst = T(0.5) * res;
+                        } else {
+                            if (useful) *dst = T(0.5) * (res + r_pair);
+                        }
+                    }
+                }
+            } else if (TAIL == 3) {
+                // coarse node I = i/2 for even i: r_2I + 1/2 (r_2I-1 [I >= 1] + r_2I+1 [I < Nc])
+                const T rl = shfl_up1(res), rr = shfl_dn1(res);
+                if (useful && out_row && (i & 1) == 0) {
+                    const int I = i >> 1;
+                    T side = T(0);
+                    if (I >= 1) side += rl;
+                    if (I < Nc) side += rr;
+                    bc[(int64_t)n * Pbc + I] = fmaT(T(0.5), side, res);
+                }
+            }
         }
         prev[S] = cur;
         if (useful && n >= n0 && n < n1) out[o] = cur;
@@ -360,7 +402,7 @@ __global__ void k_stencil_thomas(StencilView S, double* __restrict__ f) {
 
 template <typename T, int TR, int S, int HEAD, int TAIL>
 void launch_stencil_fused_s(const StencilViewT<T>& V, const StencilPass<T>& p, hipStream_t s) {
-    constexpr int H = S + (TAIL ? 1 : 0);
+    constexpr int H = S + (TAIL ? 1 : 0) + (TAIL == 3 ? 1 : 0);
     const int U = kStencilWave - 2 * H;
     const int xw = (V.N + 1 + U - 1) / U;
     const int64_t rows = V.Nt + 1;
@@ -377,12 +419,13 @@ void launch_stencil_fused_s(const StencilViewT<T>& V, const StencilPass<T>& p, h
     const int blocks = (nw + kStencilWavesPerBlock - 1) / kStencilWavesPerBlock;
     hipLaunchKernelGGL((k_stencil_fused<T, TR, S, HEAD, TAIL>), dim3(blocks),
                        dim3(kStencilWave * kStencilWavesPerBlock), 0, s, V, p.u, p.b, p.out,
-                       (int)p.zero_in, p.z, p.Pz, p.r, xw, (int)seg, nw);
+                       (int)p.zero_in, p.z, p.Pz, p.bc, p.Pbc, p.Nc, xw, (int)seg, nw);
 }
 
 template <typename T, int TR, int S>
 void launch_stencil_fused_ht(const StencilViewT<T>& V, const StencilPass<T>& p, hipStream_t s) {
-    if (p.r) launch_stencil_fused_s<T, TR, S, 0, 1>(V, p, s);
+    if (p.restrict_dir == 't') launch_stencil_fused_s<T, TR, S, 0, 2>(V, p, s);
+    else if (p.restrict_dir == 'x') launch_stencil_fused_s<T, TR, S, 0, 3>(V, p, s);
     else if (p.head == 'x') launch_stencil_fused_s<T, TR, S, 1, 0>(V, p, s);
     else if (p.head == 't') launch_stencil_fused_s<T, TR, S, 2, 0>(V, p, s);
     else launch_stencil_fused_s<T, TR, S, 0, 0>(V, p, s);
@@ -402,7 +445,8 @@ void launch_stencil_fused_t(const StencilViewT<T>& V, const StencilPass<T>& p, h
 
 template <typename T>
 int launch_stencil_fused(const StencilViewT<T>& V, const StencilPass<T>& p, hipStream_t s) {
-    if (p.sweeps < 1 || p.sweeps > kStencilMaxFused || (p.r && p.head)) return -1;
+    if (p.sweeps < 1 || p.sweeps > kStencilMaxFused || (p.restrict_dir && p.head)) return -1;
+    if (p.restrict_dir && p.restrict_dir != 'x' && p.restrict_dir != 't') return -1;
     if (p.trans) launch_stencil_fused_t<T, 1>(V, p, s);
     else launch_stencil_fused_t<T, 0>(V, p, s);
     return 0;

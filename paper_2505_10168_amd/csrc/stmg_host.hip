@@ -74,12 +74,10 @@ struct Level {
     double* u = nullptr;
     double* b = nullptr;
     double* t = nullptr;
-    double* w = nullptr;     // fine level, pipelined solves: keeps the previous iterate;
-                             // Galerkin levels: residual of the fused pre-smoothing pass
+    double* w = nullptr;     // fine level, pipelined solves: keeps the previous iterate
     float* u32 = nullptr;
     float* b32 = nullptr;
     float* t32 = nullptr;
-    float* w32 = nullptr;    // Galerkin levels, FP32 inner cycles: residual of the fused pre-smoothing pass
     int64_t elems() const { return (int64_t)(Nt + 1) * P; }
     int64_t dofs() const { return dofs_of(N, Nt); }
 };
@@ -133,11 +131,6 @@ template <> double*& Tt<double>(Level& l) { return l.t; }
 template <> float*& U<float>(Level& l) { return l.u32; }
 template <> float*& B<float>(Level& l) { return l.b32; }
 template <> float*& Tt<float>(Level& l) { return l.t32; }
-// Galerkin levels: residual of the fused pre-smoothing pass
-template <typename T> T* Wr(Level& l) {
-    if constexpr (std::is_same<T, double>::value) return l.w;
-    else return l.w32;
-}
 
 template <typename T>
 LevelView<T> view(const Level& l, double omega);
@@ -284,7 +277,7 @@ size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest, bool 
     if (galerkin && !fine) {
         const size_t rows = (size_t)std::min(Nt + 1, kStencilRowsBound) * P;
         b += (10 + (coarsest ? 4 : 0)) * rows * 8 + (size_t)(Nt + 1 + kStencilRowsBound) * 4;
-        b += precision == STMG_MIXED ? 10 * rows * 4 + (size_t)E * 4 : (size_t)E * 8;
+        if (precision == STMG_MIXED) b += 10 * rows * 4;   // FP32 copy of the stencil
     }
     if (galerkin && !bilinear && coarsest && !fine && N + 1 <= kStencilDenseMaxNodes)
         b += (size_t)kStencilRowsBound * (N + 1) * (N + 1) * 8;   // block inverses
@@ -592,9 +585,6 @@ int build(stmg_ctx* h, const double* d_q) {
                 if (l.N + 1 <= kStencilDenseMaxNodes)
                     CHK(h->alloc(&l.sinv, (int64_t)l.R * (l.N + 1) * (l.N + 1)));
             }
-            // residual of the fused pre-smoothing pass
-            if (h->o.precision == STMG_MIXED) CHK(h->alloc(&l.w32, l.elems()));
-            else CHK(h->alloc(&l.w, l.elems()));
             CHK(h->alloc(&l.srow, (int64_t)l.Nt + 1));
             CHK(h->alloc(&l.srep, (int64_t)l.R));
             HIPCHK(hipMemcpyAsync(l.srow, l.hrow.data(), l.hrow.size() * sizeof(int),
@@ -683,7 +673,8 @@ bool stencil_streams(const stmg_ctx* h) { return h->o.fused && h->o.interp == ST
 // which the caller checks).
 template <typename T>
 int stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu, char head = 0,
-                   const T* z = nullptr, int64_t Pz = 0, T* r = nullptr) {
+                   const T* z = nullptr, int64_t Pz = 0, char rdir = 0, T* bc = nullptr,
+                   int64_t Pbc = 0, int Nc = 0) {
     const StencilViewT<T> S = sview<T>(lv);
     T*& u = U<T>(lv);
     T* b = B<T>(lv);
@@ -695,7 +686,9 @@ int stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu, c
         const int passes = (left + kStencilMaxFused - 1) / kStencilMaxFused;
         const int k = stream ? (left + passes - 1) / passes : 1;
         if (stream) {
-            StencilPass<T> p{trans, k, u, b, t, zero, head, z, Pz, left == k ? r : nullptr};
+            const bool lastp = left == k;
+            StencilPass<T> p{trans, k, u, b, t, zero, head, z, Pz, lastp ? rdir : (char)0,
+                             bc, Pbc, Nc};
             if (launch_stencil_fused<T>(S, p, h->s) != 0) return fail(STMG_EINVAL, "bad stencil pass");
             head = 0;
         } else {
@@ -716,9 +709,9 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
     const auto V = view<T>(lv, h->o.omega);
     if (lv.sten) {
         if (stencil_streams(h) && nu > 0) {
-            // the last smoothing pass writes the residual into the third vector
-            CHK(stencil_smooth<T>(h, lv, trans, zero_start, nu, 0, nullptr, 0, Wr<T>(lv)));
-            launch_restrict<T>(lv.dir, V, Wr<T>(lv), B<T>(cl), cl.P, h->s, h->o.interp);
+            // the last smoothing pass restricts its residual into the coarse b
+            CHK(stencil_smooth<T>(h, lv, trans, zero_start, nu, 0, nullptr, 0, lv.dir, B<T>(cl),
+                                  cl.P, cl.N));
         } else {
             CHK(stencil_smooth<T>(h, lv, trans, zero_start, nu));
             launch_apply_stencil<T>(sview<T>(lv), trans, APPLY_RESIDUAL, U<T>(lv), B<T>(lv),

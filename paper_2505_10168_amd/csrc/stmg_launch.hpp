@@ -121,7 +121,7 @@ void launch_apply_stencil(const StencilViewT<T>& S, int trans, int mode, const T
                           T* y, bool zero_in, hipStream_t s);
 // `sweeps` (1..kStencilMaxFused) damped Jacobi steps in one streaming pass, u -> out
 // (distinct buffers); the same values as the prolongation, `sweeps` launches of
-// launch_apply_stencil and the residual launched one after the other
+// launch_apply_stencil, the residual and the restriction launched one after the other
 constexpr int kStencilMaxFused = 6;
 template <typename T>
 struct StencilPass {
@@ -134,9 +134,13 @@ struct StencilPass {
     char head;          // 0, 'x' or 't': add P z (coarse pitch Pz) to u first
     const T* z;
     int64_t Pz;
-    T* r;               // non-null: also write b - J out here (not with a head)
+    char restrict_dir;  // 'x' / 't': also write R (b - J out) (causal interpolation) to
+    T* bc;              // this coarse vector (Nc elements, pitch Pbc); not with a head
+    int64_t Pbc;
+    int Nc;
 };
-// -1 (nothing launched) for sweeps outside 1..kStencilMaxFused or a head with a residual
+// -1 (nothing launched) for sweeps outside 1..kStencilMaxFused, another restriction
+// direction or a head with a restriction
 template <typename T>
 int launch_stencil_fused(const StencilViewT<T>& V, const StencilPass<T>& p, hipStream_t s);
 // exact solve of a stencil level with couplings to the next time level (bilinear
