@@ -6,13 +6,17 @@
 // (n, i); coefficients that would reach outside the grid are zero.  The operators do
 // not depend on the time level except near the first and last levels, so a level
 // stores only its R distinct stencil rows (R is 3 or 4 in practice; array 9 holds the
-// Jacobi scale omega / J_ii of each) and a map from
-// time level to stored row; all time levels of a row class are built by the same
-// arithmetic from the same inputs and are therefore exactly equal.  These levels are
-// smoothed by streaming passes (k_stencil_fused) or one step per launch, and applied
-// one thread per DOF; with the causal transfers no row couples to a later time level,
-// so the coarsest level is solved by time stepping with one tridiagonal solve per time
-// level.
+// Jacobi scale omega / J_ii of each) and a map from time level to stored row; all time
+// levels of a row class are built by the same arithmetic from the same inputs and are
+// therefore exactly equal.  These levels are smoothed by streaming passes
+// (k_stencil_fused, which also forms the residual and its restriction) or one step per
+// launch, and applied one thread per DOF.  With the causal transfers no row couples to a
+// later time level, so the coarsest level is solved by time stepping, one tridiagonal
+// block per time level (k_stencil_coarsest_dense with the blocks' inverses up to 64
+// nodes, else k_stencil_coarsest with Thomas factors); with bilinear transfers it is
+// factored by a band LU (k_lu_*).  The kernels are instantiated for FP64 vectors and, for
+// the FP32 cycles of mixed precision, for FP32 vectors with an FP32 copy of the stencil;
+// the coarsest solves keep FP64 arithmetic and factors for both.
 #include <hip/hip_runtime.h>
 
 #include "stmg_launch.hpp"
