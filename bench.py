@@ -6,7 +6,8 @@ operators), forward STMG solve to the relative-residual tolerance, adjoint STMG 
 objective and gradient.  Reported value: DOF-updates/s = (sum over both solves of
 cycles * sum_{l < N_l} 2 nu n_l) / wall time of the K timed steps.
 
-Prints ONE JSON line (rank 0).  --gpus above 1 is rejected: this build runs on one GPU.
+Prints ONE JSON line (rank 0).  --gpus above 1 is rejected: the path runs on one GPU (the
+library has no multi-GPU form).
 """
 from __future__ import annotations
 
@@ -285,8 +286,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs the STMG path on one GPU only; "
-              "--gpus above 1 is not supported", file=sys.stderr)
+        print("bench.py: the STMG path runs on one GPU only (the library has no multi-GPU "
+              "form); --gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
 
     if args.serving:

@@ -43,7 +43,7 @@ extern "C" {
 #define STMG_EINVAL          -1   /* invalid argument                               */
 #define STMG_ENOMEM          -2   /* device allocation failed                       */
 #define STMG_EHIP            -3   /* HIP runtime error                              */
-#define STMG_EUNSUPPORTED    -4   /* valid request this build does not implement    */
+#define STMG_EUNSUPPORTED    -4   /* valid request the library does not implement   */
 
 /* reassembly methods of the coarse levels (Section 5.1) */
 #define STMG_REASSEMBLE_R     0   /* average thermal resistivity 1/k (default)     */
