@@ -248,3 +248,30 @@ def test_boxfilt_8192x65536_fused_smoother_sampled(cuda):
         e = rel(got[lo:], ref[lo:])
         print(f"rows {r0}..{r1}: rel err {e:.2e}", flush=True)
         assert e <= 1e-13
+
+
+FOOTPRINT_OPTS = [
+    ("R", {}), ("R_mixed", {"precision": 1}), ("R_reference", {"fused": 0}),
+    ("B", {"interp": 1}), ("P", {"reassembly": 3}), ("P_mixed", {"reassembly": 3, "precision": 1}),
+    ("BP", {"reassembly": 3, "interp": 1}), ("P_deff_simp", {"reassembly": 3, "deff_mode": 1}),
+    ("P_wide_coarsest", {"reassembly": 3, "max_levels": 3}),
+]
+
+
+@pytest.mark.parametrize("opts", [o for _, o in FOOTPRINT_OPTS], ids=[n for n, _ in FOOTPRINT_OPTS])
+def test_footprint_bounds_the_allocation(opts, cuda):
+    """stmg_footprint, computed before anything is allocated (the serving admission uses
+    it), bounds the device memory a handle of the same problem and options holds."""
+    import ctypes as C
+
+    from paper_2505_10168_amd import binding as B
+    rho = I.block_density(256, 16, seed=7)
+    prob = B.Problem(len(rho), 600, k_ins=1e-3)
+    s = B.Solver(prob, to_dev(rho, cuda), nu=2, **opts)
+    used = s.info()["device_bytes"]
+    n = C.c_size_t()
+    o = B.make_options(nu=2, **opts)
+    assert B.lib.stmg_footprint(C.byref(prob.c_struct()), C.byref(o), C.byref(n)) == 0
+    print(opts, used, n.value)
+    assert used <= n.value
+    s.close()
