@@ -44,6 +44,9 @@ constexpr int kWavesPerBlock = 4;
 #ifndef STMG_TARGET_WAVES_ALU
 #define STMG_TARGET_WAVES_ALU 3072
 #endif
+#ifndef STMG_TARGET_WAVES_ALU_COARSE
+#define STMG_TARGET_WAVES_ALU_COARSE 2048
+#endif
 #ifndef STMG_MIN_SEGMENT
 #define STMG_MIN_SEGMENT 2
 #endif
@@ -455,7 +458,7 @@ struct Geometry {
 };
 
 template <typename T>
-Geometry geometry(int N, int Nt, int sweeps) {
+Geometry geometry(int N, int Nt, int sweeps, bool fine) {
     constexpr int K = Lanes<T>::K;
     Geometry G;
     // Halo lanes: ceil((S+2)/K), rounded up so that the useful strip of every wave is
@@ -469,8 +472,11 @@ Geometry geometry(int N, int Nt, int sweeps) {
     const int64_t rows = Nt + 1;
     // Enough waves to keep every SIMD busy several times over.  Passes of four or
     // more sweeps are bound by their arithmetic, not by memory latency: they get fewer,
-    // longer time segments, which cuts the recomputed warm-up rows.
-    const int64_t target = sweeps >= 4 ? STMG_TARGET_WAVES_ALU : STMG_TARGET_WAVES;
+    // longer time segments, which cuts the recomputed warm-up rows; fewer still on the
+    // coarse levels, whose passes share the GPU with the other levels' latency-bound
+    // launches (measured: 2048 waves there against 3072 on the finest level).
+    const int64_t target = sweeps < 4 ? STMG_TARGET_WAVES
+                           : (fine ? STMG_TARGET_WAVES_ALU : STMG_TARGET_WAVES_ALU_COARSE);
     int64_t seg = (rows * G.xw + target - 1) / target;
     const int64_t min_seg = STMG_MIN_SEGMENT;
     if (seg < min_seg) seg = min_seg;
@@ -551,14 +557,14 @@ int fused_max_sweeps() { return kMaxFused; }
 
 int fused_parts(int N, int Nt, int sweeps) {
     // the FP32 geometry (wider lanes) never needs more waves than the FP64 one
-    return geometry<double>(N, Nt, sweeps).nwaves;
+    return geometry<double>(N, Nt, sweeps, true).nwaves;
 }
 
 template <typename T>
 int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T* b, T* out,
                  hipStream_t s) {
     if (fp.sweeps < 0 || fp.sweeps > kMaxFused) return -1;
-    Geometry G = geometry<T>(L.N, L.Nt, fp.sweeps);
+    Geometry G = geometry<T>(L.N, L.Nt, fp.sweeps, fp.fine != 0);
     FusedArgs<T> a;
     a.u = u;
     a.b = b;
