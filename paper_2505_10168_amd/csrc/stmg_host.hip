@@ -668,9 +668,9 @@ bool stencil_streams(const stmg_ctx* h) { return h->o.fused && h->o.interp == ST
 // nu damped Jacobi steps on a Galerkin level (stored stencil), in place: streaming
 // passes of up to kStencilMaxFused steps with the fused kernels and causal
 // interpolation (the stencil then couples to earlier time levels only), else one
-// launch per step.  head ('x' / 't'): the first pass adds the prolongation of z (pitch Pz) first;
-// r: the last pass also writes the residual there (both only with the fused kernels,
-// which the caller checks).
+// launch per step.  head ('x' / 't'): the first pass adds the prolongation of z (pitch
+// Pz) first; rdir ('x' / 't'): the last pass also restricts its residual into bc (pitch
+// Pbc, Nc coarse elements).  Both only with the fused kernels, which the caller checks.
 template <typename T>
 int stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu, char head = 0,
                    const T* z = nullptr, int64_t Pz = 0, char rdir = 0, T* bc = nullptr,
