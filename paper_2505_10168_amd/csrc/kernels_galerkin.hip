@@ -196,6 +196,9 @@ void launch_apply_stencil(const StencilViewT<T>& S, int trans, int mode, const T
 // (causal interpolation): t pairs the levels 2J, 2J+1 of one segment (segments start at
 // even levels and have even lengths), x takes the neighbour columns' residuals from the
 // adjacent lanes (one more halo lane).
+#ifndef STMG_STENCIL_TARGET_WAVES_ALU
+#define STMG_STENCIL_TARGET_WAVES_ALU 3072
+#endif
 constexpr int kStencilWave = 64;
 constexpr int kStencilWavesPerBlock = 4;
 
@@ -414,7 +417,7 @@ void launch_stencil_fused_s(const StencilViewT<T>& V, const StencilPass<T>& p, h
     // many segments even though each recomputes H warm-up levels (the policy of the
     // rediscretised fused passes: fewer, longer segments when S >= 4 makes the pass
     // arithmetic-bound on large levels).
-    const int64_t target = S >= 4 ? 3072 : 16384;
+    const int64_t target = S >= 4 ? STMG_STENCIL_TARGET_WAVES_ALU : 16384;
     int64_t seg = (rows * xw + target - 1) / target;
     if (seg < 2) seg = 2;
     if (seg > 1024) seg = 1024;
