@@ -23,6 +23,8 @@
 // gives bit-identical results to a V-cycle built from those.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "stmg_launch.hpp"
 
 namespace stmg {
@@ -106,29 +108,32 @@ __device__ __forceinline__ ColCoef<T> col_coef(const LevelView<T>& V, int i) {
 // uncoupled row forms its differences as fma(0, y, x) = x.  Each rounded operation
 // has the operands k_apply gives it.  Rows are visited from k = M-1 down to 0, so the
 // coupled row k-1 is still at its old value when read.  Rows beyond Nt produce values
-// that are never stored.
-template <typename T, int TR, bool JAC>
+// that are never stored.  MM = o.M, the rows per thread of the level (uniform), as a
+// constant: the row loops then run without a test per row.
+template <int TR, int MM>
+__device__ __forceinline__ int row_m(const Owner& o, int k) {
+    return TR ? o.n0 + MM - 1 - k : o.n0 + k;
+}
+template <typename T, int TR, bool JAC, int MM>
 __device__ __forceinline__ void owned_step(const LevelView<T>& V, const ColCoef<T>& c,
                                            const Owner& o, const T* u, T (&x)[kTailMaxRows],
                                            const T (&bb)[kTailMaxRows]) {
-    const int N = V.N, Nt = V.Nt, W = N + 1, i = o.i, M = o.M;
+    const int N = V.N, Nt = V.Nt, W = N + 1, i = o.i;
     const int im = i > 0 ? i - 1 : 0, ip = i < N ? i + 1 : N;
-    T XM[kTailMaxRows], XP[kTailMaxRows];
+    T XM[MM], XP[MM];
 #pragma unroll
-    for (int k = 0; k < kTailMaxRows; ++k) {
-        if (k < M) {
-            const int n = min(row_of<TR>(o, k), Nt);
-            XM[k] = u[n * W + im];
-            XP[k] = u[n * W + ip];
-        }
+    for (int k = 0; k < MM; ++k) {
+        const int n = min(row_m<TR, MM>(o, k), Nt);
+        XM[k] = u[n * W + im];
+        XP[k] = u[n * W + ip];
     }
-    const int e = min(max(TR ? o.n0 + M : o.n0 - 1, 0), Nt);   // coupled row outside the block
+    const int e = min(max(TR ? o.n0 + MM : o.n0 - 1, 0), Nt);   // coupled row outside the block
     const T EM = u[e * W + im], E0 = u[e * W + i], EP = u[e * W + ip];
 #pragma unroll
-    for (int kk = 0; kk < kTailMaxRows; ++kk) {
-        const int k = kTailMaxRows - 1 - kk;
-        if (k < M) {
-            const int n = row_of<TR>(o, k);
+    for (int kk = 0; kk < MM; ++kk) {
+        const int k = MM - 1 - kk;
+        {
+            const int n = row_m<TR, MM>(o, k);
             const T negc = (TR ? (n < Nt) : (n >= 2)) ? T(-1) : T(0);
             const T cm = k == 0 ? EM : XM[k > 0 ? k - 1 : 0];
             const T c0 = k == 0 ? E0 : x[k > 0 ? k - 1 : 0];
@@ -148,21 +153,46 @@ __device__ __forceinline__ void owned_step(const LevelView<T>& V, const ColCoef<
     }
 }
 
+// Calls f(std::integral_constant<int, M>) for the uniform rows per thread M, 1 <= M <= MX.
+template <int MX, typename F>
+__device__ __forceinline__ void with_rows(int M, F&& f) {
+    if constexpr (MX <= 1) {
+        f(std::integral_constant<int, 1>{});
+    } else {
+        if (M == MX) f(std::integral_constant<int, MX>{});
+        else with_rows<MX - 1>(M, f);
+    }
+}
+
+// One Jacobi step or the residual, with the level's rows per thread as a constant.
+template <typename T, int TR, bool JAC>
+__device__ __forceinline__ void owned_step_any(const LevelView<T>& V, const ColCoef<T>& c,
+                                               const Owner& o, const T* u,
+                                               T (&x)[kTailMaxRows],
+                                               const T (&bb)[kTailMaxRows]) {
+    with_rows<kTailMaxRows>(o.M, [&](auto mm) {
+        owned_step<T, TR, JAC, decltype(mm)::value>(V, c, o, u, x, bb);
+    });
+}
+
 // nu damped Jacobi steps; x holds the owned values before and after, u (LDS) too.
 template <typename T, int TR>
 __device__ void tail_smooth(const LevelView<T>& V, const ColCoef<T>& c, const Owner& o, T* u,
                             T (&x)[kTailMaxRows], const T (&bb)[kTailMaxRows], int nu) {
     const int W = V.N + 1;
-    for (int s = 0; s < nu; ++s) {
-        owned_step<T, TR, true>(V, c, o, u, x, bb);
-        __syncthreads();
+    with_rows<kTailMaxRows>(o.M, [&](auto mm) {
+        constexpr int MM = decltype(mm)::value;
+        for (int s = 0; s < nu; ++s) {
+            owned_step<T, TR, true, MM>(V, c, o, u, x, bb);
+            __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kTailMaxRows; ++k) {
-            const int n = row_of<TR>(o, k);
-            if (k < o.M && o.act && n <= V.Nt) u[n * W + o.i] = x[k];
+            for (int k = 0; k < MM; ++k) {
+                const int n = row_m<TR, MM>(o, k);
+                if (o.act && n <= V.Nt) u[n * W + o.i] = x[k];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-    }
+    });
 }
 
 // Owned rows of u and b from LDS into registers (zero where not owned).
@@ -192,7 +222,7 @@ __device__ void tail_down(const LevelView<T>& F, T* u, const T* b, int dir, T* u
     for (int k = 0; k < kTailMaxRows; ++k) x[k] = T(0);
     tail_smooth<T, TR>(F, c, o, u, x, bb, nu);
     T (&r)[kTailMaxRows] = x;
-    owned_step<T, TR, false>(F, c, o, u, r, bb);
+    owned_step_any<T, TR, false>(F, c, o, u, r, bb);
     if (dir == 't') {
         // pairs (2J, 2J+1) of one owner: bc_J = 1/2 (r_2J + r_2J+1 [2J+1 <= Nt]); time
         // level 2J is owned row k = 2m (J) or 2m+1 (J^T), 2J+1 the row next to it
