@@ -280,6 +280,30 @@ def test_alg4_guard_forces_t():
     assert h.path == "xtt"
 
 
+def tie_level(n_t):
+    """4 elements on [0, 1] over t in [0, 1]: h = 1/4, tau = 1/n_t.  D_e = k_e / c_e is
+    1/4, 4, 4, 1/4 (k = 1/4, 2, 2, 1/4 with c = 1, 1/2, 1/2, 1), so D_eff = sqrt(1/4 * 4)
+    = 1 and lambda_eff = tau / h^2 = 16 / n_t, exact in binary for n_t = 64."""
+    return O.Level(4, n_t, 0.25, 1.0 / n_t, np.array([0.25, 2.0, 2.0, 0.25]),
+                   np.array([1.0, 0.5, 0.5, 1.0]))
+
+
+def test_alg3_tie_takes_x():
+    """Algorithm 3 t-coarsens only when lambda_eff is strictly below lambda_crit: at
+    lambda_eff = lambda_crit = 1/4 exactly the step is x; just below it (n_t = 66,
+    lambda_eff = 16/66) the step is t, and the same holds for the Section 7.2 D_eff
+    of the SIMP extrema (material with D(0) = 1/4, D(1) = 4)."""
+    lam = O.lambda_eff(tie_level(64))
+    assert lam == 0.25
+    assert O.build_hierarchy(tie_level(64), O.Options(max_levels=2)).path == "x"
+    assert O.build_hierarchy(tie_level(66), O.Options(max_levels=2)).path == "t"
+    mat = O.Material(0.25, 4.0, 1.0, 1.0)
+    assert O.d_eff_simp(mat) == 1.0
+    simp = O.Options(max_levels=2, deff_mode="simp", material=mat)
+    assert O.build_hierarchy(tie_level(64), simp).path == "x"
+    assert O.build_hierarchy(tie_level(66), simp).path == "t"
+
+
 def test_resistivity_average_is_harmonic_mean():
     """Section 5.1: averaging 1/k gives k = 2 k_a k_b / (k_a + k_b); c is averaged."""
     rng = np.random.default_rng(1)
