@@ -196,6 +196,24 @@ int stmg_objective(stmg_t h, const double* d_u, double* theta);
  * d_grad: N_el FP64 (device). */
 int stmg_gradient(stmg_t h, const double* d_u, const double* d_lambda, double* d_grad);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the gradient of stmg_gradient
+ * without a handle and without any allocation.  The problem p supplies N_el, N_t, L,
+ * t_T and the SIMP maps; d_rho (N_el), d_u and d_lambda (compact [(N_t+1)][(N_el+1)])
+ * are device inputs, d_grad (N_el, device) the output, bit-identical to stmg_gradient
+ * of a handle built from the same p and d_rho.  Work runs on `stream` (a hipStream_t
+ * of the current device, NULL = default stream); the call returns when it is done.
+ * Temporaries live in a fixed device array of 8 Mi doubles (64 MiB) that each device
+ * holds from the library's first use until the process ends: N_el * (ceil(N_t/128)
+ * capped to 1024, + 2) doubles must fit, else EINVAL.  The array is shared by every
+ * call on a device, so calls that overlap on one device (several host threads or
+ * streams) race; serialise them.  Nothing needs to start at zero (every temporary is
+ * written before it is read).  The first call on a device resolves the array's
+ * address (hipGetSymbolAddress); no call allocates, frees or calls an allocating
+ * library routine.  Errors: EINVAL (null pointer, bad size, too large), EHIP. */
+int stmg_gradient_noalloc(const stmg_problem* p, const double* d_rho, const double* d_u,
+                          const double* d_lambda, double* d_grad, void* stream);
+
 /* One design update for the optimisation problem of Section 7.1: minimise Theta
  * subject to 0 <= rho_e <= 1 and the volume bound mean(rho) <= volume (the paper's
  * bound is volume = 1/2).  The paper moves the design with MMA, which it only cites;

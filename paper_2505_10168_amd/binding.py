@@ -77,6 +77,7 @@ def _load():
         "stmg_solve_adjoint": (I, [VP, VP, VP, VP, P(stmg_stats)]),
         "stmg_objective": (I, [VP, VP, P(D)]),
         "stmg_gradient": (I, [VP, VP, VP, VP]),
+        "stmg_gradient_noalloc": (I, [P(stmg_problem), VP, VP, VP, VP, VP]),
         "stmg_oc_update": (I, [VP, VP, VP, D, D, D, D, VP]),
         "stmg_get_info": (I, [VP, P(stmg_info)]),
         "stmg_destroy": (I, [VP]),
@@ -102,7 +103,7 @@ lib = _load()
 EXPORTED = [
     "stmg_default_options", "stmg_footprint", "stmg_create", "stmg_set_design",
     "stmg_solve_forward", "stmg_solve_adjoint", "stmg_objective", "stmg_gradient",
-    "stmg_oc_update",
+    "stmg_gradient_noalloc", "stmg_oc_update",
     "stmg_get_info", "stmg_destroy", "stmg_level_apply", "stmg_level_smooth",
     "stmg_level_presmooth_restrict", "stmg_level_prolong_postsmooth",
     "stmg_level_coarsest_solve", "stmg_vcycle", "stmg_status_string", "stmg_last_error",
@@ -183,6 +184,12 @@ def stmg_objective(h: int, u) -> float:
 
 def stmg_gradient(h: int, u, lam, grad) -> int:
     return _check(lib.stmg_gradient(h, _ptr(u), _ptr(lam), _ptr(grad)), "stmg_gradient")
+
+
+def stmg_gradient_noalloc(problem: stmg_problem, rho, u, lam, grad, stream=None) -> int:
+    return _check(lib.stmg_gradient_noalloc(C.byref(problem), _ptr(rho), _ptr(u), _ptr(lam),
+                                            _ptr(grad), _stream_ptr(stream)),
+                  "stmg_gradient_noalloc")
 
 
 def stmg_oc_update(h: int, rho, grad, volume: float, move: float, eta: float, rho_min: float,

@@ -12,6 +12,7 @@
 #include <utility>
 #include <array>
 #include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "stmg.h"
@@ -1241,6 +1242,41 @@ int reassemble(stmg_ctx* h, bool check_path) {
     return 0;
 }
 
+// ------------------------------------------------------------------------------------
+// Device scratch of the allocation-free gradient (stmg_gradient_noalloc)
+// ------------------------------------------------------------------------------------
+
+// Every device the library runs on holds one copy of this array from the load of the
+// code object until the process ends.  In host code its name is only a stand-in for the
+// symbol: the device address of each device's copy comes from hipGetSymbolAddress, once
+// per device, and only that address is handed to kernels.
+constexpr size_t kScratchDoubles = size_t(8) << 20;   // 64 MiB
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of the current device's scratch, resolved on the first call per device.
+int scratch_address(double** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return fail(STMG_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(STMG_EHIP, std::string("hipGetSymbolAddress of the scratch array: ") +
+                                       hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
 }  // namespace
 
 // ======================================================================================
@@ -1374,6 +1410,38 @@ int stmg_gradient(stmg_t h, const double* d_u, const double* d_lambda, double* d
     launch_gradient_final(h->parts, f.N, chunks, d_grad, h->s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+int stmg_gradient_noalloc(const stmg_problem* p, const double* d_rho, const double* d_u,
+                          const double* d_lambda, double* d_grad, void* stream) {
+    if (!p || !d_rho || !d_u || !d_lambda || !d_grad) return fail(STMG_EINVAL, "null argument");
+    if (p->n_el < 1 || p->n_t < 1 || (int64_t)p->n_el > (1 << 24) || (int64_t)p->n_t > (1 << 26))
+        return fail(STMG_EINVAL, "n_el and n_t must be in [1, 2^24] and [1, 2^26]");
+    if (!(p->length > 0) || !(p->t_final > 0)) return fail(STMG_EINVAL, "length and t_final must be > 0");
+    const int N = p->n_el, Nt = p->n_t;
+    const int chunks = gradient_chunks(Nt);
+    const size_t need = (size_t)N * (size_t)(chunks + 2);
+    if (need > kScratchDoubles)
+        return fail(STMG_EINVAL, "n_el * (" + std::to_string(chunks) + " time chunks + 2) = " +
+                                     std::to_string(need) + " doubles exceeds the " +
+                                     std::to_string(kScratchDoubles) + "-double scratch");
+    double* sp = nullptr;
+    CHK(scratch_address(&sp));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // scratch: dk/drho (N), dc/drho (N), per-chunk partial sums (chunks N); every entry
+    // is written before it is read, so nothing needs clearing between calls
+    double* kp = sp;
+    double* cpd = sp + N;
+    double* parts = sp + 2 * (size_t)N;
+    launch_simp_derivative(d_rho, N, p->k_ins, p->k_con, p->p_k, kp, s);
+    launch_simp_derivative(d_rho, N, p->c_ins, p->c_con, p->p_c, cpd, s);
+    const double hx = p->length / p->n_el, tau = p->t_final / p->n_t;
+    launch_gradient_partial(d_u, d_lambda, N, Nt, N + 1, N + 1, kp, cpd, hx, tau, parts, s);
+    launch_gradient_final(parts, N, chunks, d_grad, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    g_err.clear();
     return 0;
 }
 
