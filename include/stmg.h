@@ -66,10 +66,17 @@ extern "C" {
 
 #define STMG_MAX_HISTORY   1024   /* longest residual history kept in the stats     */
 
-/* Physical problem.  Materials: k(rho) = k_ins + (k_con - k_ins) rho^p_k and
- * c(rho) = c_ins + (c_con - c_ins) rho^p_c (Section 2.1, eqs. SIMP k / SIMP c).
- * theta_ref normalises the objective (Section 7.1).  q_uniform is the heat source
- * used when no element-wise load is given at creation. */
+/* kind of the per-element field a handle is built from (Section 2: k(x), c(x)) */
+#define STMG_FIELD_DENSITY       0   /* design densities rho_e in [0, 1] through SIMP      */
+#define STMG_FIELD_CONDUCTIVITY  1   /* conductivities k_e > 0 given directly; c_e = c_con */
+
+/* Physical problem.  With field_kind = STMG_FIELD_DENSITY the materials are
+ * k(rho) = k_ins + (k_con - k_ins) rho^p_k and c(rho) = c_ins + (c_con - c_ins) rho^p_c
+ * (Section 2.1, eqs. SIMP k / SIMP c); with STMG_FIELD_CONDUCTIVITY the field is k
+ * itself, the heat capacity is c_con everywhere (so the diffusivity D_e = k_e / c_con
+ * of Section 3.3 is the field over c_con), k_ins and the SIMP exponents are unused, and
+ * gradients are dTheta/dk_e.  theta_ref normalises the objective (Section 7.1).
+ * q_uniform is the heat source used when no element-wise load is given at creation. */
 typedef struct {
     int32_t n_el;          /* elements, >= 1                                        */
     int32_t n_t;           /* backward-Euler steps, >= 1                            */
@@ -80,6 +87,7 @@ typedef struct {
     double  p_k, p_c;      /* SIMP penalties (paper: 3 and 2)                       */
     double  theta_ref;     /* > 0                                                   */
     double  q_uniform;     /* uniform heat source                                   */
+    int32_t field_kind;    /* STMG_FIELD_DENSITY (0) or STMG_FIELD_CONDUCTIVITY (1)  */
 } stmg_problem;
 
 /* Solver options.  stmg_default_options() fills: nu = 2, omega = 0.5,
@@ -111,6 +119,10 @@ typedef struct {
                                     R = P^T / 2.  With B the t transfers run as separate
                                     one-thread-per-DOF kernels beside the fused smoothing
                                     passes, and no single-workgroup tail is used              */
+    int32_t debug_poison;     /* 1: the per-level entry points fill the library's internal
+                                    output vectors (nodes 0..N_el of every time level) with
+                                    NaN before computing them, so an entry a kernel fails to
+                                    write shows in the result; a testing aid, 0 by default  */
 } stmg_options;
 
 typedef struct {
@@ -124,6 +136,9 @@ typedef struct {
     double  fine_kernel_ms;          /* time_kernels: summed time of fine fused passes */
     double  fine_kernel_bytes;       /* their algorithmic bytes                         */
     int64_t fine_kernel_launches;
+    double  setup_ms;                /* wall time of the handle's last hierarchy build or
+                                        re-assembly (stmg_create / stmg_set_field)     */
+    char    path[128];               /* coarsening directions, 'x' / 't' per step       */
     double  history[STMG_MAX_HISTORY + 1];   /* r_0 .. r_cycles                       */
 } stmg_stats;
 
@@ -144,27 +159,37 @@ typedef struct stmg_ctx* stmg_t;
 /* Fill *o with the defaults listed above.  Returns STMG_EINVAL if o is NULL. */
 int stmg_default_options(stmg_options* o);
 
-/* Device bytes a handle for (p, o) will allocate, without allocating.  The figure
- * is exact for the path that field-independent D_eff (deff_mode = 1) yields and an
- * upper bound (every step taken in x, the costlier direction) otherwise. */
-int stmg_footprint(const stmg_problem* p, const stmg_options* o, size_t* bytes);
+/* Device bytes of one request for (p, o), without allocating: what a handle
+ * allocates plus the request's compact FP64 outputs, the solution u and, with
+ * with_adjoint != 0, the adjoint solution and the N_el gradient.  The handle part is
+ * exact for the path that field-independent D_eff (deff_mode = 1) yields and an upper
+ * bound (each level as large as any coarsening path can make it) otherwise. */
+int stmg_footprint(const stmg_problem* p, const stmg_options* o, int with_adjoint,
+                   size_t* bytes);
 
 /* Build the level hierarchy (Algorithms 3/4 with the reassembly method of
  * Section 5.1) and the fine load vector (Section 2.2) on the device.
- *   d_rho : N_el densities in [0, 1] (device).
+ *   d_rho : the N_el values of the field of kind p->field_kind (device): densities in
+ *           [0, 1], or conductivities > 0.  The call starts by copying it, so it may be
+ *           released once the call returns.
  *   d_q   : optional element load, [(N_t+1)][N_el] FP64 (device), row n = q at t_n,
  *           row 0 ignored; NULL = q_uniform everywhere.
  *   stream: hipStream_t used by every call on this handle (NULL = default stream).
  * N_el and N_t need not be powers of two; a direction that cannot halve is
  * replaced by the other one and coarsening stops when neither can.
- * Errors: EINVAL (bad sizes or values), ENOMEM, EHIP. */
+ * Errors: EINVAL (bad sizes or values, a conductivity field that is not positive,
+ * field_kind = CONDUCTIVITY with reassembly D or deff_mode 1, which need densities),
+ * ENOMEM, EHIP. */
 int stmg_create(stmg_t* handle, const stmg_problem* p, const stmg_options* o,
                 const double* d_rho, const double* d_q, void* stream);
 
-/* Re-assemble every level from new densities (Section 7.2: with deff_mode = 1 the
- * path and memory stay fixed across designs).  With deff_mode = 0 the path is
- * recomputed; if it changes, EUNSUPPORTED is returned and the handle is unchanged
- * (create a new handle instead). */
+/* Re-assemble every level from a new field of the handle's field_kind (Section 7.2:
+ * with deff_mode = 1 the path and memory stay fixed across designs).  With
+ * deff_mode = 0 the path is recomputed; if it changes, EUNSUPPORTED is returned and
+ * the handle is unchanged (create a new handle instead).  EINVAL for a conductivity
+ * field that is not positive (the handle then keeps its previous field). */
+int stmg_set_field(stmg_t h, const double* d_field);
+/* The same call under the name of the design loop (densities). */
 int stmg_set_design(stmg_t h, const double* d_rho);
 
 /* Solve J u = b by V-cycles (Algorithm 1) from u0, stopping by the rule of
@@ -191,15 +216,17 @@ int stmg_solve_adjoint(stmg_t h, const double* d_rhs, const double* d_l0,
  * *theta (host). */
 int stmg_objective(stmg_t h, const double* d_u, double* theta);
 
-/* dTheta/drho_e for all elements by the discrete adjoint method (Section 7.2):
- * g_e = -Lambda^T (dJ/drho_e) u with Dirichlet entries of u and Lambda removed.
- * d_grad: N_el FP64 (device). */
+/* dTheta/dfield_e for all elements by the discrete adjoint method (Section 7.2):
+ * g_e = -Lambda^T (dJ/dfield_e) u with Dirichlet entries of u and Lambda removed; the
+ * field is the densities or the conductivities (field_kind).  d_grad: N_el FP64
+ * (device). */
 int stmg_gradient(stmg_t h, const double* d_u, const double* d_lambda, double* d_grad);
 
 /* For callers that cannot allocate device memory (code under stream capture, tight
  * serving loops, harnesses that forbid hipMalloc): the gradient of stmg_gradient
  * without a handle and without any allocation.  The problem p supplies N_el, N_t, L,
- * t_T and the SIMP maps; d_rho (N_el), d_u and d_lambda (compact [(N_t+1)][(N_el+1)])
+ * t_T, the field kind and the SIMP maps; d_rho (the N_el field values), d_u and
+ * d_lambda (compact [(N_t+1)][(N_el+1)])
  * are device inputs, d_grad (N_el, device) the output, bit-identical to stmg_gradient
  * of a handle built from the same p and d_rho.  Work runs on `stream` (a hipStream_t
  * of the current device, NULL = default stream); the call returns when it is done.
@@ -239,7 +266,10 @@ int stmg_destroy(stmg_t h);
 /* ---- per-level components (each level's own grid, compact layout) -------------
  * Entry points for testing one step of Algorithm 1 at a time.  `level` is 0-based
  * (0 = finest); `transpose` selects J^T.  Level vectors have the shape of that
- * level from stmg_get_info. */
+ * level from stmg_get_info and are FP64 at the interface.  On an FP64 handle the FP64
+ * kernels run; on a MIXED handle the FP32 kernels of its inner cycles run on FP32
+ * copies of the inputs (the coarsest solve keeps FP64 arithmetic on FP32 vectors, as
+ * in those cycles) and the results are widened to FP64 (stmg_vcycle needs FP64). */
 
 /* y = J x  (Appendix A form of the BE-FE operator of Section 2.2). */
 int stmg_level_apply(stmg_t h, int level, int transpose, const double* d_x, double* d_y);
@@ -262,8 +292,16 @@ int stmg_level_prolong_postsmooth(stmg_t h, int level, int transpose, int nu,
 int stmg_level_coarsest_solve(stmg_t h, int transpose, const double* d_b, double* d_z);
 
 /* One V-cycle in place on the fine grid; *rel_res (host, optional) receives
- * ||J u - b|| / ||b|| after the cycle. */
+ * ||J u - b|| / ||b|| after the cycle.  FP64 handles only (EUNSUPPORTED otherwise). */
 int stmg_vcycle(stmg_t h, int transpose, const double* d_b, double* d_u, double* rel_res);
+
+/* Launch geometry of one fused streaming pass of `sweeps` Jacobi steps (0..6) on an
+ * n_el x n_t level (fp32: the FP32 kernels; fine: the finest level's kernels): each
+ * wavefront owns a strip of *strip_cols columns and a segment of *seg_rows time levels
+ * (*strips strips along x, *waves wavefronts).  Host-only; a testing aid, so that
+ * sampled checks can be placed across the boundaries between wavefronts. */
+int stmg_pass_geometry(int n_el, int n_t, int sweeps, int fp32, int fine, int* strip_cols,
+                       int* strips, int* seg_rows, int* waves);
 
 const char* stmg_status_string(int status);
 /* Message of the last error on the calling thread (empty if none). */

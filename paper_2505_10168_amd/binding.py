@@ -24,6 +24,7 @@ STMG_EINVAL, STMG_ENOMEM, STMG_EHIP, STMG_EUNSUPPORTED = -1, -2, -3, -4
 STMG_REASSEMBLE_R, STMG_REASSEMBLE_K, STMG_REASSEMBLE_D, STMG_REASSEMBLE_P = 0, 1, 2, 3
 STMG_INTERP_C, STMG_INTERP_B = 0, 1
 STMG_FP64, STMG_MIXED = 0, 1
+STMG_FIELD_DENSITY, STMG_FIELD_CONDUCTIVITY = 0, 1
 STMG_MAX_HISTORY = 1024
 
 
@@ -31,7 +32,8 @@ class stmg_problem(C.Structure):
     _fields_ = [("n_el", C.c_int32), ("n_t", C.c_int32), ("length", C.c_double),
                 ("t_final", C.c_double), ("k_ins", C.c_double), ("k_con", C.c_double),
                 ("c_ins", C.c_double), ("c_con", C.c_double), ("p_k", C.c_double),
-                ("p_c", C.c_double), ("theta_ref", C.c_double), ("q_uniform", C.c_double)]
+                ("p_c", C.c_double), ("theta_ref", C.c_double), ("q_uniform", C.c_double),
+                ("field_kind", C.c_int32)]
 
 
 class stmg_options(C.Structure):
@@ -40,7 +42,7 @@ class stmg_options(C.Structure):
                 ("M_min_elems", C.c_int32), ("reassembly", C.c_int32), ("deff_mode", C.c_int32),
                 ("tol", C.c_double), ("diverge", C.c_double), ("max_cycles", C.c_int32),
                 ("precision", C.c_int32), ("w_diri_override", C.c_double), ("fused", C.c_int32),
-                ("time_kernels", C.c_int32), ("interp", C.c_int32)]
+                ("time_kernels", C.c_int32), ("interp", C.c_int32), ("debug_poison", C.c_int32)]
 
 
 class stmg_stats(C.Structure):
@@ -48,8 +50,8 @@ class stmg_stats(C.Structure):
                 ("rel_residual", C.c_double), ("conv_factor", C.c_double),
                 ("solve_ms", C.c_double), ("dof_updates", C.c_double),
                 ("fine_kernel_ms", C.c_double), ("fine_kernel_bytes", C.c_double),
-                ("fine_kernel_launches", C.c_int64),
-                ("history", C.c_double * (STMG_MAX_HISTORY + 1))]
+                ("fine_kernel_launches", C.c_int64), ("setup_ms", C.c_double),
+                ("path", C.c_char * 128), ("history", C.c_double * (STMG_MAX_HISTORY + 1))]
 
 
 class stmg_info(C.Structure):
@@ -70,8 +72,9 @@ def _load():
     P, I, D, VP = C.POINTER, C.c_int, C.c_double, C.c_void_p
     sig = {
         "stmg_default_options": (I, [P(stmg_options)]),
-        "stmg_footprint": (I, [P(stmg_problem), P(stmg_options), P(C.c_size_t)]),
+        "stmg_footprint": (I, [P(stmg_problem), P(stmg_options), I, P(C.c_size_t)]),
         "stmg_create": (I, [P(VP), P(stmg_problem), P(stmg_options), VP, VP, VP]),
+        "stmg_set_field": (I, [VP, VP]),
         "stmg_set_design": (I, [VP, VP]),
         "stmg_solve_forward": (I, [VP, VP, VP, VP, P(stmg_stats)]),
         "stmg_solve_adjoint": (I, [VP, VP, VP, VP, P(stmg_stats)]),
@@ -87,6 +90,7 @@ def _load():
         "stmg_level_prolong_postsmooth": (I, [VP, I, I, I, VP, VP, VP]),
         "stmg_level_coarsest_solve": (I, [VP, I, VP, VP]),
         "stmg_vcycle": (I, [VP, I, VP, VP, P(D)]),
+        "stmg_pass_geometry": (I, [I, I, I, I, I, P(I), P(I), P(I), P(I)]),
         "stmg_status_string": (C.c_char_p, [I]),
         "stmg_last_error": (C.c_char_p, []),
     }
@@ -101,12 +105,13 @@ lib = _load()
 
 # Every symbol declared in include/stmg.h, for the export test.
 EXPORTED = [
-    "stmg_default_options", "stmg_footprint", "stmg_create", "stmg_set_design",
+    "stmg_default_options", "stmg_footprint", "stmg_create", "stmg_set_field", "stmg_set_design",
     "stmg_solve_forward", "stmg_solve_adjoint", "stmg_objective", "stmg_gradient",
     "stmg_gradient_noalloc", "stmg_oc_update",
     "stmg_get_info", "stmg_destroy", "stmg_level_apply", "stmg_level_smooth",
     "stmg_level_presmooth_restrict", "stmg_level_prolong_postsmooth",
-    "stmg_level_coarsest_solve", "stmg_vcycle", "stmg_status_string", "stmg_last_error",
+    "stmg_level_coarsest_solve", "stmg_vcycle", "stmg_pass_geometry", "stmg_status_string",
+    "stmg_last_error",
 ]
 
 
@@ -147,9 +152,10 @@ def stmg_default_options() -> stmg_options:
     return o
 
 
-def stmg_footprint(problem: stmg_problem, options: stmg_options) -> int:
+def stmg_footprint(problem: stmg_problem, options: stmg_options, with_adjoint: bool = False) -> int:
     out = C.c_size_t()
-    _check(lib.stmg_footprint(C.byref(problem), C.byref(options), C.byref(out)), "stmg_footprint")
+    _check(lib.stmg_footprint(C.byref(problem), C.byref(options), int(bool(with_adjoint)),
+                              C.byref(out)), "stmg_footprint")
     return out.value
 
 
@@ -158,6 +164,10 @@ def stmg_create(problem: stmg_problem, options: stmg_options, rho, q=None, strea
     _check(lib.stmg_create(C.byref(h), C.byref(problem), C.byref(options), _ptr(rho), _ptr(q),
                            _stream_ptr(stream)), "stmg_create")
     return h.value
+
+
+def stmg_set_field(h: int, field) -> int:
+    return _check(lib.stmg_set_field(h, _ptr(field)), "stmg_set_field")
 
 
 def stmg_set_design(h: int, rho) -> int:
@@ -238,6 +248,14 @@ def stmg_vcycle(h, transpose, b, u) -> float:
     return r.value
 
 
+def stmg_pass_geometry(n_el: int, n_t: int, sweeps: int, fp32: bool = False,
+                       fine: bool = False) -> dict:
+    out = [C.c_int() for _ in range(4)]
+    _check(lib.stmg_pass_geometry(n_el, n_t, sweeps, int(fp32), int(fine),
+                                  *[C.byref(o) for o in out]), "stmg_pass_geometry")
+    return dict(zip(("strip_cols", "strips", "seg_rows", "waves"), (o.value for o in out)))
+
+
 # ---- convenience wrapper -------------------------------------------------------------
 
 @dataclass
@@ -256,11 +274,12 @@ class Problem:
     p_c: float = 2.0
     theta_ref: float = 1.0
     q_uniform: float = 1.0
+    field_kind: int = STMG_FIELD_DENSITY
 
     def c_struct(self) -> stmg_problem:
         return stmg_problem(self.n_el, self.n_t, self.length, self.t_final, self.k_ins,
                             self.k_con, self.c_ins, self.c_con, self.p_k, self.p_c,
-                            self.theta_ref, self.q_uniform)
+                            self.theta_ref, self.q_uniform, self.field_kind)
 
 
 def make_options(**kw) -> stmg_options:
@@ -284,6 +303,8 @@ class SolveStats:
     fine_kernel_ms: float
     fine_kernel_bytes: float
     fine_kernel_launches: int
+    setup_ms: float = 0.0
+    path: str = ""
     history: list = field(default_factory=list)
 
     @classmethod
@@ -291,20 +312,34 @@ class SolveStats:
         n = s.cycles
         return cls(s.status, s.cycles, s.n_levels, s.rel_residual, s.conv_factor, s.solve_ms,
                    s.dof_updates, s.fine_kernel_ms, s.fine_kernel_bytes, s.fine_kernel_launches,
-                   [s.history[i] for i in range(n + 1)])
+                   s.setup_ms, s.path.decode(), [s.history[i] for i in range(n + 1)])
 
 
 class Solver:
-    """Owns one libstmg handle (hierarchy resident on the device)."""
+    """Owns one libstmg handle (hierarchy resident on the device).
+
+    Every library call runs on the handle's stream (``stream``, else the stream current
+    at construction).  Before each call that stream waits for the work already queued
+    on the caller's current stream (which may still be producing an input), and the
+    outputs this class allocates are allocated while the handle's stream is current, so
+    the caching allocator never hands the library a block that other streams' pending
+    work still uses."""
 
     def __init__(self, problem: Problem, rho, q=None, stream=None, **options):
         import torch
+        self._torch = torch
         self.problem = problem
         self.options = make_options(**options)
         self.device = rho.device
-        self.stream = stream
-        self.handle = stmg_create(problem.c_struct(), self.options, rho, q, stream)
-        self._torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._order()
+        self.handle = stmg_create(problem.c_struct(), self.options, rho, q, self.stream)
+
+    def _order(self):
+        """Make the handle's stream wait for the caller's current stream."""
+        cur = self._torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -330,34 +365,46 @@ class Solver:
                 "device_bytes": i.device_bytes, "tail_level": i.tail_level}
 
     def _new(self, shape=None):
-        return self._torch.empty(shape or self.shape, dtype=self._torch.float64, device=self.device)
+        """Output tensor allocated on the handle's stream."""
+        with self._torch.cuda.stream(self.stream):
+            return self._torch.empty(shape or self.shape, dtype=self._torch.float64,
+                                     device=self.device)
 
     def solve_forward(self, rhs=None, u0=None, out=None):
         u = out if out is not None else self._new()
         st = stmg_stats()
+        self._order()
         stmg_solve_forward(self.handle, rhs, u0, u, st)
         return u, SolveStats.from_c(st)
 
     def solve_adjoint(self, rhs=None, l0=None, out=None):
         lam = out if out is not None else self._new()
         st = stmg_stats()
+        self._order()
         stmg_solve_adjoint(self.handle, rhs, l0, lam, st)
         return lam, SolveStats.from_c(st)
 
     def objective(self, u) -> float:
+        self._order()
         return stmg_objective(self.handle, u)
 
-    def gradient(self, u, lam):
-        g = self._torch.empty(self.problem.n_el, dtype=self._torch.float64, device=self.device)
+    def gradient(self, u, lam, out=None):
+        g = out if out is not None else self._new((self.problem.n_el,))
+        self._order()
         stmg_gradient(self.handle, u, lam, g)
         return g
 
+    def set_field(self, field):
+        self._order()
+        stmg_set_field(self.handle, field)
+
     def set_design(self, rho):
-        stmg_set_design(self.handle, rho)
+        self.set_field(rho)
 
     def oc_update(self, rho, grad, volume: float, move: float = 0.2, eta: float = 0.5,
                   rho_min: float = 1e-3, out=None):
-        new = out if out is not None else self._torch.empty_like(rho)
+        new = out if out is not None else self._new(tuple(rho.shape))
+        self._order()
         stmg_oc_update(self.handle, rho, grad, volume, move, eta, rho_min, new)
         return new
 

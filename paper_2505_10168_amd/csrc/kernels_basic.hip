@@ -246,6 +246,19 @@ void launch_copy2d(const Tin* src, int64_t sp, Tout* dst, int64_t dp, int rows, 
                        dim3(kBlock), 0, s, src, sp, dst, dp, rows, cols, scale);
 }
 
+template <typename T>
+__global__ void k_fill2d(T* __restrict__ x, int64_t P, int rows, int cols, T v) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    for (int r = blockIdx.y; r < rows; r += gridDim.y) x[(int64_t)r * P + c] = v;
+}
+
+template <typename T>
+void launch_fill2d(T* x, int64_t P, int rows, int cols, T v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill2d<T>, dim3(blocks_for(cols), rows_grid(rows)), dim3(kBlock), 0, s,
+                       x, P, rows, cols, v);
+}
+
 template <typename Tin>
 __global__ void k_axpy2d(const Tin* __restrict__ src, int64_t sp, double* __restrict__ dst,
                          int64_t dp, int rows, int cols, double scale) {
@@ -856,6 +869,8 @@ void launch_oc_update(const double* chi, const double* g, int n, double volume, 
 // ---- explicit instantiations ---------------------------------------------------------
 template void launch_fill<double>(double*, int64_t, double, hipStream_t);
 template void launch_fill<float>(float*, int64_t, float, hipStream_t);
+template void launch_fill2d<double>(double*, int64_t, int, int, double, hipStream_t);
+template void launch_fill2d<float>(float*, int64_t, int, int, float, hipStream_t);
 template void launch_copy2d<double, double>(const double*, int64_t, double*, int64_t, int, int,
                                             double, hipStream_t);
 template void launch_copy2d<double, float>(const double*, int64_t, float*, int64_t, int, int,

@@ -555,6 +555,17 @@ void dispatch_sweeps(int S, int tail, const LevelView<T>& L, const FusedArgs<T>&
 
 int fused_max_sweeps() { return kMaxFused; }
 
+int fused_geometry(int N, int Nt, int sweeps, bool fp32, bool fine, int* strip_cols, int* strips,
+                   int* seg_rows, int* waves) {
+    if (sweeps < 0 || sweeps > kMaxFused) return -1;
+    const Geometry G = fp32 ? geometry<float>(N, Nt, sweeps, fine) : geometry<double>(N, Nt, sweeps, fine);
+    *strip_cols = G.U;
+    *strips = G.xw;
+    *seg_rows = G.seg;
+    *waves = G.nwaves;
+    return 0;
+}
+
 int fused_parts(int N, int Nt, int sweeps) {
     // the FP32 geometry (wider lanes) never needs more waves than the FP64 one
     return geometry<double>(N, Nt, sweeps, true).nwaves;
@@ -589,13 +600,22 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
     const int tail = fp.tail == 'x' ? TAIL_RX
                      : (fp.tail == 't' ? TAIL_RT : (fp.tail == 'n' ? TAIL_NORM : TAIL_NONE));
     if (fp.tail == 'c' || fp.prolong == 'c') {
-        // defect correction (FP64 only): u += s_old e; r = b - J u; f = r / s_new; norm
+        // defect correction (FP64 only): u += s_old e; r = b - J u; f = r / s_new; norm.
+        // Without the head ('c' tail alone) u is taken as it is: the first step of a
+        // solve, which must not read a correction left by an earlier solve.
         if constexpr (std::is_same<T, double>::value) {
-            if (fp.sweeps != 0 || fp.tail != 'c' || fp.prolong != 'c') return -1;
-            if (fp.trans)
-                launch_one<T, 1, 0, TAIL_DEFECT, 3>(L, a, lc, s);
-            else
-                launch_one<T, 0, 0, TAIL_DEFECT, 3>(L, a, lc, s);
+            if (fp.sweeps != 0 || fp.tail != 'c' || (fp.prolong != 'c' && fp.prolong != 0)) return -1;
+            if (fp.prolong == 'c') {
+                if (fp.trans)
+                    launch_one<T, 1, 0, TAIL_DEFECT, 3>(L, a, lc, s);
+                else
+                    launch_one<T, 0, 0, TAIL_DEFECT, 3>(L, a, lc, s);
+            } else {
+                if (fp.trans)
+                    launch_one<T, 1, 0, TAIL_DEFECT, 0>(L, a, lc, s);
+                else
+                    launch_one<T, 0, 0, TAIL_DEFECT, 0>(L, a, lc, s);
+            }
             return G.nwaves;
         } else {
             return -1;

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <type_traits>
 #include <utility>
@@ -198,6 +199,7 @@ struct stmg_ctx {
     uint64_t vcycles = 0;        // fine-level V-cycles started (sampled kernel timing)
     int tail_lds = 0;            // its dynamic LDS bytes (FP64 vectors: an upper bound)
     int norm_parts = 0;          // partial count written by the last fused norm
+    double setup_ms = 0;         // wall time of the last build or re-assembly
 
     ~stmg_ctx() {
         for (void* q : allocs) (void)hipFree(q);
@@ -243,6 +245,8 @@ int validate(const stmg_problem* p, const stmg_options* o) {
     if (!(p->k_ins > 0) || !(p->k_con > 0) || !(p->c_ins > 0) || !(p->c_con > 0))
         return fail(STMG_EINVAL, "material constants must be > 0");
     if (!(p->theta_ref > 0)) return fail(STMG_EINVAL, "theta_ref must be > 0");
+    if (p->field_kind != STMG_FIELD_DENSITY && p->field_kind != STMG_FIELD_CONDUCTIVITY)
+        return fail(STMG_EINVAL, "unknown field_kind");
     if (!std::isfinite(p->q_uniform)) return fail(STMG_EINVAL, "q_uniform must be finite");
     if (o->nu < 0 || o->nu > 64) return fail(STMG_EINVAL, "nu must be in [0, 64]");
     if (!(o->omega > 0)) return fail(STMG_EINVAL, "omega must be > 0");
@@ -259,6 +263,11 @@ int validate(const stmg_problem* p, const stmg_options* o) {
     if (o->interp != STMG_INTERP_C && o->interp != STMG_INTERP_B)
         return fail(STMG_EINVAL, "unknown interpolation");
     if (!(o->tol > 0) || !(o->diverge > 0)) return fail(STMG_EINVAL, "tol and diverge must be > 0");
+    if (o->debug_poison != 0 && o->debug_poison != 1) return fail(STMG_EINVAL, "debug_poison must be 0 or 1");
+    if (p->field_kind == STMG_FIELD_CONDUCTIVITY &&
+        (o->reassembly == STMG_REASSEMBLE_D || o->deff_mode == 1))
+        return fail(STMG_EINVAL, "a conductivity field has no design densities: reassembly D and "
+                                 "deff_mode 1 need field_kind = STMG_FIELD_DENSITY");
     return 0;
 }
 
@@ -377,17 +386,34 @@ int fetch_stats(stmg_ctx* h, const Level& l, double out[4]) {
     return 0;
 }
 
+// The fine level's element statistics must describe a positive, finite material.
+int check_material(const double st[4]) {
+    if (!(st[0] > 0) || !std::isfinite(st[1]) || !std::isfinite(st[3]) || !(st[2] > 0))
+        return fail(STMG_EINVAL, "conductivities and heat capacities must be positive and finite");
+    return 0;
+}
+
 double level_w(const stmg_options& o, const Level& l, const double st[4]) {
     if (o.w_diri_override > 0) return o.w_diri_override;
     // W_Diri = max_e c_e dx/dt + max_e k_e / dx  (Appendix A)
     return st[2] * l.h / l.tau + st[3] / l.h;
 }
 
-// Fills k, c, chi of level 0 from rho (SIMP, Section 2.1).
+// Fills k, c, chi of level 0 and the field derivatives of k and c from the field:
+// densities through SIMP (Section 2.1), or conductivities with c = c_con (then
+// dk/dfield = 1 and dc/dfield = 0).
 int level0_material(stmg_ctx* h) {
     Level& f = h->L[0];
     const stmg_problem& p = h->p;
     HIPCHK(hipMemcpyAsync(f.chi, h->rho, (size_t)f.N * 8, hipMemcpyDeviceToDevice, h->s));
+    if (p.field_kind == STMG_FIELD_CONDUCTIVITY) {
+        HIPCHK(hipMemcpyAsync(f.k, h->rho, (size_t)f.N * 8, hipMemcpyDeviceToDevice, h->s));
+        launch_fill<double>(f.c, f.N, p.c_con, h->s);
+        launch_fill<double>(h->kp, f.N, 1.0, h->s);
+        launch_fill<double>(h->cpd, f.N, 0.0, h->s);
+        HIPCHK(hipGetLastError());
+        return 0;
+    }
     launch_simp(h->rho, f.N, p.k_ins, p.k_con, p.p_k, f.k, h->s);
     launch_simp(h->rho, f.N, p.c_ins, p.c_con, p.p_c, f.c, h->s);
     launch_simp_derivative(h->rho, f.N, p.k_ins, p.k_con, p.p_k, h->kp, h->s);
@@ -528,6 +554,7 @@ int build(stmg_ctx* h, const double* d_q) {
         Level& cur = h->L.back();
         double st[4];
         CHK(fetch_stats(h, cur, st));
+        if (h->L.size() == 1) CHK(check_material(st));
         cur.W = level_w(h->o, cur, st);
         if (is_last(h, h->L.size(), cur)) break;
         double lam;
@@ -1111,7 +1138,7 @@ int defect_step(stmg_ctx* h, int trans, double s_e, double s_f, double* norm) {
         FusedPass fp{};
         fp.trans = trans;
         fp.sweeps = 0;
-        fp.prolong = 'c';
+        fp.prolong = s_e != 0.0 ? 'c' : 0;   // the first step has no correction to add
         fp.tail = 'c';
         fp.e32 = f.u32;
         fp.s_old = s_e;
@@ -1122,8 +1149,8 @@ int defect_step(stmg_ctx* h, int trans, double s_e, double s_f, double* norm) {
         const bool timed = h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
         timer_begin(h, timed, fp);
         const int nw = launch_fused<double>(V64, fp, f.u, f.b, f.t, h->s);
-        // u, e, b read; u, f written
-        timer_end(h, timed, (double)f.dofs() * (8 + 4 + 8 + 8 + 4));
+        // u, (e), b read; u, f written
+        timer_end(h, timed, (double)f.dofs() * (8 + (s_e != 0.0 ? 4 : 0) + 8 + 8 + 4));
         if (nw < 0) return fail(STMG_EINVAL, "defect-correction pass rejected");
         std::swap(f.u, f.t);
         HIPCHK(hipGetLastError());
@@ -1181,6 +1208,8 @@ int solve(stmg_ctx* h, int trans, const double* d_rhs, const double* d_u0, doubl
     if (st) {
         std::memset(st, 0, sizeof(*st));
         st->n_levels = (int)h->L.size();
+        st->setup_ms = h->setup_ms;
+        for (size_t i = 0; i + 1 < h->L.size() && i + 1 < sizeof(st->path); ++i) st->path[i] = h->L[i].dir;
     }
     h->timer.used = 0;
     CHK(set_rhs(h, trans, d_rhs));
@@ -1205,19 +1234,114 @@ int solve(stmg_ctx* h, int trans, const double* d_rhs, const double* d_u0, doubl
 int check_level(stmg_ctx* h, int level) {
     if (!h) return fail(STMG_EINVAL, "null handle");
     if (level < 0 || level >= (int)h->L.size()) return fail(STMG_EINVAL, "level out of range");
-    if (h->o.precision != STMG_FP64)
-        return fail(STMG_EUNSUPPORTED, "per-level entry points need an FP64 handle");
     return 0;
 }
 
-int copy_in(stmg_ctx* h, const Level& l, const double* src, double* dst) {
-    launch_copy2d<double, double>(src, l.N + 1, dst, l.P, l.Nt + 1, l.N + 1, 1.0, h->s);
+// FP64 interface vectors (compact) <-> level vectors of the cycle's precision (pitched)
+template <typename T>
+int copy_in(stmg_ctx* h, const Level& l, const double* src, T* dst) {
+    launch_copy2d<double, T>(src, l.N + 1, dst, l.P, l.Nt + 1, l.N + 1, 1.0, h->s);
     HIPCHK(hipGetLastError());
     return 0;
 }
-int copy_out(stmg_ctx* h, const Level& l, const double* src, double* dst) {
-    launch_copy2d<double, double>(src, l.P, dst, l.N + 1, l.Nt + 1, l.N + 1, 1.0, h->s);
+template <typename T>
+int copy_out(stmg_ctx* h, const Level& l, const T* src, double* dst) {
+    launch_copy2d<T, double>(src, l.P, dst, l.N + 1, l.Nt + 1, l.N + 1, 1.0, h->s);
     HIPCHK(hipGetLastError());
+    return 0;
+}
+
+// debug_poison: NaN in the nodes of a level vector a per-level call is about to compute
+// (the padding columns keep their zeros, which the streaming kernels read)
+template <typename T>
+void poison(stmg_ctx* h, const Level& l, T* x) {
+    if (h->o.debug_poison) launch_fill2d<T>(x, l.P, l.Nt + 1, l.N + 1, std::numeric_limits<T>::quiet_NaN(), h->s);
+}
+
+template <typename T>
+int level_apply(stmg_ctx* h, int level, int transpose, const double* d_x, double* d_y) {
+    Level& l = h->L[level];
+    CHK(copy_in<T>(h, l, d_x, U<T>(l)));
+    poison<T>(h, l, Tt<T>(l));
+    if (l.sten)
+        launch_apply_stencil<T>(sview<T>(l), transpose, APPLY_J, U<T>(l), B<T>(l), Tt<T>(l), false, h->s);
+    else
+        launch_apply<T>(view<T>(l, h->o.omega), transpose, APPLY_J, U<T>(l), B<T>(l), Tt<T>(l), false, h->s);
+    CHK(copy_out<T>(h, l, Tt<T>(l), d_y));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+template <typename T>
+int level_smooth(stmg_ctx* h, int level, int transpose, int nu, const double* d_b, double* d_u) {
+    Level& l = h->L[level];
+    CHK(copy_in<T>(h, l, d_b, B<T>(l)));
+    CHK(copy_in<T>(h, l, d_u, U<T>(l)));
+    poison<T>(h, l, Tt<T>(l));
+    const auto V = view<T>(l, h->o.omega);
+    T*& u = U<T>(l);
+    T*& t = Tt<T>(l);
+    if (l.sten) {
+        CHK(stencil_smooth<T>(h, l, transpose, false, nu));
+    } else if (h->o.fused) {
+        for (int S : chunks_of(nu)) {
+            FusedPass fp{};
+            fp.trans = transpose;
+            fp.sweeps = S;
+            launch_fused<T>(V, fp, u, B<T>(l), t, h->s);
+            std::swap(u, t);
+        }
+    } else {
+        for (int k = 0; k < nu; ++k) {
+            launch_apply<T>(V, transpose, APPLY_JACOBI, u, B<T>(l), t, false, h->s);
+            std::swap(u, t);
+        }
+    }
+    CHK(copy_out<T>(h, l, u, d_u));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+template <typename T>
+int level_presmooth_restrict(stmg_ctx* h, int level, int transpose, int nu, const double* d_b,
+                             double* d_u, double* d_bc) {
+    Level& l = h->L[level];
+    Level& c = h->L[level + 1];
+    CHK(copy_in<T>(h, l, d_b, B<T>(l)));
+    CHK(copy_in<T>(h, l, d_u, U<T>(l)));
+    poison<T>(h, l, Tt<T>(l));
+    poison<T>(h, c, B<T>(c));
+    CHK(pre_smooth_restrict<T>(h, level, transpose, false, nu));
+    CHK(copy_out<T>(h, l, U<T>(l), d_u));
+    CHK(copy_out<T>(h, c, B<T>(c), d_bc));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+template <typename T>
+int level_prolong_postsmooth(stmg_ctx* h, int level, int transpose, int nu, const double* d_b,
+                             const double* d_z, double* d_u) {
+    Level& l = h->L[level];
+    Level& c = h->L[level + 1];
+    CHK(copy_in<T>(h, l, d_b, B<T>(l)));
+    CHK(copy_in<T>(h, l, d_u, U<T>(l)));
+    CHK(copy_in<T>(h, c, d_z, U<T>(c)));
+    poison<T>(h, l, Tt<T>(l));
+    CHK(prolong_post_smooth<T>(h, level, transpose, nu, false));
+    CHK(copy_out<T>(h, l, U<T>(l), d_u));
+    HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+template <typename T>
+int level_coarsest_solve(stmg_ctx* h, int transpose, const double* d_b, double* d_z) {
+    const int last = (int)h->L.size() - 1;
+    Level& l = h->L[last];
+    CHK(copy_in<T>(h, l, d_b, B<T>(l)));
+    poison<T>(h, l, U<T>(l));
+    CHK(coarsest_solve<T>(h, last, transpose));
+    CHK(copy_out<T>(h, l, U<T>(l), d_z));
+    HIPCHK(hipStreamSynchronize(h->s));
     return 0;
 }
 
@@ -1227,6 +1351,7 @@ int reassemble(stmg_ctx* h, bool check_path) {
         Level& l = h->L[i];
         double st[4];
         CHK(fetch_stats(h, l, st));
+        if (i == 0) CHK(check_material(st));
         if (i + 1 < h->L.size()) {
             double lam;
             char d = choose_direction(h, l, st, &lam);
@@ -1307,10 +1432,12 @@ int stmg_default_options(stmg_options* o) {
     return 0;
 }
 
-int stmg_footprint(const stmg_problem* p, const stmg_options* o, size_t* bytes) {
+int stmg_footprint(const stmg_problem* p, const stmg_options* o, int with_adjoint, size_t* bytes) {
     CHK(validate(p, o));
     if (!bytes) return fail(STMG_EINVAL, "null output");
-    *bytes = footprint_of(p, o);
+    // the request's compact outputs: u, and with the adjoint Lambda and the gradient
+    const size_t vec = (size_t)dofs_of(p->n_el, p->n_t) * 8;
+    *bytes = footprint_of(p, o) + vec + (with_adjoint ? vec + (size_t)p->n_el * 8 : 0);
     return 0;
 }
 
@@ -1320,6 +1447,7 @@ int stmg_create(stmg_t* handle, const stmg_problem* p, const stmg_options* o,
     *handle = nullptr;
     CHK(validate(p, o));
     if (!d_rho) return fail(STMG_EINVAL, "null density");
+    const auto t0 = std::chrono::steady_clock::now();
     auto* h = new stmg_ctx();
     h->p = *p;
     h->o = *o;
@@ -1355,28 +1483,34 @@ int stmg_create(stmg_t* handle, const stmg_problem* p, const stmg_options* o,
         delete h;
         return rc;
     }
+    h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *handle = h;
     g_err.clear();
     return 0;
 }
 
-int stmg_set_design(stmg_t h, const double* d_rho) {
-    if (!h || !d_rho) return fail(STMG_EINVAL, "null argument");
-    // keep the old design to restore the handle if the path would change
+int stmg_set_field(stmg_t h, const double* d_field) {
+    if (!h || !d_field) return fail(STMG_EINVAL, "null argument");
+    const auto t0 = std::chrono::steady_clock::now();
+    // keep the old field to restore the handle if the new one is rejected
     std::vector<double> old((size_t)h->p.n_el);
     HIPCHK(hipMemcpyAsync(old.data(), h->rho, old.size() * 8, hipMemcpyDeviceToHost, h->s));
-    HIPCHK(hipMemcpyAsync(h->rho, d_rho, old.size() * 8, hipMemcpyDeviceToDevice, h->s));
+    HIPCHK(hipMemcpyAsync(h->rho, d_field, old.size() * 8, hipMemcpyDeviceToDevice, h->s));
     HIPCHK(hipStreamSynchronize(h->s));
     int rc = reassemble(h, h->o.deff_mode == 0);
-    if (rc == STMG_EUNSUPPORTED) {
+    if (rc == STMG_EUNSUPPORTED || rc == STMG_EINVAL) {
         std::string msg = g_err;
         HIPCHK(hipMemcpyAsync(h->rho, old.data(), old.size() * 8, hipMemcpyHostToDevice, h->s));
         HIPCHK(hipStreamSynchronize(h->s));
         CHK(reassemble(h, false));
-        return fail(STMG_EUNSUPPORTED, msg);
+        return fail(rc, msg);
     }
+    if (rc == 0)
+        h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return rc;
 }
+
+int stmg_set_design(stmg_t h, const double* d_rho) { return stmg_set_field(h, d_rho); }
 
 int stmg_solve_forward(stmg_t h, const double* d_rhs, const double* d_u0, double* d_u,
                        stmg_stats* st) {
@@ -1419,6 +1553,8 @@ int stmg_gradient_noalloc(const stmg_problem* p, const double* d_rho, const doub
     if (p->n_el < 1 || p->n_t < 1 || (int64_t)p->n_el > (1 << 24) || (int64_t)p->n_t > (1 << 26))
         return fail(STMG_EINVAL, "n_el and n_t must be in [1, 2^24] and [1, 2^26]");
     if (!(p->length > 0) || !(p->t_final > 0)) return fail(STMG_EINVAL, "length and t_final must be > 0");
+    if (p->field_kind != STMG_FIELD_DENSITY && p->field_kind != STMG_FIELD_CONDUCTIVITY)
+        return fail(STMG_EINVAL, "unknown field_kind");
     const int N = p->n_el, Nt = p->n_t;
     const int chunks = gradient_chunks(Nt);
     const size_t need = (size_t)N * (size_t)(chunks + 2);
@@ -1434,8 +1570,13 @@ int stmg_gradient_noalloc(const stmg_problem* p, const double* d_rho, const doub
     double* kp = sp;
     double* cpd = sp + N;
     double* parts = sp + 2 * (size_t)N;
-    launch_simp_derivative(d_rho, N, p->k_ins, p->k_con, p->p_k, kp, s);
-    launch_simp_derivative(d_rho, N, p->c_ins, p->c_con, p->p_c, cpd, s);
+    if (p->field_kind == STMG_FIELD_CONDUCTIVITY) {
+        launch_fill<double>(kp, N, 1.0, s);
+        launch_fill<double>(cpd, N, 0.0, s);
+    } else {
+        launch_simp_derivative(d_rho, N, p->k_ins, p->k_con, p->p_k, kp, s);
+        launch_simp_derivative(d_rho, N, p->c_ins, p->c_con, p->p_c, cpd, s);
+    }
     const double hx = p->length / p->n_el, tau = p->t_final / p->n_t;
     launch_gradient_partial(d_u, d_lambda, N, Nt, N + 1, N + 1, kp, cpd, hx, tau, parts, s);
     launch_gradient_final(parts, N, chunks, d_grad, s);
@@ -1484,47 +1625,19 @@ int stmg_destroy(stmg_t h) {
     return 0;
 }
 
+#define STMG_BY_PRECISION(h, call) \
+    ((h)->o.precision == STMG_MIXED ? call<float> : call<double>)
+
 int stmg_level_apply(stmg_t h, int level, int transpose, const double* d_x, double* d_y) {
     CHK(check_level(h, level));
     if (!d_x || !d_y) return fail(STMG_EINVAL, "null vector");
-    Level& l = h->L[level];
-    CHK(copy_in(h, l, d_x, l.u));
-    if (l.sten)
-        launch_apply_stencil<double>(stencil_view(l), transpose, APPLY_J, l.u, l.b, l.t, false, h->s);
-    else
-        launch_apply<double>(view<double>(l, h->o.omega), transpose, APPLY_J, l.u, l.b, l.t, false,
-                             h->s);
-    CHK(copy_out(h, l, l.t, d_y));
-    HIPCHK(hipStreamSynchronize(h->s));
-    return 0;
+    return STMG_BY_PRECISION(h, level_apply)(h, level, transpose, d_x, d_y);
 }
 
 int stmg_level_smooth(stmg_t h, int level, int transpose, int nu, const double* d_b, double* d_u) {
     CHK(check_level(h, level));
     if (!d_b || !d_u || nu < 0) return fail(STMG_EINVAL, "bad argument");
-    Level& l = h->L[level];
-    CHK(copy_in(h, l, d_b, l.b));
-    CHK(copy_in(h, l, d_u, l.u));
-    const auto V = view<double>(l, h->o.omega);
-    if (l.sten) {
-        CHK(stencil_smooth<double>(h, l, transpose, false, nu));
-    } else if (h->o.fused) {
-        for (int S : chunks_of(nu)) {
-            FusedPass fp{};
-            fp.trans = transpose;
-            fp.sweeps = S;
-            launch_fused<double>(V, fp, l.u, l.b, l.t, h->s);
-            std::swap(l.u, l.t);
-        }
-    } else {
-        for (int k = 0; k < nu; ++k) {
-            launch_apply<double>(V, transpose, APPLY_JACOBI, l.u, l.b, l.t, false, h->s);
-            std::swap(l.u, l.t);
-        }
-    }
-    CHK(copy_out(h, l, l.u, d_u));
-    HIPCHK(hipStreamSynchronize(h->s));
-    return 0;
+    return STMG_BY_PRECISION(h, level_smooth)(h, level, transpose, nu, d_b, d_u);
 }
 
 int stmg_level_presmooth_restrict(stmg_t h, int level, int transpose, int nu, const double* d_b,
@@ -1532,15 +1645,7 @@ int stmg_level_presmooth_restrict(stmg_t h, int level, int transpose, int nu, co
     CHK(check_level(h, level));
     if (level + 1 >= (int)h->L.size()) return fail(STMG_EINVAL, "coarsest level has no restriction");
     if (!d_b || !d_u || !d_bc || nu < 0) return fail(STMG_EINVAL, "bad argument");
-    Level& l = h->L[level];
-    Level& c = h->L[level + 1];
-    CHK(copy_in(h, l, d_b, l.b));
-    CHK(copy_in(h, l, d_u, l.u));
-    CHK(pre_smooth_restrict<double>(h, level, transpose, false, nu));
-    CHK(copy_out(h, l, l.u, d_u));
-    CHK(copy_out(h, c, c.b, d_bc));
-    HIPCHK(hipStreamSynchronize(h->s));
-    return 0;
+    return STMG_BY_PRECISION(h, level_presmooth_restrict)(h, level, transpose, nu, d_b, d_u, d_bc);
 }
 
 int stmg_level_prolong_postsmooth(stmg_t h, int level, int transpose, int nu, const double* d_b,
@@ -1548,36 +1653,31 @@ int stmg_level_prolong_postsmooth(stmg_t h, int level, int transpose, int nu, co
     CHK(check_level(h, level));
     if (level + 1 >= (int)h->L.size()) return fail(STMG_EINVAL, "coarsest level has no prolongation");
     if (!d_b || !d_u || !d_z || nu < 0) return fail(STMG_EINVAL, "bad argument");
-    Level& l = h->L[level];
-    Level& c = h->L[level + 1];
-    CHK(copy_in(h, l, d_b, l.b));
-    CHK(copy_in(h, l, d_u, l.u));
-    CHK(copy_in(h, c, d_z, c.u));
-    CHK(prolong_post_smooth<double>(h, level, transpose, nu, false));
-    CHK(copy_out(h, l, l.u, d_u));
-    HIPCHK(hipStreamSynchronize(h->s));
-    return 0;
+    return STMG_BY_PRECISION(h, level_prolong_postsmooth)(h, level, transpose, nu, d_b, d_z, d_u);
 }
 
 int stmg_level_coarsest_solve(stmg_t h, int transpose, const double* d_b, double* d_z) {
     if (!h) return fail(STMG_EINVAL, "null handle");
-    const int last = (int)h->L.size() - 1;
-    CHK(check_level(h, last));
+    CHK(check_level(h, (int)h->L.size() - 1));
     if (!d_b || !d_z) return fail(STMG_EINVAL, "null vector");
-    Level& l = h->L[last];
-    CHK(copy_in(h, l, d_b, l.b));
-    CHK(coarsest_solve<double>(h, last, transpose));
-    CHK(copy_out(h, l, l.u, d_z));
-    HIPCHK(hipStreamSynchronize(h->s));
-    return 0;
+    return STMG_BY_PRECISION(h, level_coarsest_solve)(h, transpose, d_b, d_z);
 }
 
 int stmg_vcycle(stmg_t h, int transpose, const double* d_b, double* d_u, double* rel_res) {
     CHK(check_level(h, 0));
+    if (h->o.precision != STMG_FP64) return fail(STMG_EUNSUPPORTED, "stmg_vcycle needs an FP64 handle");
     if (!d_b || !d_u) return fail(STMG_EINVAL, "null vector");
     Level& f = h->L[0];
-    CHK(copy_in(h, f, d_b, f.b));
-    CHK(copy_in(h, f, d_u, f.u));
+    CHK(copy_in<double>(h, f, d_b, f.b));
+    CHK(copy_in<double>(h, f, d_u, f.u));
+    if (h->o.debug_poison) {
+        poison<double>(h, f, f.t);
+        for (size_t i = 1; i < h->L.size(); ++i) {
+            poison<double>(h, h->L[i], h->L[i].u);
+            poison<double>(h, h->L[i], h->L[i].b);
+            poison<double>(h, h->L[i], h->L[i].t);
+        }
+    }
     CHK(vcycle<double>(h, 0, transpose, false, false));
     if (rel_res) {
         double nb, r;
@@ -1585,8 +1685,17 @@ int stmg_vcycle(stmg_t h, int transpose, const double* d_b, double* d_u, double*
         CHK(residual_norm64(h, transpose, &r));
         *rel_res = r / nb;
     }
-    CHK(copy_out(h, f, f.u, d_u));
+    CHK(copy_out<double>(h, f, f.u, d_u));
     HIPCHK(hipStreamSynchronize(h->s));
+    return 0;
+}
+
+int stmg_pass_geometry(int n_el, int n_t, int sweeps, int fp32, int fine, int* strip_cols,
+                       int* strips, int* seg_rows, int* waves) {
+    if (n_el < 1 || n_t < 1 || !strip_cols || !strips || !seg_rows || !waves)
+        return fail(STMG_EINVAL, "bad argument");
+    if (fused_geometry(n_el, n_t, sweeps, fp32 != 0, fine != 0, strip_cols, strips, seg_rows, waves) != 0)
+        return fail(STMG_EINVAL, "sweeps must be in [0, " + std::to_string(fused_max_sweeps()) + "]");
     return 0;
 }
 

@@ -32,6 +32,9 @@ void launch_load_vector(const double* q, double q0, int N, int Nt, double h, dou
 // ---- data movement ------------------------------------------------------------------
 template <typename T>
 void launch_fill(T* x, int64_t n, T v, hipStream_t s);
+// x[r*P + c] = v for r < rows, c < cols (columns beyond cols, the padding, untouched)
+template <typename T>
+void launch_fill2d(T* x, int64_t P, int rows, int cols, T v, hipStream_t s);
 // dst[r*dp + c] = (Tout)(scale * src[r*sp + c]) for r < rows, c < cols
 template <typename Tin, typename Tout>
 void launch_copy2d(const Tin* src, int64_t sp, Tout* dst, int64_t dp, int rows, int cols,
@@ -197,6 +200,10 @@ struct FusedPass {
 template <typename T>
 int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T* b, T* out,
                  hipStream_t s);
+// launch geometry of a fused pass: columns per strip, strips, time levels per
+// segment, wavefronts (-1 for an unsupported sweep count)
+int fused_geometry(int N, int Nt, int sweeps, bool fp32, bool fine, int* strip_cols, int* strips,
+                   int* seg_rows, int* waves);
 int fused_parts(int N, int Nt, int sweeps);
 int fused_max_sweeps();
 

@@ -167,13 +167,24 @@ class Request:
         return (self.n_el + 1) * (self.n_t + 1)
 
 
-def request_stream(n: int, rate_per_s: float, seed: int = 5,
-                   el_exp=(7, 12), t_exp=(8, 14)) -> list[Request]:
-    """Poisson arrivals of solve requests with power-of-two grids.
+def log_uniform_size(rng, lo: int, hi: int) -> int:
+    """exp(U(ln lo, ln hi)) rounded to two significant bits, i.e. to one of
+    {4, 5, 6, 7} * 2^q (four sizes per octave, each halving q times), kept in [lo, hi]."""
+    v = math.exp(rng.uniform(math.log(lo), math.log(hi)))
+    q = max(int(math.floor(math.log2(v))) - 2, 0)
+    return int(min(max(round(v / 2 ** q) * 2 ** q, lo), hi))
 
-    Elements 2^U{el_exp}, time steps 2^U{t_exp} (log-uniform over integer exponents),
-    block-16 0/1 density fields, kappa_min from {1e-2, 1e-3, 1e-4}; exactly half of
-    the requests also ask for the adjoint and gradient, in shuffled order.
+
+def request_stream(n: int, rate_per_s: float, seed: int = 5,
+                   el_range=(128, 4096), t_range=(256, 16384)) -> list[Request]:
+    """Poisson arrivals of solve requests with log-uniform grid sizes.
+
+    Elements log-uniform in el_range and time steps log-uniform in t_range, each
+    rounded to two significant bits ({4, 5, 6, 7} * 2^q: sizes that halve q times, so
+    that the hierarchy can coarsen far in both directions; el_range starts at 64 or
+    more, so fields are whole blocks of 16); block-16 0/1 density fields, kappa_min from
+    {1e-2, 1e-3, 1e-4}; exactly half of the requests also ask for the adjoint and
+    gradient, in shuffled order.
     """
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate_per_s, size=n) if rate_per_s > 0 else np.zeros(n)
@@ -182,8 +193,8 @@ def request_stream(n: int, rate_per_s: float, seed: int = 5,
     rng.shuffle(adj)
     out = []
     for r in range(n):
-        n_el = 2 ** int(rng.integers(el_exp[0], el_exp[1] + 1))
-        n_t = 2 ** int(rng.integers(t_exp[0], t_exp[1] + 1))
+        n_el = log_uniform_size(rng, el_range[0], el_range[1])
+        n_t = log_uniform_size(rng, t_range[0], t_range[1])
         kmin = float(rng.choice([1e-2, 1e-3, 1e-4]))
         rho = block_density(n_el, 16, seed=int(rng.integers(0, 2**31)))
         out.append(Request(r, float(arrivals[r]), n_el, n_t, kmin, rho, bool(adj[r])))

@@ -3,12 +3,18 @@
 Requests (grid, density field, kappa_min, forward-only or forward + adjoint +
 gradient) arrive at any time.  A fixed number of slots, each a host thread with its
 own HIP stream, pull requests from the queue as soon as the slot is free and the
-request's device footprint (stmg_footprint, plus its output vectors) fits the HBM
-budget; admitted requests run concurrently, so their kernels overlap on the device.
+request's device footprint (stmg_footprint: the hierarchy and the request's output
+vectors) fits the HBM budget; admitted requests run concurrently, so their kernels
+overlap on the device.
 Hierarchies stay resident after a request: a later request of the same grid and
 material re-assembles the idle hierarchy from its density (stmg_set_design, with the
 field-independent coarsening path of Section 7.2) instead of allocating a new one.
 Idle hierarchies are evicted, least recently used first, when memory is needed.
+
+Recovery: a mixed-precision solve that diverges (FP32 range or rounding can break
+the inner cycles where FP64 would not, cf. the divergence bound of Section 3.1) is
+solved once more on an FP64 hierarchy built for the request; the extra device memory
+is admitted like a request (waiting for releases), and the result records the retry.
 
 All arithmetic runs in libstmg; every kernel is deterministic and independent of
 co-running work, so a result does not depend on the mix it was solved in.
@@ -59,6 +65,7 @@ class SolveResult:
     completed: float
     slot: int
     reused_hierarchy: bool
+    fp64_retry: bool = False            # the mixed solve diverged and FP64 solved it
 
     @property
     def latency(self) -> float:
@@ -103,6 +110,7 @@ class ServerStats:
     reused: int = 0
     created: int = 0
     evicted: int = 0
+    retried_fp64: int = 0
     peak_in_flight: int = 0
     peak_bytes: int = 0
     dof_updates: float = 0.0
@@ -113,7 +121,10 @@ class Server:
     """Continuous batching of STMG solves (see the module docstring)."""
 
     def __init__(self, device=None, slots: int = 8, hbm_budget: int | None = None,
-                 precision: int = B.STMG_MIXED, keep_resident: bool = True, **options):
+                 precision: int = B.STMG_MIXED, keep_resident: bool = True,
+                 retry_fp64: bool = True, mixed_overrides: dict | None = None, **options):
+        """mixed_overrides: options applied to the mixed-precision attempt only (for
+        example a tight divergence bound that forces the FP64 retry in a test)."""
         import torch
         self.torch = torch
         self.device = torch.device(device if device is not None else "cuda:0")
@@ -122,6 +133,11 @@ class Server:
             hbm_budget = int(0.8 * free)
         self.admission = Admission(hbm_budget)
         self.options = dict(options, precision=precision, deff_mode=1)
+        self.fp64_options = dict(self.options, precision=B.STMG_FP64)
+        if precision == B.STMG_MIXED and mixed_overrides:
+            self.options.update(mixed_overrides)
+        self.retry_fp64 = retry_fp64 and precision == B.STMG_MIXED
+        self._growing = 0                      # in-flight requests waiting for retry memory
         self.keep_resident = keep_resident
         self.stats = ServerStats()
         self._cv = threading.Condition()
@@ -182,10 +198,15 @@ class Server:
     def _problem(self, req: SolveRequest) -> B.Problem:
         return B.Problem(req.n_el, req.n_t, req.length, req.t_final, k_ins=req.kappa_min)
 
-    def _footprint(self, req: SolveRequest) -> int:
-        hier = B.stmg_footprint(self._problem(req).c_struct(), B.make_options(**self.options))
-        outputs = (2 if req.with_adjoint else 1) * req.dofs * 8 + 8 * req.n_el
-        return hier + outputs
+    def _footprint(self, req: SolveRequest, options: dict | None = None) -> int:
+        """Device bytes of the request: hierarchy plus outputs (stmg_footprint)."""
+        return B.stmg_footprint(self._problem(req).c_struct(),
+                                B.make_options(**(options or self.options)), req.with_adjoint)
+
+    @staticmethod
+    def _outputs(req: SolveRequest) -> int:
+        """The output part of stmg_footprint: u, and with the adjoint Lambda and g."""
+        return req.dofs * 8 + ((req.dofs + req.n_el) * 8 if req.with_adjoint else 0)
 
     def _take_idle(self, key):
         for hid, (k, solver, nbytes) in self._idle.items():
@@ -206,16 +227,10 @@ class Server:
         """Called with the lock held: returns (request, reused solver or None, bytes)."""
         if not self._waiting:
             return None
-        free = self.admission.budget - self._in_use - self._idle_bytes
-
-        def need(r):
-            # an idle hierarchy of the same key can be reused: only its outputs are new
-            for k, _, nb in self._idle.values():
-                if k == r.key():
-                    return self._footprint(r) - nb
-            return self._footprint(r)
-
-        i = self.admission.pick(self._waiting, free + self._idle_bytes, need)
+        # every idle hierarchy, a reusable one included, can be evicted, so a request
+        # fits when its whole footprint fits beside the requests in flight
+        i = self.admission.pick(self._waiting, self.admission.budget - self._in_use,
+                                self._footprint)
         if i is None:
             return None
         req = self._waiting.pop(i)
@@ -255,6 +270,10 @@ class Server:
                         solver.set_design(rho)
                         created = False
                     u, fst = solver.solve_forward()
+                    retried = False
+                    if fst.status == B.STMG_DIVERGED and self.retry_fp64:
+                        solver, total, u, fst = self._fp64_retry(req, solver, total, rho)
+                        retried = True
                     theta = solver.objective(u)
                     grad, ast = None, None
                     if req.with_adjoint:
@@ -266,10 +285,11 @@ class Server:
                     stream.synchronize()
                 done = time.perf_counter()
                 res = SolveResult(req.rid, theta, final, grad, fst, ast, req.arrival, admitted,
-                                  done, slot, reused)
+                                  done, slot, reused, retried)
                 with self._cv:
                     self.stats.completed += 1
                     self.stats.reused += int(reused)
+                    self.stats.retried_fp64 += int(retried)
                     self.stats.created += int(created)
                     self.stats.dof_updates += fst.dof_updates + (ast.dof_updates if ast else 0.0)
                     self.stats.latencies.append(res.latency)
@@ -280,12 +300,54 @@ class Server:
                     self._release(req, solver, total, keep=False)
                 fut.set_exception(exc)
 
+    def _fp64_retry(self, req, solver, total, rho):
+        """The mixed solve diverged: drop its hierarchy and solve once in FP64 on a new
+        one, admitted for the difference in footprint.  Returns the FP64 solver, the
+        request's new byte total, u and the stats."""
+        solver.close()
+        need = self._footprint(req, self.fp64_options)
+        if not self._grow(need - total):
+            raise MemoryError(f"request {req.rid}: no memory for the FP64 retry ({need} bytes)")
+        try:
+            fp64 = B.Solver(self._problem(req), rho, stream=solver.stream, **self.fp64_options)
+        except Exception:
+            self._grow(total - need)           # hand the extra bytes back
+            raise
+        fp64.fp64_retry = True
+        u, fst = fp64.solve_forward()
+        return fp64, need, u, fst
+
+    def _grow(self, extra: int) -> bool:
+        """Admit `extra` more bytes for a request in flight, waiting for releases and
+        evicting idle hierarchies; gives up when every request in flight is waiting too."""
+        if extra <= 0:
+            with self._cv:
+                self._in_use += extra
+            return True
+        with self._cv:
+            self._growing += 1
+            try:
+                while True:
+                    self._evict_for(extra)
+                    if self.admission.budget - self._in_use - self._idle_bytes >= extra:
+                        self._in_use += extra
+                        self.stats.peak_bytes = max(self.stats.peak_bytes,
+                                                    self._in_use + self._idle_bytes)
+                        return True
+                    if self._in_flight - self._growing <= 0:
+                        return False
+                    self._cv.wait(timeout=0.05)
+            finally:
+                self._growing -= 1
+
     def _release(self, req, solver, total, keep=True):
         """Lock held: return the request's memory; keep its hierarchy resident."""
         self._in_use -= total
         self._in_flight -= 1
+        if getattr(solver, "fp64_retry", False):
+            keep = False                       # FP64 hierarchies do not serve later requests
         if solver is not None and keep and self.keep_resident:
-            hb = total - ((2 if req.with_adjoint else 1) * req.dofs * 8 + 8 * req.n_el)
+            hb = total - self._outputs(req)
             self._idle[id(solver)] = (req.key(), solver, hb)
             self._idle_bytes += hb
         elif solver is not None:

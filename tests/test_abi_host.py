@@ -58,6 +58,31 @@ def test_footprint_grows_with_grid_and_precision():
     assert fixed <= big
 
 
+def test_footprint_counts_the_request_outputs():
+    """with_adjoint adds the adjoint solution and the gradient to the solution vector."""
+    o = B.make_options()
+    prob = B.Problem(100, 300)
+    f0 = B.stmg_footprint(prob.c_struct(), o, False)
+    f1 = B.stmg_footprint(prob.c_struct(), o, True)
+    assert f1 - f0 == (101 * 301 + 100) * 8
+
+
+def test_field_kind_validation():
+    """A conductivity field has no densities: reassembly D and the SIMP-extrema D_eff
+    need field_kind = density; unknown kinds are rejected."""
+    cond = B.Problem(64, 64, field_kind=B.STMG_FIELD_CONDUCTIVITY)
+    assert B.stmg_footprint(cond.c_struct(), B.make_options()) > 0
+    for bad in (dict(reassembly=B.STMG_REASSEMBLE_D), dict(deff_mode=1)):
+        with pytest.raises(B.StmgError) as e:
+            B.stmg_footprint(cond.c_struct(), B.make_options(**bad))
+        assert e.value.code == B.STMG_EINVAL
+    with pytest.raises(B.StmgError) as e:
+        B.stmg_footprint(B.Problem(64, 64, field_kind=2).c_struct(), B.make_options())
+    assert e.value.code == B.STMG_EINVAL
+    with pytest.raises(B.StmgError):
+        B.stmg_footprint(B.Problem(64, 64).c_struct(), B.make_options(debug_poison=2))
+
+
 @pytest.mark.parametrize("field,value", [("n_el", 0), ("n_t", -1), ("length", 0.0),
                                          ("k_ins", -1.0), ("theta_ref", 0.0)])
 def test_create_rejects_bad_problem_without_device_work(field, value):
@@ -100,7 +125,7 @@ def test_galerkin_footprint_in_mixed_precision():
         for prec in (B.STMG_FP64, B.STMG_MIXED):
             o = B.make_options(reassembly=reas, precision=prec, deff_mode=1, max_levels=3)
             n = C.c_size_t()
-            assert B.lib.stmg_footprint(C.byref(p), C.byref(o), C.byref(n)) == 0
+            assert B.lib.stmg_footprint(C.byref(p), C.byref(o), 0, C.byref(n)) == 0
             sizes[reas, prec] = n.value
     extra64 = sizes[B.STMG_REASSEMBLE_P, B.STMG_FP64] - sizes[B.STMG_REASSEMBLE_R, B.STMG_FP64]
     extra32 = sizes[B.STMG_REASSEMBLE_P, B.STMG_MIXED] - sizes[B.STMG_REASSEMBLE_R, B.STMG_MIXED]
@@ -116,7 +141,7 @@ def test_footprint_counts_the_bilinear_galerkin_coarsest_factors():
         o = B.make_options(reassembly=B.STMG_REASSEMBLE_P, interp=interp, deff_mode=1,
                            max_levels=2)
         n = C.c_size_t()
-        assert B.lib.stmg_footprint(C.byref(p), C.byref(o), C.byref(n)) == 0
+        assert B.lib.stmg_footprint(C.byref(p), C.byref(o), 0, C.byref(n)) == 0
         sizes[interp] = n.value
     assert sizes[B.STMG_INTERP_B] > sizes[B.STMG_INTERP_C] + 2 * (33 * 65) ** 2 * 8 - 1
 
@@ -135,7 +160,7 @@ int main(void) {
     p.n_el = 64; p.n_t = 64; p.length = 1.0; p.t_final = 0.1;
     p.k_ins = 1e-3; p.k_con = 1.0; p.c_ins = 1.0; p.c_con = 1.0; p.p_k = 3.0; p.p_c = 2.0;
     p.theta_ref = 1.0; p.q_uniform = 1.0;
-    if (stmg_footprint(&p, &o, &bytes) != STMG_OK || bytes == 0) return 3;
+    if (stmg_footprint(&p, &o, 1, &bytes) != STMG_OK || bytes == 0) return 3;
     if (stmg_create(NULL, &p, &o, NULL, NULL, NULL) != STMG_EINVAL) return 4;
     printf("%s %zu %d\n", stmg_status_string(STMG_DIVERGED), bytes, o.nu);
     return 0;

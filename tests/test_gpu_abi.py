@@ -1,0 +1,193 @@
+"""GPU tests of the boundary's set-up forms against the oracle: the Algorithm 3 tie,
+hierarchies built from a conductivity field (Section 2: k(x), c(x)), the statistics a
+solve reports, the FP32 per-level components of a mixed-precision handle, and a mixed
+solve that follows a diverged one on the same handle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from tests.helpers import I, O, rel, to_dev, to_np
+from tests.test_gpu_parity import CASES
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n_t,path", [(64, "x"), (66, "t")])
+def test_alg3_tie_takes_x(n_t, path, cuda):
+    """lambda_eff = lambda_crit = 1/4 exactly (h = 1/4, tau = 1/64, D_eff = 1) gives x,
+    lambda_eff = 16/66 gives t: from a conductivity field, from densities through SIMP
+    (k in {1/4, 4}) with D_eff from the field, and with the Section 7.2 extrema."""
+    from paper_2505_10168_amd import binding as B
+    k = np.array([0.25, 4.0, 4.0, 0.25])
+    rho = np.array([0.0, 1.0, 1.0, 0.0])
+    forms = [
+        (B.Problem(4, n_t, 1.0, 1.0, field_kind=B.STMG_FIELD_CONDUCTIVITY), k, {}),
+        (B.Problem(4, n_t, 1.0, 1.0, k_ins=0.25, k_con=4.0), rho, {}),
+        (B.Problem(4, n_t, 1.0, 1.0, k_ins=0.25, k_con=4.0), rho, {"deff_mode": 1}),
+    ]
+    for prob, field, extra in forms:
+        s = B.Solver(prob, to_dev(field, cuda), max_levels=2, **extra)
+        info = s.info()
+        assert info["lambda_eff"][0] == 16.0 / n_t
+        assert info["path"] == path, (prob, extra, info["path"])
+        s.close()
+    lv = O.Level(4, n_t, 0.25, 1.0 / n_t, k, np.ones(4))
+    assert O.build_hierarchy(lv, O.Options(max_levels=2)).path == path
+
+
+def conductivity_case(n_el=200, n_t=480, c=0.7, seed=11):
+    """Element conductivities spanning two decades in blocks of 8, heat capacity c."""
+    rng = np.random.default_rng(seed)
+    k = np.repeat(10.0 ** rng.uniform(-2, 0, n_el // 8), 8)
+    # the oracle's SIMP map with k_ins = 0, k_con = 1, p_k = 1 is k itself, and
+    # c_ins = c_con makes c constant (derivatives 1 and 0)
+    mat = O.Material(0.0, 1.0, c, c, 1.0, 2.0)
+    return k, n_t, c, mat
+
+
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_conductivity_field_matches_oracle(transpose, cuda):
+    from paper_2505_10168_amd import binding as B
+    k, n_t, c, mat = conductivity_case()
+    n_el = k.size
+    prob = B.Problem(n_el, n_t, c_con=c, field_kind=B.STMG_FIELD_CONDUCTIVITY)
+    s = B.Solver(prob, to_dev(k, cuda), nu=5, max_cycles=400)
+    lv = O.make_fine_level(k, mat, n_t, 1.0, 0.1)
+    np.testing.assert_array_equal(lv.k, k)
+    h = O.build_hierarchy(lv, O.Options(nu=5))
+    info = s.info()
+    assert info["path"] == h.path and info["n_el"] == [l.n_el for l in h.levels]
+    for a, l in zip(info["w_diri"], h.levels):
+        assert a == pytest.approx(l.W, rel=1e-15)
+    for a, lam in zip(info["lambda_eff"], h.lambdas):
+        assert a == pytest.approx(lam, rel=1e-14)
+    b = O.load_vector(lv, 1.0)
+    rhs = O.adjoint_rhs(lv, b) if transpose else b
+    u = np.zeros(lv.shape)
+    ud, bd = to_dev(u, cuda), to_dev(rhs, cuda)
+    for it in range(3):
+        B.stmg_vcycle(s.handle, transpose, bd, ud)
+        u = O.vcycle(h, 0, u, rhs, bool(transpose))
+        assert rel(to_np(ud), u) <= 1e-12, (it, rel(to_np(ud), u))
+    # converged solves, objective and dTheta/dk against the oracle's direct solves
+    uf, st = s.solve_forward()
+    la, sa = s.solve_adjoint()
+    assert st.status == 0 and sa.status == 0
+    u_ex = O.direct_solve(lv, b)
+    l_ex = O.direct_solve(lv, O.adjoint_rhs(lv, b), transpose=True)
+    assert rel(to_np(uf), u_ex) <= 1e-8 and rel(to_np(la), l_ex) <= 1e-8
+    assert s.objective(uf) == pytest.approx(O.objective(lv, b, u_ex), rel=1e-9)
+    g = to_np(s.gradient(to_dev(u_ex, cuda), to_dev(l_ex, cuda)))
+    g_ref = O.gradient(lv, mat, k, u_ex, l_ex)
+    print(f"conductivity field: path {info['path']}, cycles {st.cycles}/{sa.cycles}, "
+          f"gradient rel err {rel(g, g_ref):.2e}")
+    assert rel(g, g_ref) <= 1e-12
+    s.close()
+
+
+def test_conductivity_field_must_be_positive(cuda):
+    from paper_2505_10168_amd import binding as B
+    k, n_t, c, _ = conductivity_case(64, 96)
+    prob = B.Problem(64, n_t, c_con=c, field_kind=B.STMG_FIELD_CONDUCTIVITY)
+    bad = k.copy()
+    bad[5] = 0.0
+    with pytest.raises(B.StmgError) as e:
+        B.Solver(prob, to_dev(bad, cuda))
+    assert e.value.code == B.STMG_EINVAL
+    s = B.Solver(prob, to_dev(k, cuda), deff_mode=0)
+    u0, st0 = s.solve_forward()
+    bad[5] = -1.0
+    with pytest.raises(B.StmgError) as e:
+        s.set_field(to_dev(bad, cuda))
+    assert e.value.code == B.STMG_EINVAL
+    u1, st1 = s.solve_forward()          # the handle keeps the previous field
+    assert st1.cycles == st0.cycles and np.array_equal(to_np(u0), to_np(u1))
+    s.close()
+
+
+def test_stats_report_path_and_setup_time(cuda):
+    from paper_2505_10168_amd import binding as B
+    rho = I.block_density(256, 16, seed=7)
+    s = B.Solver(B.Problem(256, 600, k_ins=1e-3), to_dev(rho, cuda), nu=3, deff_mode=1)
+    _, st = s.solve_forward()
+    assert st.path == s.info()["path"] and len(st.path) == st.n_levels - 1
+    assert st.setup_ms > 0
+    s.set_design(to_dev(I.block_density(256, 16, seed=8), cuda))
+    _, st2 = s.solve_adjoint()
+    assert st2.setup_ms > 0 and st2.path == st.path
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_fp32_level_components_match_oracle(name, transpose, cuda):
+    """The FP32 kernels of the mixed-precision inner cycles, one step of Algorithm 1 at
+    a time, against the FP64 oracle on the same (FP64) inputs.  The FP32 rounding of
+    the inputs alone is 6e-8 relative; each Jacobi step or residual multiplies the
+    error by at most the norm of the step (about 2 here), so a few steps stay below
+    1e-6 of the largest value, the bar (2.7e-7 seen; the coarsest solve: FP64
+    arithmetic on FP32 vectors, one rounding, 5e-8)."""
+    from paper_2505_10168_amd import binding as B
+    rho, n_t, kmin, c_ins, opts = CASES[name]
+    nu = opts.get("nu", 2)
+    prob = B.Problem(len(rho), n_t, k_ins=kmin, c_ins=c_ins)
+    s = B.Solver(prob, to_dev(rho, cuda), precision=B.STMG_MIXED, debug_poison=1, **opts)
+    mat = O.Material(kmin, 1.0, c_ins, 1.0)
+    lv = O.make_fine_level(rho, mat, n_t, 1.0, 0.1)
+    h = O.build_hierarchy(lv, O.Options(nu=nu))
+    assert s.info()["path"] == h.path
+    T = bool(transpose)
+    worst = {}
+    for l in range(len(h.levels) - 1):
+        lev, cl, d = h.levels[l], h.levels[l + 1], h.directions[l]
+        rng = np.random.default_rng(300 + l)
+        u = rng.standard_normal(lev.shape)
+        b = rng.standard_normal(lev.shape)
+        z = rng.standard_normal(cl.shape)
+        y = to_dev(np.full(lev.shape, np.nan), cuda)
+        B.stmg_level_apply(s.handle, l, transpose, to_dev(u, cuda), y)
+        worst["apply"] = max(worst.get("apply", 0), rel(to_np(y), O.apply_J(lev, u, T)))
+        ud = to_dev(u, cuda)
+        bc = to_dev(np.full(cl.shape, np.nan), cuda)
+        B.stmg_level_presmooth_restrict(s.handle, l, transpose, nu, to_dev(b, cuda), ud, bc)
+        u_ref = O.jacobi(h, l, u, b, nu, T)
+        bc_ref = O.restrict(lev, d, b - O.apply_J(lev, u_ref, T))
+        worst["pre"] = max(worst.get("pre", 0), rel(to_np(ud), u_ref))
+        worst["restrict"] = max(worst.get("restrict", 0), rel(to_np(bc), bc_ref))
+        ud = to_dev(u, cuda)
+        B.stmg_level_prolong_postsmooth(s.handle, l, transpose, nu, to_dev(b, cuda),
+                                        to_dev(z, cuda), ud)
+        ref = O.jacobi(h, l, u + O.prolong(lev, d, z), b, nu, T)
+        worst["post"] = max(worst.get("post", 0), rel(to_np(ud), ref))
+    lev = h.levels[-1]
+    b = np.random.default_rng(9).standard_normal(lev.shape)
+    z = to_dev(np.full(lev.shape, np.nan), cuda)
+    B.stmg_level_coarsest_solve(s.handle, transpose, to_dev(b, cuda), z)
+    worst["coarsest"] = rel(to_np(z), O.direct_solve(lev, b, T))
+    print(f"FP32 components {name} T={transpose}: " +
+          ", ".join(f"{k} {v:.1e}" for k, v in worst.items()))
+    assert max(worst.values()) <= 1e-6
+    s.close()
+
+
+def test_mixed_solve_after_a_diverged_one_matches_a_fresh_handle(cuda):
+    """A diverged mixed solve leaves a non-finite FP32 correction behind (here an
+    initial guess of infinities); the next solve on the same handle starts from u = 0
+    and must not read it: its iterates equal those of a fresh handle, bit for bit."""
+    import torch
+
+    from paper_2505_10168_amd import binding as B
+    rho = I.block_density(128, 16, seed=21)
+    p = B.Problem(128, 256, k_ins=1e-3)
+    a = B.Solver(p, to_dev(rho, cuda), nu=5, precision=B.STMG_MIXED)
+    inf = torch.full(a.shape, float("inf"), dtype=torch.float64, device=cuda)
+    _, bad = a.solve_forward(u0=inf)
+    assert bad.status == B.STMG_DIVERGED
+    ua, sa = a.solve_forward()
+    b = B.Solver(p, to_dev(rho, cuda), nu=5, precision=B.STMG_MIXED)
+    ub, sb = b.solve_forward()
+    assert sa.status == 0 and sa.cycles == sb.cycles and sa.history == sb.history
+    assert np.array_equal(to_np(ua), to_np(ub))
+    a.close()
+    b.close()

@@ -65,7 +65,7 @@ def test_autograd_backward_after_interleaved_forward(cuda):
 
 
 def small_stream(n, seed):
-    return I.request_stream(n, 0.0, seed=seed, el_exp=(6, 9), t_exp=(7, 10))
+    return I.request_stream(n, 0.0, seed=seed, el_range=(64, 512), t_range=(128, 1024))
 
 
 def to_req(r):
@@ -76,12 +76,12 @@ def to_req(r):
 def test_serving_results_same_alone_and_in_the_mix(cuda):
     from paper_2505_10168_amd.serving import Server
     reqs = small_stream(16, seed=11)
-    with Server(cuda, slots=4, nu=5, max_cycles=300) as srv:
+    with Server(cuda, slots=4, nu=20, max_cycles=300) as srv:
         futs = [srv.submit(to_req(r)) for r in reqs]
         mixed = {f.result().rid: f.result() for f in futs}
         stats = srv.stats
     assert stats.completed == len(reqs) and stats.peak_in_flight > 1
-    with Server(cuda, slots=1, nu=5, max_cycles=300, keep_resident=False) as solo:
+    with Server(cuda, slots=1, nu=20, max_cycles=300, keep_resident=False) as solo:
         alone = {r.rid: solo.submit(to_req(r)).result() for r in reqs}
     for r in reqs:
         m, a = mixed[r.rid], alone[r.rid]
@@ -103,15 +103,15 @@ def test_serving_admission_by_footprint(cuda):
     from paper_2505_10168_amd.serving import Server, SolveRequest
     reqs = small_stream(8, seed=12)
     big = max(reqs, key=lambda r: r.dofs)
-    with Server(cuda, slots=4, nu=5, max_cycles=300, hbm_budget=1) as tiny:
+    with Server(cuda, slots=4, nu=20, max_cycles=300, hbm_budget=1) as tiny:
         fut = tiny.submit(to_req(big))
         with pytest.raises(MemoryError):
             fut.result()
     # a budget that fits exactly one of the largest requests at a time
-    probe = Server(cuda, slots=1, nu=5)
+    probe = Server(cuda, slots=1, nu=20)
     one = probe._footprint(to_req(big))
     probe.close()
-    with Server(cuda, slots=4, nu=5, max_cycles=300, hbm_budget=int(1.5 * one),
+    with Server(cuda, slots=4, nu=20, max_cycles=300, hbm_budget=int(1.5 * one),
                 keep_resident=False) as srv:
         futs = [srv.submit(to_req(r)) for r in reqs]
         res = [f.result() for f in futs]
@@ -153,3 +153,25 @@ def test_autograd_with_galerkin_coarse_operators(cuda):
         assert theta.item() == pytest.approx(th_ref, rel=1e-9)
         assert rel(to_np(x.grad), g_ref) <= 1e-8
     cs.close()
+
+
+def test_serving_retries_a_diverged_mixed_solve_in_fp64(cuda):
+    """A mixed-precision solve that diverges is solved once more in FP64.  The
+    divergence is forced from the host: the mixed attempt runs with a divergence bound
+    of 1e-3 on the relative residual, which the first cycle already exceeds; the FP64
+    retry uses the normal bound.  The result reports the retry, its FP64 status, and
+    equals a plain FP64 solve of the same request."""
+    from paper_2505_10168_amd import binding as B
+    from paper_2505_10168_amd.serving import Server, SolveRequest
+    rho = I.block_density(128, 16, seed=41)
+    with Server(cuda, slots=2, nu=5, max_cycles=300, mixed_overrides={"diverge": 1e-3}) as srv:
+        res = srv.submit(SolveRequest(128, 256, rho, 1e-3, True)).result()
+        assert srv.stats.retried_fp64 == 1
+    assert res.fp64_retry and res.forward.status == B.STMG_OK
+    assert res.adjoint.status == B.STMG_OK and res.forward.rel_residual < 1e-10
+    s = B.Solver(B.Problem(128, 256, k_ins=1e-3), to_dev(rho, cuda), nu=5, max_cycles=300,
+                 deff_mode=1)
+    u, st = s.solve_forward()
+    assert st.cycles == res.forward.cycles
+    assert np.array_equal(to_np(u)[-1], res.final_temperature)
+    s.close()

@@ -75,21 +75,31 @@ def test_objective_and_gradient_match_oracle(name, cuda):
 
 
 def test_gradient_block_2048x8192_against_oracle_and_differences(cuda):
-    """Configuration 4: forward + adjoint STMG on 2048 x 8192 with the high-contrast
-    field, the gradient over all 2048 densities against the oracle's adjoint gradient
-    from direct solves, and against central differences of Theta (oracle direct
+    """Configuration 4 through the torch.autograd.Function: Theta(rho) with forward and
+    adjoint STMG solves on 2048 x 8192 with the high-contrast field, and the gradient
+    its backward returns over all 2048 densities, against the oracle's adjoint gradient
+    from direct solves and against central differences of Theta (oracle direct
     solves, h = 1e-6) on 16 seeded elements: 12 conducting elements drawn among those
     whose oracle sensitivity exceeds 1% of the largest (sensitivity decays behind
     insulating blocks to ~1e-30, below the ~1e-10 rounding noise of a difference of
-    the 1.7e7-term objective) and 4 insulating ones (k' = 0 there, so g = 0 exactly)."""
+    the 1.7e7-term objective) and 4 insulating ones (k' = 0 there, so g = 0 exactly).
+    The handle-level gradient (same hierarchy, stmg_gradient) must agree with it."""
     from paper_2505_10168_amd import binding as B
+    from paper_2505_10168_amd.autograd import ComplianceSolver
     w = I.workload("block_2048x8192")
     mat = O.Material(w.kappa_min, 1.0, 1.0, 1.0)
-    s = B.Solver(B.Problem(w.n_el, w.n_t, k_ins=w.kappa_min), to_dev(w.rho, cuda), nu=5)
+    prob = B.Problem(w.n_el, w.n_t, k_ins=w.kappa_min)
+    cs = ComplianceSolver(prob, to_dev(w.rho, cuda), nu=5, deff_mode=0)
+    x = to_dev(w.rho, cuda).requires_grad_(True)
+    theta_fn = cs(x)
+    theta_fn.backward()
+    g = to_np(x.grad)
+    assert cs.last_forward.status == 0 and cs.last_adjoint.status == 0
+    s = B.Solver(prob, to_dev(w.rho, cuda), nu=5)
     u, st = s.solve_forward()
     lam, sa = s.solve_adjoint()
     assert st.status == 0 and sa.status == 0
-    g = to_np(s.gradient(u, lam))
+    assert rel(to_np(s.gradient(u, lam)), g) <= 1e-10
     lv = O.make_fine_level(w.rho, mat, w.n_t, w.length, w.t_final)
     b = O.load_vector(lv, 1.0)
     u_or = O.direct_solve(lv, b)
@@ -99,7 +109,10 @@ def test_gradient_block_2048x8192_against_oracle_and_differences(cuda):
     print(f"max |g| = {gmax:.4e} at element {int(np.abs(g_or).argmax())}; "
           f"stmg vs oracle adjoint gradient {np.abs(g - g_or).max() / gmax:.2e}", flush=True)
     assert np.abs(g - g_or).max() <= 1e-8 * gmax
+    assert theta_fn.item() == pytest.approx(O.objective(lv, b, u_or), rel=1e-9)
     assert s.objective(u) == pytest.approx(O.objective(lv, b, u_or), rel=1e-9)
+    cs.close()
+    s.close()
 
     rng = np.random.default_rng(40)
     live = np.flatnonzero((w.rho == 1.0) & (np.abs(g_or) >= 1e-2 * gmax))
@@ -211,43 +224,134 @@ def test_block_1024x4096_iterates_and_solution(cuda):
     assert rel(to_np(uf), exact) <= 1e-8 and rel(to_np(lam), exact_l) <= 1e-8
 
 
-def window_reference(w, S, rows, b_full, u_full, transpose=False):
-    """Oracle sweeps on a window of time levels of the full fine level: the first S
-    levels of the window are warm-up (their coupling leaves the window) and only the
-    following levels are compared."""
+def window_level(w, rows):
+    """Oracle level of a window of time levels [r0, r1) of the full fine level (the
+    window's first level plays the part of level 0, so the first levels of a result
+    are spoiled by the missing coupling and are not compared)."""
     mat = O.Material(w.kappa_min, 1.0, 1.0, 1.0)
     full = O.make_fine_level(w.rho, mat, w.n_t, w.length, w.t_final)
     r0, r1 = rows
-    sub = O.Level(full.n_el, r1 - r0 - 1, full.h, full.tau, full.k, full.c, w_override=full.W)
+    return O.Level(full.n_el, r1 - r0 - 1, full.h, full.tau, full.k, full.c, w_override=full.W)
+
+
+def window_reference(w, S, rows, b_full, u_full, transpose=False, z_full=None):
+    """Oracle sweeps on a window of time levels of the full fine level, optionally after
+    the x prolongation of a coarse window z_full[r0:r1]."""
+    sub = window_level(w, rows)
+    r0, r1 = rows
     hh = O.Hierarchy([sub], [], [], O.Options())
-    out = O.jacobi(hh, 0, u_full[r0:r1].copy(), b_full[r0:r1].copy(), S, transpose)
-    return out
+    u = u_full[r0:r1].copy()
+    if z_full is not None:
+        u = u + O.prolong(sub, "x", z_full[r0:r1])
+    return O.jacobi(hh, 0, u, b_full[r0:r1].copy(), S, transpose)
 
 
-def test_boxfilt_8192x65536_fused_smoother_sampled(cuda):
-    """Configuration 3 at full size (5.4e8 DOFs): two fused Jacobi steps of the fine
-    level from seeded random u and b, compared with the oracle on windows of time levels
-    (start, a segment boundary region, the middle and the end)."""
-    import torch
+def segment_windows(w, sweeps, fp32, fine, half=16):
+    """Row windows across the boundaries between the time segments of different
+    wavefronts: the first, one in the middle and the last boundary."""
     from paper_2505_10168_amd import binding as B
+    g = B.stmg_pass_geometry(w.n_el, w.n_t, sweeps, fp32, fine)
+    seg = g["seg_rows"]
+    bounds = list(range(seg, w.n_t + 1, seg))
+    picks = [bounds[0], bounds[len(bounds) // 2], bounds[-1]]
+    return seg, [(max(0, k - half), min(w.n_t + 1, k + half)) for k in picks] + [(0, 2 * half)]
+
+
+@pytest.fixture(scope="module")
+def boxfilt_inputs():
     w = I.workload("boxfilt_8192x65536")
     rng = np.random.default_rng(99)
     shape = (w.n_t + 1, w.n_el + 1)
     u = rng.standard_normal(shape)
     b = rng.standard_normal(shape)
-    s = B.Solver(B.Problem(w.n_el, w.n_t, k_ins=w.kappa_min), to_dev(w.rho, cuda), nu=2)
-    ud = to_dev(u, cuda)
-    B.stmg_level_smooth(s.handle, 0, 0, 2, to_dev(b, cuda), ud)
-    torch.cuda.synchronize()
+    z = rng.standard_normal((w.n_t + 1, w.n_el // 2 + 1))
+    return w, u, b, z
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_boxfilt_8192x65536_level_passes_across_segments(precision, boxfilt_inputs, cuda):
+    """Configuration 3 at full size (5.4e8 DOFs): the fine level's two-step smoothing
+    pass, the pre-smoothing pass with its residual and x restriction, and the
+    prolongation + post-smoothing pass, from seeded random u, b and z, compared with the
+    oracle on windows of time levels that straddle the boundaries between wavefronts'
+    time segments (the segment length comes from the kernels' launch geometry), in
+    FP64 (1e-13) and with the FP32 kernels of a mixed handle (1e-6, as for the small
+    grids)."""
+    import torch
+
+    from paper_2505_10168_amd import binding as B
+    w, u, b, z = boxfilt_inputs
+    fp32 = precision == "fp32"
+    tol = 1e-6 if fp32 else 1e-13
+    opts = dict(precision=B.STMG_MIXED) if fp32 else {}
+    s = B.Solver(B.Problem(w.n_el, w.n_t, k_ins=w.kappa_min), to_dev(w.rho, cuda), nu=2,
+                 debug_poison=1, **opts)
+    assert s.info()["path"].startswith("x")
     S = 2
-    for r0 in (0, 33000, 65537 - 40):
-        r1 = r0 + 40
+    bd = to_dev(b, cuda)
+    seg, wins = segment_windows(w, S, fp32, True)
+    print(f"{precision}: segments of {seg} time levels; windows {wins}", flush=True)
+    # smoothing alone
+    ud = to_dev(u, cuda)
+    B.stmg_level_smooth(s.handle, 0, 0, S, bd, ud)
+    sm = to_np(ud)
+    # pre-smoothing with the residual restricted to the x-coarsened level
+    ud = to_dev(u, cuda)
+    bc = torch.empty((w.n_t + 1, w.n_el // 2 + 1), dtype=torch.float64, device=cuda)
+    B.stmg_level_presmooth_restrict(s.handle, 0, 0, S, bd, ud, bc)
+    pre, bcn = to_np(ud), to_np(bc)
+    # prolongation of z and post-smoothing
+    ud = to_dev(u, cuda)
+    B.stmg_level_prolong_postsmooth(s.handle, 0, 0, S, bd, to_dev(z, cuda), ud)
+    post = to_np(ud)
+    del ud, bc, bd
+    s.close()
+    torch.cuda.synchronize()
+    for r0, r1 in wins:
         ref = window_reference(w, S, (r0, r1), b, u)
-        got = to_np(ud[r0:r1])
         lo = 0 if r0 == 0 else S + 1
-        e = rel(got[lo:], ref[lo:])
-        print(f"rows {r0}..{r1}: rel err {e:.2e}", flush=True)
-        assert e <= 1e-13
+        e_sm, e_pre = rel(sm[r0:r1][lo:], ref[lo:]), rel(pre[r0:r1][lo:], ref[lo:])
+        sub = window_level(w, (r0, r1))
+        r = b[r0:r1] - O.apply_J(sub, ref)
+        bc_ref = O.restrict(sub, "x", r)
+        lr = 0 if r0 == 0 else S + 2
+        e_bc = rel(bcn[r0:r1][lr:], bc_ref[lr:])
+        refp = window_reference(w, S, (r0, r1), b, u, z_full=z)
+        e_post = rel(post[r0:r1][lo:], refp[lo:])
+        print(f"rows {r0}..{r1}: smooth {e_sm:.1e} pre {e_pre:.1e} restrict {e_bc:.1e} "
+              f"post {e_post:.1e}", flush=True)
+        assert max(e_sm, e_pre, e_bc, e_post) <= tol
+
+
+def test_boxfilt_8192x65536_solutions_against_direct_solve(cuda):
+    """Configuration 3 solved to the 1e-10 relative residual in FP64 and in mixed
+    precision, each compared element by element with the oracle's direct solve
+    (backward-Euler time stepping of Section 2.2) on the same input; the errors are
+    printed and bounded by 1e-8 of max|u| (the bound of configuration 2)."""
+    import torch
+
+    from paper_2505_10168_amd import binding as B
+    w = I.workload("boxfilt_8192x65536")
+    prob = B.Problem(w.n_el, w.n_t, k_ins=w.kappa_min)
+    got = {}
+    for name, prec in (("fp64", B.STMG_FP64), ("mixed", B.STMG_MIXED)):
+        s = B.Solver(prob, to_dev(w.rho, cuda), nu=2, precision=prec)
+        out = torch.full(s.shape, float("nan"), dtype=torch.float64, device=cuda)
+        u, st = s.solve_forward(out=out)
+        assert st.status == 0 and st.rel_residual < 1e-10
+        got[name] = (to_np(u), st)
+        del u, out
+        s.close()
+        torch.cuda.synchronize()
+        print(f"{name}: {st.cycles} cycles, residual {st.rel_residual:.2e}, "
+              f"{st.solve_ms:.0f} ms", flush=True)
+    mat = O.Material(w.kappa_min, 1.0, 1.0, 1.0)
+    lv = O.make_fine_level(w.rho, mat, w.n_t, w.length, w.t_final)
+    exact = O.direct_solve(lv, O.load_vector(lv, 1.0))
+    for name, (u, st) in got.items():
+        e = rel(u, exact)
+        print(f"config 3 {name}: error against the oracle's direct solve {e:.2e}", flush=True)
+        assert e <= 1e-8
 
 
 FOOTPRINT_OPTS = [
@@ -271,7 +375,7 @@ def test_footprint_bounds_the_allocation(opts, cuda):
     used = s.info()["device_bytes"]
     n = C.c_size_t()
     o = B.make_options(nu=2, **opts)
-    assert B.lib.stmg_footprint(C.byref(prob.c_struct()), C.byref(o), C.byref(n)) == 0
+    assert B.lib.stmg_footprint(C.byref(prob.c_struct()), C.byref(o), 0, C.byref(n)) == 0
     print(opts, used, n.value)
     assert used <= n.value
     s.close()

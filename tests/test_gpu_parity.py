@@ -25,6 +25,8 @@ def make_pair(name, cuda, fused=1, **extra):
     rho, n_t, kmin, c_ins, opts = CASES[name]
     opts = dict(opts, **extra)
     prob = B.Problem(len(rho), n_t, k_ins=kmin, c_ins=c_ins)
+    # debug_poison: the per-level calls fill their internal outputs with NaN first
+    opts.setdefault("debug_poison", 1)
     solver = B.Solver(prob, to_dev(rho, cuda), fused=fused, **opts)
     oopts = {k: v for k, v in opts.items()
              if k in ("nu", "max_levels", "min_coarse_dofs", "max_cycles")}
@@ -52,7 +54,7 @@ def test_apply_every_level(name, transpose, cuda):
     s, _, _, h = make_pair(name, cuda)
     for l, lev in enumerate(h.levels):
         x = np.random.default_rng(10 + l).standard_normal(lev.shape)
-        y = to_dev(np.zeros(lev.shape), cuda)
+        y = to_dev(np.full(lev.shape, np.nan), cuda)   # every entry must be written
         B.stmg_level_apply(s.handle, l, transpose, to_dev(x, cuda), y)
         ref = O.apply_J(lev, x, bool(transpose))
         assert rel(to_np(y), ref) <= 1e-14, (l, rel(to_np(y), ref))
@@ -91,7 +93,7 @@ def test_presmooth_restrict_and_prolong_postsmooth(name, transpose, fused, cuda)
         z = rng.standard_normal(cl.shape)
         # pre-smoothing and restriction (Algorithm 1)
         ud = to_dev(u, cuda)
-        bc = to_dev(np.zeros(cl.shape), cuda)
+        bc = to_dev(np.full(cl.shape, np.nan), cuda)
         B.stmg_level_presmooth_restrict(s.handle, l, transpose, nu, to_dev(b, cuda), ud, bc)
         u_ref = O.jacobi(h, l, u, b, nu, bool(transpose))
         bc_ref = O.restrict(lev, d, b - O.apply_J(lev, u_ref, bool(transpose)))
@@ -112,7 +114,7 @@ def test_coarsest_solve(name, transpose, cuda):
     s, _, _, h = make_pair(name, cuda)
     lev = h.levels[-1]
     b = np.random.default_rng(3).standard_normal(lev.shape)
-    z = to_dev(np.zeros(lev.shape), cuda)
+    z = to_dev(np.full(lev.shape, np.nan), cuda)
     B.stmg_level_coarsest_solve(s.handle, transpose, to_dev(b, cuda), z)
     ref = O.direct_solve(lev, b, bool(transpose))
     assert rel(to_np(z), ref) <= 1e-13
@@ -308,7 +310,7 @@ def test_galerkin_levels_match_oracle(name, transpose, interp, cuda):
         G = h.galerkin[l].T if transpose else h.galerkin[l]
         shape = h.levels[l].shape
         x = rng.standard_normal(shape)
-        y = to_dev(np.zeros(shape), cuda)
+        y = to_dev(np.full(shape, np.nan), cuda)
         B.stmg_level_apply(s.handle, l, transpose, to_dev(x, cuda), y)
         ref = (G @ x.ravel()).reshape(shape)
         print(f"level {l} {shape}: apply rel {rel(to_np(y), ref):.1e}")
@@ -316,7 +318,7 @@ def test_galerkin_levels_match_oracle(name, transpose, interp, cuda):
     last = info["n_levels"] - 1
     G = (h.galerkin[last].T if transpose else h.galerkin[last]).tocsc()
     b = rng.standard_normal(h.levels[last].shape)
-    z = to_dev(np.zeros(b.shape), cuda)
+    z = to_dev(np.full(b.shape, np.nan), cuda)
     B.stmg_level_coarsest_solve(s.handle, transpose, to_dev(b, cuda), z)
     ref = spla.spsolve(G, b.ravel()).reshape(b.shape)
     print(f"coarsest {b.shape}: rel {rel(to_np(z), ref):.1e}")
