@@ -1,10 +1,17 @@
 """Benchmark of the STMG hot path on one MI355X.
 
+Default workload: boxfilt_8192x65536 (8192 elements x 65536 steps, 5.4e8 space-time
+DOFs, box-filtered uniform densities, kappa_min = 1e-4), FP64, V(2,2) cycles to the
+1e-10 relative residual: the largest configuration, the one that is bound by HBM.
+
 One step = one pass of the whole path on a device-resident design field:
 re-assemble every level from rho (SIMP, Algorithm 3 decision, R-averaged coarse
 operators), forward STMG solve to the relative-residual tolerance, adjoint STMG solve,
 objective and gradient.  Reported value: DOF-updates/s = (sum over both solves of
-cycles * sum_{l < N_l} 2 nu n_l) / wall time of the K timed steps.
+cycles * sum_{l < N_l} 2 nu n_l) / wall time of the K timed steps.  Beside it: the
+mixed-precision forward solve of the same input (time to the same FP64 residual),
+the fine-level kernel's achieved bandwidth against the HBM peak, the device's streaming
+rates from plain HIP copy and triad kernels, and the CPU oracle on a bounded sample.
 
 Prints ONE JSON line (rank 0).  --gpus above 1 is rejected: the path runs on one GPU (the
 library has no multi-GPU form).
@@ -29,14 +36,20 @@ if str(ROOT) not in sys.path:
 METRIC = "STMG DOF-updates/s + % HBM roofline; p50/p99 solve latency at 1e-10 resid"
 HBM_PEAK_GBS = 8000.0
 
-# Workloads: name -> (nu, precision).  nu = 2 unless V(2,2) fails to converge within
-# the cycle cap, then the paper's default nu = 5.
+# Workloads: name -> (nu, concurrent solves by default).  nu = 2 unless V(2,2) fails
+# to converge within the cycle cap, then the paper's default nu = 5.  The forward and
+# adjoint solves of a step run concurrently where the levels are small enough for one
+# solve's latency-bound launches to leave the device idle; on the HBM-bound
+# configuration they run one after the other (each saturates HBM alone).
 WORKLOADS = {
-    "uniform_64x64": 2,
-    "block_1024x4096": 5,
-    "block_2048x8192": 5,
-    "boxfilt_8192x65536": 2,
+    "uniform_64x64": (2, True),
+    "block_1024x4096": (5, True),
+    "block_2048x8192": (5, True),
+    "boxfilt_8192x65536": (2, False),
 }
+DEFAULT_WORKLOAD = "boxfilt_8192x65536"
+# the oracle samples at most this many DOFs (the leading time steps of the workload)
+CPU_SAMPLE_DOFS = 4_300_000
 
 
 # The fine passes of every TIMED_EVERY-th V-cycle are bracketed by HIP events: enough
@@ -61,33 +74,101 @@ def measured_traffic(workload: str):
     return entry["bytes_per_launch"] if entry else None
 
 
-def copy_peak_gbs(dev, nbytes: int = 2 << 30, reps: int = 5) -> float:
-    """Device-to-device copy rate of a 2 GiB FP64 buffer, (read + write bytes) / time:
-    the streaming rate this device sustains in practice, reported beside the spec peak."""
+def stream_rates(dev, nbytes: int = 2 << 30, reps: int = 10) -> dict:
+    """Streaming rates of this device from the library's plain HIP kernels on 2 GiB FP64
+    vectors, (bytes read + written) / time: a copy (1 read, 1 write stream) and a triad
+    (2 reads, 1 write), with non-temporal stores as the fused passes use and without;
+    torch's copy_ beside them.  The practical ceiling the fine pass is compared with."""
     import torch
-    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
-    b = torch.empty_like(a)
-    for _ in range(2):
-        b.copy_(a)
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / reps
-    del a, b
+
+    from paper_2505_10168_amd import binding as B
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.full_like(a, 2.0)
+    y = torch.empty_like(a)
+    st = torch.cuda.current_stream(dev)
+    out = {}
+
+    def timed(fn, moved):
+        for _ in range(2):
+            fn()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(st)
+        for _ in range(reps):
+            fn()
+        t1.record(st)
+        torch.cuda.synchronize()
+        return moved / (t0.elapsed_time(t1) / reps * 1e-3) / 1e9
+
+    for nt in (True, False):
+        tag = "_nt" if nt else ""
+        out["copy" + tag] = timed(lambda: B.stmg_stream_calibrate(a, None, 0.0, y, nt, st),
+                                  2 * nbytes)
+        out["triad" + tag] = timed(lambda: B.stmg_stream_calibrate(a, b, 0.5, y, nt, st),
+                                   3 * nbytes)
+    out["torch_copy"] = timed(lambda: y.copy_(a), 2 * nbytes)
+    del a, b, y
     torch.cuda.empty_cache()
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return {k: round(v, 1) for k, v in out.items()}
 
 
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else float("nan")
 
 
+def cpu_model() -> str:
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(workload: str, nu: int, budget_s: float) -> dict:
-    """Time the oracle's forward V-cycles on the same input in a single-threaded child
-    process, for about budget_s seconds."""
+    """Time the oracle's forward V-cycles on the workload's input in child processes,
+    for about budget_s seconds each: once with every BLAS/OpenMP pool pinned to one
+    thread and once allowed all of the host's threads.  Workloads above CPU_SAMPLE_DOFS
+    are sampled: the same field, h and tau over the leading time steps only."""
+    w_dofs = None
+    try:
+        from paper_2505_10168_amd import inputs as I
+        w = I.workload(workload)
+        w_dofs = w.dofs
+        # a power of two of leading steps keeps the sample's time axis halvable
+        n_t = w.n_t if w.dofs <= CPU_SAMPLE_DOFS else \
+            1 << max(1, int(np.log2(CPU_SAMPLE_DOFS / (w.n_el + 1))))
+    except Exception:
+        n_t = None
+    runs = {}
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    for threads in (1, nproc):
+        runs[threads] = _cpu_run(workload, nu, budget_s, n_t, threads)
+    one = runs[1]
+    if one.get("error"):
+        return {"value": None, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+                "sample": f"failed: {one['error']}"}
+    many = runs[nproc]
+    sampled = n_t is not None and w_dofs is not None and n_t != w.n_t
+    what = (f"the first {n_t} of {w.n_t} time steps of {workload} (same field, h and tau; "
+            f"{(w.n_el + 1) * (n_t + 1):.3g} of {w_dofs:.3g} DOFs)" if sampled else workload)
+    return {
+        "value": one["dof_updates"] / one["seconds"], "unit": "DOF-updates/s", "cores": 1,
+        "kind": "oracle",
+        "sample": f"{one['cycles']} forward V-cycles (nu={nu}) of the NumPy FP64 oracle on "
+                  f"{what}, {one['seconds']:.1f} s; hierarchy setup {one['setup_s']:.1f} s "
+                  f"excluded",
+        "all_threads": {"threads_allowed": nproc,
+                        "value": (many["dof_updates"] / many["seconds"]) if not many.get("error")
+                        else None,
+                        "cycles": many.get("cycles")},
+        "nproc": nproc, "cpu_model": cpu_model(),
+        "note": "the oracle's NumPy/SciPy kernels run on one thread whatever the pool size",
+    }
+
+
+def _cpu_run(workload: str, nu: int, budget_s: float, n_t, threads: int) -> dict:
     code = f"""
 import os, sys, time, json
 sys.path.insert(0, {str(ROOT)!r})
@@ -95,8 +176,9 @@ import numpy as np
 import oracle as O
 from paper_2505_10168_amd import inputs as I
 w = I.workload({workload!r})
+n_t = {n_t!r} or w.n_t
 mat = O.Material(w.kappa_min, 1.0, 1.0, 1.0)
-lv = O.make_fine_level(w.rho, mat, w.n_t, w.length, w.t_final)
+lv = O.make_fine_level(w.rho, mat, n_t, w.length, w.t_final * n_t / w.n_t)
 t0 = time.perf_counter()
 h = O.build_hierarchy(lv, O.Options(nu={nu}))
 b = O.load_vector(lv, 1.0)
@@ -112,18 +194,16 @@ while True:
         break
 print(json.dumps({{"cycles": n, "seconds": el, "dof_updates": n * per_cycle, "setup_s": setup}}))
 """
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                         timeout=max(600, 20 * budget_s))
+    t = str(threads)
+    env = dict(os.environ, OMP_NUM_THREADS=t, OPENBLAS_NUM_THREADS=t, MKL_NUM_THREADS=t)
+    try:
+        out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                             env=env, timeout=max(600, 20 * budget_s))
+    except subprocess.TimeoutExpired:
+        return {"error": "timed out"}
     if out.returncode != 0:
-        return {"value": None, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-                "sample": f"failed: {out.stderr[-300:]}"}
-    r = json.loads(out.stdout.strip().splitlines()[-1])
-    return {"value": r["dof_updates"] / r["seconds"], "unit": "DOF-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{r['cycles']} forward V-cycles (nu={nu}) of the NumPy FP64 oracle on "
-                      f"{workload}, {r['seconds']:.1f} s, single thread; hierarchy setup "
-                      f"{r['setup_s']:.1f} s excluded"}
+        return {"error": out.stderr[-300:]}
+    return json.loads(out.stdout.strip().splitlines()[-1])
 
 
 def serving_bench(args):
@@ -260,7 +340,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="block_1024x4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--nu", type=int, default=None)
     ap.add_argument("--fused", type=int, default=1)
@@ -270,10 +350,15 @@ def main():
                     help="coarse operators: resistivity (R, default), conductivity (K) or "
                          "design-field (D) averaging, or Galerkin products (P)")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--sequential", action="store_true",
-                    help="run the forward and adjoint solves of a step one after the other "
-                         "on one handle instead of concurrently on two")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    conc = ap.add_mutually_exclusive_group()
+    conc.add_argument("--sequential", action="store_true",
+                      help="run the forward and adjoint solves of a step one after the other "
+                           "on one handle")
+    conc.add_argument("--concurrent", action="store_true",
+                      help="run them concurrently, one handle, stream and host thread each")
+    ap.add_argument("--mixed-solves", type=int, default=3,
+                    help="timed mixed-precision forward solves of the same input (0: none)")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving", type=int, default=0,
                     help="run the serving workload with this many requests instead")
@@ -304,14 +389,14 @@ def main():
 
     dev = torch.device("cuda:0")
     w = I.workload(args.workload)
-    nu = args.nu if args.nu is not None else WORKLOADS[args.workload]
+    nu_default, conc_default = WORKLOADS[args.workload]
+    nu = args.nu if args.nu is not None else nu_default
     precision = B.STMG_MIXED if args.precision == "mixed" else B.STMG_FP64
     prob = B.Problem(w.n_el, w.n_t, w.length, w.t_final, k_ins=w.kappa_min)
     rho = torch.from_numpy(w.rho).to(dev)
     # The adjoint right-hand side does not depend on u, so a step's two solves are
-    # independent: by default each runs on its own handle and stream from its own host
-    # thread, and the latency-bound coarse levels of one overlap the other's work.
-    concurrent = not (args.sequential or args.no_adjoint)
+    # independent and may run concurrently, each on its own handle, stream and thread.
+    concurrent = (args.concurrent or (conc_default and not args.sequential)) and not args.no_adjoint
     s_fwd = torch.cuda.Stream(device=dev) if concurrent else None
     s_adj = torch.cuda.Stream(device=dev) if concurrent else None
     opts = dict(nu=nu, precision=precision, fused=args.fused, time_kernels=TIMED_EVERY,
@@ -322,15 +407,16 @@ def main():
     pool = ThreadPoolExecutor(max_workers=2) if concurrent else None
     info = solver.info()
     u = solver._new()
-    lam = solver._new()
-    grad = torch.empty(w.n_el, dtype=torch.float64, device=dev)
+    lam = adj_solver._new()
+    grad = solver._new((w.n_el,))
 
     def forward():
         solver.set_design(rho)
         return solver.solve_forward(out=u)[1]
 
     def adjoint():
-        adj_solver.set_design(rho)
+        if adj_solver is not solver:
+            adj_solver.set_design(rho)
         return adj_solver.solve_adjoint(out=lam)[1]
 
     def step(record):
@@ -342,7 +428,7 @@ def main():
             if not args.no_adjoint:
                 rec["adj"] = adjoint()
         if not args.no_adjoint:
-            B.stmg_gradient(solver.handle, u, lam, grad)
+            solver.gradient(u, lam, out=grad)
         rec["theta"] = solver.objective(u)
         record.append(rec)
 
@@ -364,8 +450,41 @@ def main():
     kern_bytes = sum(s.fine_kernel_bytes for s in solves)
     launches = sum(s.fine_kernel_launches for s in solves)
     achieved = kern_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    # fine passes per solve: two per V-cycle (pre-smoothing with restriction,
+    # prolongation with post-smoothing and the norm) on the default path
+    avg_us = 1e3 * kern_ms / launches if launches else None
+    fine_share = (sum(2 * s.cycles for s in solves) * avg_us * 1e-3 / sum(lat)
+                  if avg_us and precision == B.STMG_FP64 else None)
     bad = [s.status for s in solves if s.status != 0]
-    copy_gbs = copy_peak_gbs(dev)
+
+    fwd_ms = [r["fwd"].solve_ms for r in recs]
+    mixed = None
+    if args.mixed_solves and precision == B.STMG_FP64:
+        # the same forward solve in mixed precision on the same input
+        msolver = B.Solver(prob, rho, **dict(opts, precision=B.STMG_MIXED, time_kernels=0))
+        mu = msolver._new()
+        msolver.solve_forward(out=mu)
+        mst = [msolver.solve_forward(out=mu)[1] for _ in range(args.mixed_solves)]
+        mms = [m.solve_ms for m in mst]
+        mixed = {"form": "FP32 smoothing and transfers inside FP64 defect correction, "
+                         "same input and tolerance",
+                 "solve_ms_p50": percentile(mms, 50), "solves": len(mms),
+                 "cycles": mst[-1].cycles, "rel_residual": mst[-1].rel_residual,
+                 "status": mst[-1].status,
+                 "fp64_forward_solve_ms_p50": percentile(fwd_ms, 50),
+                 "speedup_vs_fp64": percentile(fwd_ms, 50) / percentile(mms, 50),
+                 "dof_updates_per_s": mst[-1].dof_updates / (percentile(mms, 50) * 1e-3)}
+        del mu
+        msolver.close()
+    solver.close()
+    if concurrent:
+        adj_solver.close()
+        pool.shutdown()
+    del u, lam, grad
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    rates = stream_rates(dev)
+    copy_gbs = rates["copy_nt"]
 
     out = {
         "metric": METRIC,
@@ -398,10 +517,12 @@ def main():
             "fwd_rel_residual": recs[-1]["fwd"].rel_residual,
             "adj_rel_residual": recs[-1]["adj"].rel_residual if "adj" in recs[-1] else None,
             "theta": recs[-1]["theta"], "non_converged": len(bad),
+            "setup_ms": recs[-1]["fwd"].setup_ms,
         },
+        "mixed_precision": mixed,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_fused_fine (fine-level fused smoother passes)",
+            "kernel": "k_fused_fine (the fine level's fused smoothing passes)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -409,19 +530,17 @@ def main():
             "traffic": measured_traffic(args.workload) if args.precision == "fp64" else None,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "launches": launches,
-            "avg_launch_us": 1e3 * kern_ms / launches if launches else None,
+            "avg_launch_us": avg_us,
             "bytes_per_launch": kern_bytes / launches if launches else None,
+            "share_of_solve_time": fine_share,
             "timed_every_nth_cycle": TIMED_EVERY,
+            "stream_GBs": rates,
             "copy_GBs": copy_gbs,
             "copy_frac": (achieved / copy_gbs) if achieved else None,
         },
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, nu, args.cpu_budget)
-    solver.close()
-    if concurrent:
-        adj_solver.close()
-        pool.shutdown()
     print(json.dumps(out), flush=True)
 
 

@@ -295,6 +295,15 @@ int stmg_level_coarsest_solve(stmg_t h, int transpose, const double* d_b, double
  * ||J u - b|| / ||b|| after the cycle.  FP64 handles only (EUNSUPPORTED otherwise). */
 int stmg_vcycle(stmg_t h, int transpose, const double* d_b, double* d_u, double* rel_res);
 
+/* Streaming-rate calibration (a measurement aid): y = a (d_b == NULL) or y = a + s b
+ * over n FP64 values with the access pattern of the fused passes (16-byte loads and
+ * stores, non-temporal stores when nontemporal != 0).  Device pointers, 16-byte
+ * aligned, n even.  Unlike every other call this one returns as soon as the kernel is
+ * queued on `stream`, so that events around it time the kernel alone.
+ * Errors: EINVAL (null or misaligned pointer, odd n), EHIP. */
+int stmg_stream_calibrate(const double* d_a, const double* d_b, double s, double* d_y, int64_t n,
+                          int nontemporal, void* stream);
+
 /* Launch geometry of one fused streaming pass of `sweeps` Jacobi steps (0..6) on an
  * n_el x n_t level (fp32: the FP32 kernels; fine: the finest level's kernels): each
  * wavefront owns a strip of *strip_cols columns and a segment of *seg_rows time levels

@@ -91,6 +91,7 @@ def _load():
         "stmg_level_coarsest_solve": (I, [VP, I, VP, VP]),
         "stmg_vcycle": (I, [VP, I, VP, VP, P(D)]),
         "stmg_pass_geometry": (I, [I, I, I, I, I, P(I), P(I), P(I), P(I)]),
+        "stmg_stream_calibrate": (I, [VP, VP, D, VP, C.c_int64, I, VP]),
         "stmg_status_string": (C.c_char_p, [I]),
         "stmg_last_error": (C.c_char_p, []),
     }
@@ -110,7 +111,8 @@ EXPORTED = [
     "stmg_gradient_noalloc", "stmg_oc_update",
     "stmg_get_info", "stmg_destroy", "stmg_level_apply", "stmg_level_smooth",
     "stmg_level_presmooth_restrict", "stmg_level_prolong_postsmooth",
-    "stmg_level_coarsest_solve", "stmg_vcycle", "stmg_pass_geometry", "stmg_status_string",
+    "stmg_level_coarsest_solve", "stmg_vcycle", "stmg_pass_geometry", "stmg_stream_calibrate",
+    "stmg_status_string",
     "stmg_last_error",
 ]
 
@@ -254,6 +256,13 @@ def stmg_pass_geometry(n_el: int, n_t: int, sweeps: int, fp32: bool = False,
     _check(lib.stmg_pass_geometry(n_el, n_t, sweeps, int(fp32), int(fine),
                                   *[C.byref(o) for o in out]), "stmg_pass_geometry")
     return dict(zip(("strip_cols", "strips", "seg_rows", "waves"), (o.value for o in out)))
+
+
+def stmg_stream_calibrate(a, b, s: float, y, nontemporal: bool = True, stream=None) -> int:
+    """Queue y = a (b None) or y = a + s b on `stream` (default: the current stream)."""
+    return _check(lib.stmg_stream_calibrate(_ptr(a), _ptr(b), s, _ptr(y), y.numel(),
+                                            int(nontemporal), _stream_ptr(stream)),
+                  "stmg_stream_calibrate")
 
 
 # ---- convenience wrapper -------------------------------------------------------------

@@ -16,7 +16,7 @@ CSRC = PKG / "csrc"
 OUT_DIR = PKG / "_lib"
 LIB = OUT_DIR / "libstmg.so"
 SOURCES = ["kernels_basic.hip", "kernels_fused.hip", "kernels_tail.hip", "kernels_galerkin.hip",
-           "stmg_host.hip"]
+           "kernels_stream.hip", "stmg_host.hip"]
 ARCH = os.environ.get("STMG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,7 +1,7 @@
 // Setup, reference (one thread per DOF), reduction and sensitivity kernels of libstmg.
 //
 // Layout: every space-time vector of a level is time-major with a padded row pitch
-// P >= N+4 (multiple of 64 elements); entry (n, i) sits at n*P + i.  Padding
+// P >= N+4 (multiple of 32 elements); entry (n, i) sits at n*P + i.  Padding
 // columns are zero and never written.
 #include <hip/hip_runtime.h>
 #include <math.h>

@@ -1690,6 +1690,18 @@ int stmg_vcycle(stmg_t h, int transpose, const double* d_b, double* d_u, double*
     return 0;
 }
 
+int stmg_stream_calibrate(const double* d_a, const double* d_b, double s, double* d_y, int64_t n,
+                          int nontemporal, void* stream) {
+    if (!d_a || !d_y || n < 0 || (n & 1)) return fail(STMG_EINVAL, "bad argument");
+    if ((reinterpret_cast<uintptr_t>(d_a) | reinterpret_cast<uintptr_t>(d_b) |
+         reinterpret_cast<uintptr_t>(d_y)) & 15)
+        return fail(STMG_EINVAL, "vectors must be 16-byte aligned");
+    if (launch_stream(d_a, d_b, s, d_y, n, nontemporal != 0, static_cast<hipStream_t>(stream)) != 0)
+        return fail(STMG_EINVAL, "vector too long");
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
 int stmg_pass_geometry(int n_el, int n_t, int sweeps, int fp32, int fine, int* strip_cols,
                        int* strips, int* seg_rows, int* waves) {
     if (n_el < 1 || n_t < 1 || !strip_cols || !strips || !seg_rows || !waves)

@@ -200,6 +200,10 @@ struct FusedPass {
 template <typename T>
 int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T* b, T* out,
                  hipStream_t s);
+// y = a (b null) or y = a + s b over n FP64 values (n even), 16-byte accesses;
+// -1 for an odd or too large n
+int launch_stream(const double* a, const double* b, double s, double* y, int64_t n, bool nt,
+                  hipStream_t st);
 // launch geometry of a fused pass: columns per strip, strips, time levels per
 // segment, wavefronts (-1 for an unsupported sweep count)
 int fused_geometry(int N, int Nt, int sweeps, bool fp32, bool fine, int* strip_cols, int* strips,
