@@ -450,10 +450,10 @@ def main():
     kern_bytes = sum(s.fine_kernel_bytes for s in solves)
     launches = sum(s.fine_kernel_launches for s in solves)
     achieved = kern_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
-    # fine passes per solve: two per V-cycle (pre-smoothing with restriction,
-    # prolongation with post-smoothing and the norm) on the default path
+    # share of the solves' wall time spent in fine-level passes (all of them, from the
+    # average of the timed ones)
     avg_us = 1e3 * kern_ms / launches if launches else None
-    fine_share = (sum(2 * s.cycles for s in solves) * avg_us * 1e-3 / sum(lat)
+    fine_share = (sum(s.fine_passes for s in solves) * avg_us * 1e-3 / sum(lat)
                   if avg_us and precision == B.STMG_FP64 else None)
     bad = [s.status for s in solves if s.status != 0]
 

@@ -136,6 +136,7 @@ typedef struct {
     double  fine_kernel_ms;          /* time_kernels: summed time of fine fused passes */
     double  fine_kernel_bytes;       /* their algorithmic bytes                         */
     int64_t fine_kernel_launches;
+    int64_t fine_passes;             /* fused passes launched on the finest level      */
     double  setup_ms;                /* wall time of the handle's last hierarchy build or
                                         re-assembly (stmg_create / stmg_set_field)     */
     char    path[128];               /* coarsening directions, 'x' / 't' per step       */

@@ -50,7 +50,8 @@ class stmg_stats(C.Structure):
                 ("rel_residual", C.c_double), ("conv_factor", C.c_double),
                 ("solve_ms", C.c_double), ("dof_updates", C.c_double),
                 ("fine_kernel_ms", C.c_double), ("fine_kernel_bytes", C.c_double),
-                ("fine_kernel_launches", C.c_int64), ("setup_ms", C.c_double),
+                ("fine_kernel_launches", C.c_int64), ("fine_passes", C.c_int64),
+                ("setup_ms", C.c_double),
                 ("path", C.c_char * 128), ("history", C.c_double * (STMG_MAX_HISTORY + 1))]
 
 
@@ -312,6 +313,7 @@ class SolveStats:
     fine_kernel_ms: float
     fine_kernel_bytes: float
     fine_kernel_launches: int
+    fine_passes: int = 0
     setup_ms: float = 0.0
     path: str = ""
     history: list = field(default_factory=list)
@@ -321,7 +323,8 @@ class SolveStats:
         n = s.cycles
         return cls(s.status, s.cycles, s.n_levels, s.rel_residual, s.conv_factor, s.solve_ms,
                    s.dof_updates, s.fine_kernel_ms, s.fine_kernel_bytes, s.fine_kernel_launches,
-                   s.setup_ms, s.path.decode(), [s.history[i] for i in range(n + 1)])
+                   s.fine_passes, s.setup_ms, s.path.decode(),
+                   [s.history[i] for i in range(n + 1)])
 
 
 class Solver:

@@ -77,6 +77,7 @@ struct Level {
     double* b = nullptr;
     double* t = nullptr;
     double* w = nullptr;     // fine level, pipelined solves: keeps the previous iterate
+    double* v = nullptr;     // fine level, chained solves: fourth vector of the rotation
     float* u32 = nullptr;
     float* b32 = nullptr;
     float* t32 = nullptr;
@@ -181,6 +182,10 @@ struct stmg_ctx {
     hipStream_t s = nullptr;
     std::vector<Level> L;
     double* bload = nullptr;     // fine load vector b (Section 2.2)
+    double* brow = nullptr;      // uniform load: its rows 0 (zeros) and 1, the same for n >= 1
+    double* brow_adj = nullptr;  // the same scaled by dt / Theta_ref (adjoint right-hand side)
+    const double* bfine = nullptr;   // during a solve: the two rows the fine passes read
+    bool b_const = false;        // during a solve: the fine right-hand side is bfine
     double* rho = nullptr;       // current densities
     double* kp = nullptr;        // dk/drho
     double* cpd = nullptr;       // dc/drho
@@ -200,6 +205,8 @@ struct stmg_ctx {
     int tail_lds = 0;            // its dynamic LDS bytes (FP64 vectors: an upper bound)
     int norm_parts = 0;          // partial count written by the last fused norm
     double setup_ms = 0;         // wall time of the last build or re-assembly
+    double bload_norm = -1;      // ||assembled load||, computed on first use
+    int64_t fine_passes = 0;     // finest-level fused passes of the current solve
 
     ~stmg_ctx() {
         for (void* q : allocs) (void)hipFree(q);
@@ -299,7 +306,7 @@ size_t level_bytes(int N, int Nt, int precision, bool fine, bool coarsest, bool 
     if (coarsest) b += 3 * (size_t)(N + 1) * 8 + (N <= kDenseCoarsestMax ? (size_t)N * N * 8 : 0);
     if (precision == STMG_FP64 || fine) b += 3 * (size_t)E * 8;
     if (precision == STMG_MIXED) b += 3 * (size_t)E * 4;
-    if (fine && pipelined) b += (size_t)E * 8;
+    if (fine && pipelined) b += 2 * (size_t)E * 8;
     return b;
 }
 
@@ -310,6 +317,7 @@ size_t footprint_of(const stmg_problem* p, const stmg_options* o) {
     size_t total = 0;
     const int fine_parts = 1 << 20;
     total += (size_t)(T0 + 1) * pitch_for(N0) * 8;   // bload
+    total += 4 * (size_t)pitch_for(N0) * 8;            // its two rows, forward and adjoint
     total += (size_t)N0 * 8 * 4 + 64 + 4096;          // rho, kp, cpd, scalars
     total += (size_t)fine_parts * 8;
     if (o->deff_mode == 1) {
@@ -625,7 +633,10 @@ int build(stmg_ctx* h, const double* d_q) {
             CHK(h->alloc(&l.b, l.elems()));
             CHK(h->alloc(&l.t, l.elems()));
         }
-        if (fine && pipelined_options(&h->o)) CHK(h->alloc(&l.w, l.elems()));
+        if (fine && pipelined_options(&h->o)) {
+            CHK(h->alloc(&l.w, l.elems()));
+            CHK(h->alloc(&l.v, l.elems()));
+        }
         if (h->o.precision == STMG_MIXED) {
             CHK(h->alloc(&l.u32, l.elems()));
             CHK(h->alloc(&l.b32, l.elems()));
@@ -637,10 +648,21 @@ int build(stmg_ctx* h, const double* d_q) {
     Level& fl = h->L[0];
     CHK(h->alloc(&h->bload, fl.elems()));
     launch_load_vector(d_q, p.q_uniform, fl.N, fl.Nt, fl.h, h->bload, fl.P, h->s);
+    if (!d_q) {
+        // a uniform source gives the same load on every time level n >= 1 (and zeros on
+        // level 0): two rows stand for the whole vector in the fine passes
+        CHK(h->alloc(&h->brow, 2 * fl.P));
+        CHK(h->alloc(&h->brow_adj, 2 * fl.P));
+        launch_copy2d<double, double>(h->bload, fl.P, h->brow, fl.P, std::min(2, fl.Nt + 1), fl.N + 1, 1.0, h->s);
+        launch_copy2d<double, double>(h->bload, fl.P, h->brow_adj, fl.P, std::min(2, fl.Nt + 1), fl.N + 1,
+                                      fl.tau / p.theta_ref, h->s);
+    }
     HIPCHK(hipGetLastError());
     // partial-sum buffer: largest fused pass on the fine level, reductions, gradient
     int64_t need = 1024;
     for (int S = 0; S <= fused_max_sweeps(); ++S) need = std::max<int64_t>(need, fused_parts(fl.N, fl.Nt, S));
+    for (int S = 1; S <= mixed_max_sweeps(); ++S)
+        need = std::max<int64_t>(need, fused_parts(fl.N, fl.Nt, mixed_chain_sweeps(S)));
     need = std::max<int64_t>(need, (int64_t)gradient_chunks(fl.Nt) * fl.N);
     CHK(h->alloc(&h->parts, need));
     h->nparts = need;
@@ -653,13 +675,10 @@ int build(stmg_ctx* h, const double* d_q) {
 // V-cycle (Algorithm 1)
 // ------------------------------------------------------------------------------------
 
-double level_pass_bytes(const Level& l, int sizeofT, bool read_u) {
-    return (double)l.dofs() * sizeofT * (read_u ? 3.0 : 2.0);
-}
-
 // The next fine pass records its start and end in a fresh event pair (events recorded by
 // the kernel launch itself: see FusedPass::ev_start).
 void timer_begin(stmg_ctx* h, bool on, FusedPass& fp) {
+    if (fp.fine) ++h->fine_passes;
     if (!on) return;
     KernelTimer& T = h->timer;
     if (T.used == T.ev.size()) {
@@ -730,8 +749,39 @@ int stencil_smooth(stmg_ctx* h, Level& lv, int trans, bool zero_start, int nu, c
     return 0;
 }
 
+// Right-hand side a pass on level l reads: during a solve with a uniform load the
+// finest FP64 passes read its two rows (time level 0 and every later level) instead of
+// a full vector.
 template <typename T>
-int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) {
+const T* level_b(const stmg_ctx* h, Level& lv, int l, int* b_const) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (l == 0 && h->b_const) {
+            *b_const = 1;
+            return h->bfine;
+        }
+    }
+    *b_const = 0;
+    return B<T>(lv);
+}
+
+// Levels that start from zero (every coarse level, and the finest level of an FP32
+// inner cycle) can skip storing their pre-smoothed iterate: the post-smoothing pass
+// recomputes it from b in registers (the same steps, so the same bits), which saves
+// writing and reading one vector of the level per cycle.  Taken when the whole
+// recomputed chain fits one pass.
+#ifndef STMG_RECOMPUTE
+#define STMG_RECOMPUTE 1
+#endif
+template <typename T>
+bool recompute_pre(const stmg_ctx* h, int l, bool zero_start, int nu) {
+    const Level& lv = h->L[l];
+    return STMG_RECOMPUTE && h->o.fused && zero_start && !lv.sten && nu >= 1 &&
+           2 * nu <= fused_max_chain_sweeps() && !(lv.dir == 't' && h->o.interp == STMG_INTERP_B);
+}
+
+template <typename T>
+int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu,
+                        bool no_store = false) {
     Level& lv = h->L[l];
     Level& cl = h->L[l + 1];
     const auto V = view<T>(lv, h->o.omega);
@@ -750,7 +800,8 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
         return 0;
     }
     T*& u = U<T>(lv);
-    T* b = B<T>(lv);
+    int bconst = 0;
+    const T* b = level_b<T>(h, lv, l, &bconst);
     T*& t = Tt<T>(lv);
     const bool timed = l == 0 && h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
     // bilinear t transfers run as their own kernels after the fused passes
@@ -761,6 +812,7 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
         for (size_t k = 0; k < ch.size(); ++k) {
             FusedPass fp{};
             fp.trans = trans;
+            fp.b_const = bconst;
             fp.sweeps = ch[k];
             fp.zero_in = zero;
             const bool lastc = k + 1 == ch.size();
@@ -771,8 +823,12 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
             fp.Ntc = cl.Nt;
             fp.fine = l == 0;
             timer_begin(h, timed, fp);
-            launch_fused<T>(V, fp, u, b, t, h->s);
-            timer_end(h, timed, level_pass_bytes(lv, sizeof(T), !zero) + (lastc ? (double)cl.dofs() * sizeof(T) : 0.0));
+            const bool skip = no_store && lastc;
+            launch_fused<T>(V, fp, u, b, skip ? nullptr : t, h->s);
+            timer_end(h, timed, (double)lv.dofs() * sizeof(T) *
+                                    ((zero ? 0 : 1) + (bconst ? 0 : 1) + (skip ? 0 : 1)) +
+                                    (lastc ? (double)cl.dofs() * sizeof(T) : 0.0));
+            if (skip) break;
             if constexpr (std::is_same<T, double>::value) {
                 if (l == 0 && k == 0 && h->rotate_in) {
                     // keep this cycle's input: (u, t, w) <- (t, w, u)
@@ -805,12 +861,13 @@ int pre_smooth_restrict(stmg_ctx* h, int l, int trans, bool zero_start, int nu) 
 }
 
 template <typename T>
-int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
+int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm, bool recompute = false) {
     Level& lv = h->L[l];
     Level& cl = h->L[l + 1];
     const auto V = view<T>(lv, h->o.omega);
     T*& u = U<T>(lv);
-    T* b = B<T>(lv);
+    int bconst = 0;
+    const T* b = level_b<T>(h, lv, l, &bconst);
     T*& t = Tt<T>(lv);
     const T* z = U<T>(cl);
     const bool timed = l == 0 && h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
@@ -826,12 +883,34 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
         HIPCHK(hipGetLastError());
         return 0;
     }
+    if (recompute) {
+        // the pre-smoothing steps again from zero, the prolongation, the post-smoothing
+        FusedPass fp{};
+        fp.trans = trans;
+        fp.b_const = bconst;
+        fp.pre_sweeps = nu;
+        fp.sweeps = nu;
+        fp.zero_in = 1;
+        fp.prolong = lv.dir;
+        fp.z = z;
+        fp.Pz = cl.P;
+        fp.Nc = cl.N;
+        fp.Ntc = cl.Nt;
+        fp.fine = l == 0;
+        timer_begin(h, timed, fp);
+        if (launch_fused<T>(V, fp, nullptr, b, t, h->s) < 0) return fail(STMG_EINVAL, "recompute pass rejected");
+        timer_end(h, timed, (double)lv.dofs() * sizeof(T) * 2 + (double)cl.dofs() * sizeof(T));
+        std::swap(u, t);
+        HIPCHK(hipGetLastError());
+        return 0;
+    }
     if (h->o.fused) {
         if (split) launch_prolong_add<T>(lv.dir, V, z, cl.P, u, h->s, h->o.interp);
         std::vector<int> ch = chunks_of(nu);
         for (size_t k = 0; k < ch.size(); ++k) {
             FusedPass fp{};
             fp.trans = trans;
+            fp.b_const = bconst;
             fp.sweeps = ch[k];
             fp.prolong = (k == 0 && !split) ? lv.dir : 0;
             fp.z = z;
@@ -844,7 +923,8 @@ int prolong_post_smooth(stmg_ctx* h, int l, int trans, int nu, bool norm) {
             fp.fine = l == 0;
             timer_begin(h, timed, fp);
             int nw = launch_fused<T>(V, fp, u, b, t, h->s);
-            timer_end(h, timed, level_pass_bytes(lv, sizeof(T), true) + (k == 0 ? (double)cl.dofs() * sizeof(T) : 0.0));
+            timer_end(h, timed, (double)lv.dofs() * sizeof(T) * (bconst ? 2 : 3) +
+                                    (k == 0 ? (double)cl.dofs() * sizeof(T) : 0.0));
             if (lastc && norm) h->norm_parts = nw;
             std::swap(u, t);
         }
@@ -923,9 +1003,10 @@ int vcycle(stmg_ctx* h, int l, int trans, bool zero_start, bool norm) {
     if (l == last) return coarsest_solve<T>(h, l, trans);
     if (h->o.fused == 1 && l == h->tail_start && zero_start && !norm)
         return tail_vcycle<T>(h, l, trans);
-    CHK(pre_smooth_restrict<T>(h, l, trans, zero_start, h->o.nu));
+    const bool rec = recompute_pre<T>(h, l, zero_start, h->o.nu) && !norm;
+    CHK(pre_smooth_restrict<T>(h, l, trans, zero_start, h->o.nu, rec));
     CHK(vcycle<T>(h, l + 1, trans, true, false));
-    CHK(prolong_post_smooth<T>(h, l, trans, h->o.nu, norm));
+    CHK(prolong_post_smooth<T>(h, l, trans, h->o.nu, norm, rec));
     if (l == 0) ++h->vcycles;
     return 0;
 }
@@ -1081,24 +1162,149 @@ int vcycles_pipelined(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* cy
     return 0;
 }
 
-int solve_fp64(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
+// FP64 V-cycles with the finest level's post-smoothing of cycle k, the residual norm
+// of its iterate u_k and the pre-smoothing (with its restricted residual) of cycle
+// k + 1 in ONE streaming pass (a chain of 2 nu steps), so the finest level is read
+// and written once per cycle instead of twice.  The pass stores u_k (for the stopping
+// test) and the pre-smoothed iterate of cycle k + 1 in two of four rotating vectors:
+//   first pre-smoothing: u0 -> D
+//   odd k:  D -> mid B, out C      even k:  C -> mid A, out D
+// so u_k survives the speculative cycle k + 1 that runs while the host tests r_k (the
+// termination test stays one cycle behind, as in vcycles_pipelined).  Iterates are
+// those of the plain loop, bit for bit; the norm partials are summed in another order.
+#ifndef STMG_CHAINED
+#define STMG_CHAINED 1
+#endif
+bool chained_options(const stmg_ctx* h) {
+    const Level& f = h->L[0];
+    return STMG_CHAINED && h->o.fused && h->L.size() >= 2 && f.v && h->hscal_pinned && !f.sten && h->o.nu >= 1 &&
+           2 * h->o.nu <= fused_max_chain_sweeps() &&
+           !(f.dir == 't' && h->o.interp == STMG_INTERP_B);
+}
+
+int vcycles_chained(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats* st, int* cycles,
+                    double* r_out, int* code) {
     Level& f = h->L[0];
-    double nb;
-    CHK(norm64(h, f.b, f, &nb));
-    if (!(nb > 0) || !std::isfinite(nb)) return fail(STMG_EINVAL, "right-hand side is zero or not finite");
-    double r;
-    CHK(residual_norm64(h, trans, &r));
-    r /= nb;
+    Level& c = h->L[1];
+    const int nu = h->o.nu, maxc = h->o.max_cycles;
+    const auto V = view<double>(f, h->o.omega);
+    double* A = f.u;   // holds u0 (unless zero) and later u_k of even k
+    double* Bv = f.t;
+    double* Cv = f.w;
+    double* D = f.v;
+    double* in = A;
+    int nparts = 0;
+    int bconst = 0;
+    const double* bb = level_b<double>(h, f, 0, &bconst);
+    auto timed_now = [&]() { return h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0; };
+    // first pre-smoothing and restriction (from zero: u0 is not read)
+    {
+        FusedPass fp{};
+        fp.trans = trans;
+        fp.b_const = bconst;
+        fp.sweeps = nu;
+        fp.zero_in = zero_u0;
+        fp.tail = f.dir;
+        fp.bc = c.b;
+        fp.Pbc = c.P;
+        fp.Nc = c.N;
+        fp.Ntc = c.Nt;
+        fp.fine = 1;
+        const bool timed = timed_now();
+        timer_begin(h, timed, fp);
+        if (launch_fused<double>(V, fp, in, bb, D, h->s) < 0) return fail(STMG_EINVAL, "pre-smoothing pass rejected");
+        timer_end(h, timed, (double)f.dofs() * 8 * ((zero_u0 ? 1 : 2) + (bconst ? 0 : 1)) +
+                                (double)c.dofs() * 8);
+        HIPCHK(hipGetLastError());
+    }
+    double tags[2] = {0, 0};
+    double* mids[2] = {A, Bv};   // u_k of even / odd k
+    auto enqueue = [&](int k) -> int {
+        CHK(vcycle<double>(h, 1, trans, true, false));
+        const bool odd = (k & 1) != 0;
+        double* src = odd ? D : Cv;
+        double* out = odd ? Cv : D;
+        FusedPass fp{};
+        fp.trans = trans;
+        fp.b_const = bconst;
+        fp.prolong = f.dir;
+        fp.z = c.u;
+        fp.Pz = c.P;
+        fp.Nc = c.N;
+        fp.Ntc = c.Nt;
+        fp.sweeps = nu;
+        fp.mid = mids[odd ? 1 : 0];
+        fp.next_sweeps = nu;
+        fp.tail = f.dir;
+        fp.bc = c.b;
+        fp.Pbc = c.P;
+        fp.parts = h->parts;
+        fp.fine = 1;
+        const bool timed = timed_now();
+        timer_begin(h, timed, fp);
+        nparts = launch_fused<double>(V, fp, src, bb, out, h->s);
+        if (nparts < 0) return fail(STMG_EINVAL, "cycle pass rejected");
+        // read: input, b (unless constant in time), coarse correction; written: u_k,
+        // the next input, coarse b
+        timer_end(h, timed, (double)f.dofs() * 8 * (bconst ? 3 : 4) + 2.0 * (double)c.dofs() * 8);
+        HIPCHK(hipGetLastError());
+        ++h->vcycles;
+        h->norm_parts = nparts;
+        return post_norm_async(h, k & 1, &tags[k & 1]);
+    };
+    int rc = enqueue(1);
+    int cyc = 1;
+    bool stop = false;
+    double r = 0;
+    while (rc == 0) {
+        if (cyc < maxc && (rc = enqueue(cyc + 1)) != 0) break;
+        double ss = 0;
+        if ((rc = wait_norm(h, cyc & 1, tags[cyc & 1], &ss)) != 0) break;
+        r = std::sqrt(ss) / nb;
+        if (st) st->history[cyc] = r;
+        *code = classify(h->o, r, &stop);
+        if (stop || cyc == maxc) break;
+        ++cyc;
+    }
+    if (hipStreamSynchronize(h->s) != hipSuccess && rc == 0) rc = fail(STMG_EHIP, "stream synchronisation failed");
+    if (rc != 0) return rc;
+    // u_cyc is the MID output of pass cyc; keep the four vectors, with f.u on the result
+    double* res = mids[cyc & 1];
+    double* others[3];
+    int k = 0;
+    for (double* q : {A, Bv, Cv, D})
+        if (q != res) others[k++] = q;
+    f.u = res;
+    f.t = others[0];
+    f.w = others[1];
+    f.v = others[2];
+    *cycles = cyc;
+    *r_out = r;
+    return 0;
+}
+
+int solve_fp64(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats* st, int* status) {
+    Level& f = h->L[0];
+    double r = 1.0;   // ||b - J 0|| / ||b||
+    if (!zero_u0) {
+        CHK(residual_norm64(h, trans, &r));
+        r /= nb;
+    }
     if (st) st->history[0] = r;
     const double r0 = r;
     int cyc = 0, code = STMG_NOT_CONVERGED;
     bool stop = false;
     const bool timed = h->o.time_kernels != 0;
     const bool single = h->L.size() == 1;
-    if (!single && f.w && h->hscal_pinned) {
+    if (chained_options(h)) {
+        CHK(vcycles_chained(h, trans, zero_u0, nb, st, &cyc, &r, &code));
+        if (timed) collect_timer(h, st);
+    } else if (!single && f.w && h->hscal_pinned) {
+        if (zero_u0) CHK(set_u0(h, nullptr));
         CHK(vcycles_pipelined(h, trans, nb, st, &cyc, &r, &code));
         if (timed) collect_timer(h, st);
     } else {
+        if (zero_u0) CHK(set_u0(h, nullptr));
         for (cyc = 1; cyc <= h->o.max_cycles; ++cyc) {
             CHK(vcycle<double>(h, 0, trans, false, true));
             double ss;
@@ -1135,8 +1341,11 @@ int defect_step(stmg_ctx* h, int trans, double s_e, double s_f, double* norm) {
     const auto V64 = view<double>(f, h->o.omega);
     const double inv = 1.0 / s_f;
     if (h->o.fused) {
+        int bconst = 0;
+        const double* bb = level_b<double>(h, f, 0, &bconst);
         FusedPass fp{};
         fp.trans = trans;
+        fp.b_const = bconst;
         fp.sweeps = 0;
         fp.prolong = s_e != 0.0 ? 'c' : 0;   // the first step has no correction to add
         fp.tail = 'c';
@@ -1148,9 +1357,9 @@ int defect_step(stmg_ctx* h, int trans, double s_e, double s_f, double* norm) {
         fp.fine = 1;
         const bool timed = h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
         timer_begin(h, timed, fp);
-        const int nw = launch_fused<double>(V64, fp, f.u, f.b, f.t, h->s);
+        const int nw = launch_fused<double>(V64, fp, f.u, bb, f.t, h->s);
         // u, (e), b read; u, f written
-        timer_end(h, timed, (double)f.dofs() * (8 + (s_e != 0.0 ? 4 : 0) + 8 + 8 + 4));
+        timer_end(h, timed, (double)f.dofs() * (8 + (s_e != 0.0 ? 4 : 0) + (bconst ? 0 : 8) + 8 + 4));
         if (nw < 0) return fail(STMG_EINVAL, "defect-correction pass rejected");
         std::swap(f.u, f.t);
         HIPCHK(hipGetLastError());
@@ -1163,11 +1372,21 @@ int defect_step(stmg_ctx* h, int trans, double s_e, double s_f, double* norm) {
     return norm64(h, f.t, f, norm);
 }
 
-int solve_mixed(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
+// The fused mixed-precision pass of the finest level (launch_mixed) replaces, per
+// outer step, the FP32 post-smoothing pass, the FP64 defect pass and the next FP32
+// pre-smoothing pass: the FP32 correction is never stored.  Same bits as the unfused
+// loop below.
+#ifndef STMG_MIXED_FUSED
+#define STMG_MIXED_FUSED 1
+#endif
+bool mixed_fused_options(const stmg_ctx* h) {
+    const Level& f = h->L[0];
+    return STMG_MIXED_FUSED && h->o.fused && h->L.size() >= 2 && !f.sten && h->o.nu >= 1 &&
+           h->o.nu <= mixed_max_sweeps() && !(f.dir == 't' && h->o.interp == STMG_INTERP_B);
+}
+
+int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) {
     Level& f = h->L[0];
-    double nb;
-    CHK(norm64(h, f.b, f, &nb));
-    if (!(nb > 0) || !std::isfinite(nb)) return fail(STMG_EINVAL, "right-hand side is zero or not finite");
     const double sq = std::sqrt((double)f.dofs());
     double s_f = nb / sq;   // scale of the right-hand side the next step writes
     double rn;
@@ -1176,13 +1395,57 @@ int solve_mixed(stmg_ctx* h, int trans, stmg_stats* st, int* status) {
     if (st) st->history[0] = r;
     const double r0 = r;
     const bool timed = h->o.time_kernels != 0;
+    const bool fusedm = mixed_fused_options(h);
     int cyc = 0, code = STMG_NOT_CONVERGED;
     bool stop = false;
+    if (fusedm) CHK(pre_smooth_restrict<float>(h, 0, trans, true, h->o.nu, true));
     for (cyc = 1; cyc <= h->o.max_cycles; ++cyc) {
-        CHK(vcycle<float>(h, 0, trans, true, false));
         const double s_e = s_f;
         s_f = rn > 0 ? rn / sq : 1.0;
-        CHK(defect_step(h, trans, s_e, s_f, &rn));
+        if (fusedm) {
+            Level& c = h->L[1];
+            CHK(vcycle<float>(h, 1, trans, true, false));
+            int bconst = 0;
+            MixedPass mp{};
+            mp.trans = trans;
+            mp.sweeps = h->o.nu;
+            mp.prolong = f.dir;
+            mp.f = f.b32;
+            mp.z = c.u32;
+            mp.Pz = c.P;
+            mp.u = f.u;
+            mp.b = level_b<double>(h, f, 0, &bconst);
+            mp.b_const = bconst;
+            mp.u_out = f.t;
+            mp.f_out = f.t32;
+            mp.pre = 1;
+            mp.tail = f.dir;
+            mp.bc = c.b32;
+            mp.Pbc = c.P;
+            mp.Nc = c.N;
+            mp.s_e = s_e;
+            mp.inv_s = 1.0 / s_f;
+            mp.parts = h->parts;
+            const bool tk = h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
+            FusedPass ev{};
+            ev.fine = 1;
+            timer_begin(h, tk, ev);
+            mp.ev_start = ev.ev_start;
+            mp.ev_stop = ev.ev_stop;
+            const int nw = launch_mixed(view<float>(f, h->o.omega), view<double>(f, h->o.omega), mp, h->s);
+            if (nw < 0) return fail(STMG_EINVAL, "mixed pass rejected");
+            // read f, z, u, b; written u, f', bc
+            timer_end(h, tk, (double)f.dofs() * (4 + 8 + (bconst ? 0 : 8) + 8 + 4) +
+                                 2.0 * (double)c.dofs() * 4);
+            HIPCHK(hipGetLastError());
+            ++h->vcycles;
+            std::swap(f.u, f.t);
+            std::swap(f.b32, f.t32);
+            CHK(finish_norm(h, nw, &rn));
+        } else {
+            CHK(vcycle<float>(h, 0, trans, true, false));
+            CHK(defect_step(h, trans, s_e, s_f, &rn));
+        }
         r = rn / nb;
         if (timed) collect_timer(h, st);
         if (st) st->history[cyc] = r;
@@ -1212,18 +1475,43 @@ int solve(stmg_ctx* h, int trans, const double* d_rhs, const double* d_u0, doubl
         for (size_t i = 0; i + 1 < h->L.size() && i + 1 < sizeof(st->path); ++i) st->path[i] = h->L[i].dir;
     }
     h->timer.used = 0;
-    CHK(set_rhs(h, trans, d_rhs));
-    CHK(set_u0(h, d_u0));
+    h->fine_passes = 0;
+    const bool zero_u0 = d_u0 == nullptr;
+    Level& fl = h->L[0];
+    // the fused passes of the finest level read the uniform load's two rows instead of
+    // a full right-hand side; paths that read the full vector get it copied as before
+    const bool split0 = fl.dir == 't' && h->o.interp == STMG_INTERP_B;
+    h->b_const = !d_rhs && h->brow && h->o.fused && h->L.size() >= 2 && !split0 && zero_u0;
+    h->bfine = trans ? h->brow_adj : h->brow;
+    struct ResetB {
+        stmg_ctx* c;
+        ~ResetB() { c->b_const = false; }
+    } reset_b{h};
+    if (!h->b_const) CHK(set_rhs(h, trans, d_rhs));
+    if (!zero_u0) CHK(set_u0(h, d_u0));
+    Level& f0 = h->L[0];
+    double nb;
+    if (d_rhs) {
+        CHK(norm64(h, f0.b, f0, &nb));
+    } else {
+        // the assembled load is fixed for the handle: its norm is taken once
+        if (h->bload_norm < 0) CHK(norm64(h, h->bload, f0, &h->bload_norm));
+        nb = h->bload_norm * (trans ? f0.tau / h->p.theta_ref : 1.0);
+    }
+    if (!(nb > 0) || !std::isfinite(nb)) return fail(STMG_EINVAL, "right-hand side is zero or not finite");
     int status = STMG_NOT_CONVERGED;
-    if (h->o.precision == STMG_FP64)
-        CHK(solve_fp64(h, trans, st, &status));
-    else
-        CHK(solve_mixed(h, trans, st, &status));
+    if (h->o.precision == STMG_FP64) {
+        CHK(solve_fp64(h, trans, zero_u0, nb, st, &status));
+    } else {
+        if (zero_u0) CHK(set_u0(h, nullptr));
+        CHK(solve_mixed(h, trans, nb, st, &status));
+    }
     Level& f = h->L[0];
     launch_copy2d<double, double>(f.u, f.P, d_u, f.N + 1, f.Nt + 1, f.N + 1, 1.0, h->s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->s));
     if (st) {
+        st->fine_passes = h->fine_passes;
         st->status = status;
         st->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }

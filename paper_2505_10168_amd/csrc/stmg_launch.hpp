@@ -175,10 +175,20 @@ void launch_stencil_coarsest_dense(const StencilView& S, const double* inv, int 
 
 // ---- fused streaming kernels ----------------------------------------------------------
 // Pass descriptor of one fused streaming launch on a level.
+// One streaming pass: pre_sweeps Jacobi steps, the prolongation head, `sweeps` steps,
+// optionally the MID stage (iterate stored to `mid`, its residual norm into parts),
+// next_sweeps steps, the result stored to `out` (unless null), the tail.  Besides the
+// plain passes (pre_sweeps = next_sweeps = 0, no mid) two chains are instantiated, for
+// 1..3 steps: recompute (zero_in, pre_sweeps = sweeps, x/t head, no tail) and cycle
+// (FP64, mid set, sweeps = next_sweeps, x/t head, x/t tail).
 struct FusedPass {
     int trans;          // 0: J, 1: J^T (streams backwards in time)
-    int sweeps;         // Jacobi steps fused in this pass (0..fused_max_sweeps())
+    int sweeps;         // Jacobi steps after the head (0..fused_max_sweeps())
+    int pre_sweeps;     // steps before the head
+    int next_sweeps;    // steps after the MID stage
+    void* mid;          // MID output (type T), level pitch
     int zero_in;        // input u is identically zero (not read)
+    int b_const;        // b holds two rows: zeros (time level 0) and every later level
     char prolong;       // 0, 'x' or 't': add P z to the input first; 'c': u += s_old e32
     const void* z;      // coarse correction (type T), pitch Pz
     int64_t Pz;
@@ -200,6 +210,37 @@ struct FusedPass {
 template <typename T>
 int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T* b, T* out,
                  hipStream_t s);
+// The fused mixed-precision pass of the finest level: the FP32 post-smoothing of the
+// inner cycle that ends (its pre-smoothing recomputed from zero), the FP64 defect
+// correction u' = u + s_e e, r = b - J u', f' = r inv_s (FP32) with the norm partials,
+// and (pre) the FP32 pre-smoothing of the next inner cycle with its restricted residual.
+struct MixedPass {
+    int trans;
+    int sweeps;           // steps per smoothing (1..mixed_max_sweeps())
+    char prolong;         // 'x' / 't': direction of the finest coarsening
+    const float* f;
+    const float* z;
+    int64_t Pz;
+    const double* u;
+    const double* b;
+    int b_const;
+    double* u_out;
+    float* f_out;
+    int pre;              // also pre-smooth the next inner cycle and restrict
+    char tail;            // its restriction direction ('x' / 't')
+    float* bc;
+    int64_t Pbc;
+    int Nc;
+    double s_e;
+    double inv_s;
+    double* parts;
+    hipEvent_t ev_start;  // non-null: recorded at the kernel's own start and end
+    hipEvent_t ev_stop;
+};
+int launch_mixed(const LevelView<float>& L32, const LevelView<double>& L64, const MixedPass& mp,
+                 hipStream_t s);
+int mixed_chain_sweeps(int S);   // chain length the pass's geometry is sized for
+int mixed_max_sweeps();
 // y = a (b null) or y = a + s b over n FP64 values (n even), 16-byte accesses;
 // -1 for an odd or too large n
 int launch_stream(const double* a, const double* b, double s, double* y, int64_t n, bool nt,
@@ -210,6 +251,7 @@ int fused_geometry(int N, int Nt, int sweeps, bool fp32, bool fine, int* strip_c
                    int* seg_rows, int* waves);
 int fused_parts(int N, int Nt, int sweeps);
 int fused_max_sweeps();
+int fused_max_chain_sweeps();
 
 // ---- single-workgroup V-cycle tail (the smallest levels, resident in LDS) -----------
 constexpr int kTailThreads = 1024;     // one workgroup
