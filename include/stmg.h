@@ -93,7 +93,8 @@ typedef struct {
 /* Solver options.  stmg_default_options() fills: nu = 2, omega = 0.5,
  * lambda_crit = 0.25, max_levels = 0, min_coarse_dofs = 1024, M_min_elems = 0,
  * reassembly = R, deff_mode = 0, tol = 1e-10, diverge = 1e9, max_cycles = 100,
- * precision = FP64, w_diri_override = 0, fused = 1, time_kernels = 0, interp = C. */
+ * precision = FP64, w_diri_override = 0, fused = 1, time_kernels = 0, interp = C,
+ * debug_poison = 0, inner_cycles = 2. */
 typedef struct {
     int32_t nu;               /* smoothing steps before and after the coarse correction (Algorithm 1) */
     double  omega;            /* Jacobi damping (Section 3.1 uses 1/2)                       */
@@ -123,6 +124,10 @@ typedef struct {
                                     output vectors (nodes 0..N_el of every time level) with
                                     NaN before computing them, so an entry a kernel fails to
                                     write shows in the result; a testing aid, 0 by default  */
+    int32_t inner_cycles;     /* MIXED: FP32 V-cycles per FP64 defect correction (1..8).  Each
+                                    correction u += e solves J e = r approximately by that many
+                                    cycles from e = 0; the history and `cycles` count
+                                    corrections.                                              */
 } stmg_options;
 
 typedef struct {

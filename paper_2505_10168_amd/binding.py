@@ -42,7 +42,8 @@ class stmg_options(C.Structure):
                 ("M_min_elems", C.c_int32), ("reassembly", C.c_int32), ("deff_mode", C.c_int32),
                 ("tol", C.c_double), ("diverge", C.c_double), ("max_cycles", C.c_int32),
                 ("precision", C.c_int32), ("w_diri_override", C.c_double), ("fused", C.c_int32),
-                ("time_kernels", C.c_int32), ("interp", C.c_int32), ("debug_poison", C.c_int32)]
+                ("time_kernels", C.c_int32), ("interp", C.c_int32), ("debug_poison", C.c_int32),
+                ("inner_cycles", C.c_int32)]
 
 
 class stmg_stats(C.Structure):

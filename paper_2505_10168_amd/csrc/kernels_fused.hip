@@ -202,8 +202,8 @@ __device__ __forceinline__ int grid_wave() {
 // of stages applied to every row as it streams past,
 //   S1 Jacobi steps -> HEAD -> S2 steps -> [MID] -> S3 steps -> store -> [TAIL]
 // HEAD: 0 none, 1 x prolongation, 2 t prolongation, 3 defect correction u += s e.
-// MID: the iterate after S2 steps is stored to a.mid and its residual norm summed
-// (the end of one V-cycle, whose S3 steps then pre-smooth the next cycle).
+// MID: the iterate after S2 steps is stored to a.mid (unless null) and its residual
+// norm summed (the end of one V-cycle, whose S3 steps then pre-smooth the next cycle).
 // The store of the chain's result is skipped when a.out is null.
 // PF: rows in flight per wave (register prefetch ring).
 template <typename T, int TR, int S1, int HEAD, int S2, int MID, int S3, int TAIL,
@@ -377,7 +377,7 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
             }
             steps(std::integral_constant<int, S1>{}, std::integral_constant<int, S1 + S2>{});
             if constexpr (MID) {
-                if (out_row && useful && lane_in) st(a.mid + (int64_t)n * P + g, x);
+                if (a.mid != nullptr && out_row && useful && lane_in) st(a.mid + (int64_t)n * P + g, x);
                 row_step<T, K, false, DIR>(L, C, x, prev[IM], bb, rm);
 #pragma unroll
                 for (int j = 0; j < K; ++j) prev[IM][j] = x[j];
@@ -510,6 +510,7 @@ __global__ __launch_bounds__(256) void k_fused_fine(LevelView<T> L, FusedArgs<T>
 // value is computed by the operations of the separate passes, so the bits are those of
 // the unfused mixed cycle.
 struct MixedArgs {
+    const float* e;      // FROM_E: the pre-smoothed FP32 iterate of the inner cycle that ends
     const float* f;      // FP32 right-hand side of the inner cycle that ends here
     const float* z;      // FP32 coarse correction, pitch Pz
     int64_t Pz;
@@ -527,7 +528,7 @@ struct MixedArgs {
     int HL, xw, seg, nwaves;
 };
 
-template <int TR, int S, int HEAD, int PRE, int TAIL, int PF = 2>
+template <int TR, int S, int HEAD, int PRE, int TAIL, int FROM_E, int PF = 2>
 __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const LevelView<double>& L64,
                                            const MixedArgs& a, const int wave) {
     constexpr int K = 2;
@@ -571,7 +572,8 @@ __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const Le
     const int rows = Nt + 1;
     const int n0 = wt * a.seg;
     const int n1 = min(rows, n0 + a.seg);
-    constexpr int NA = 2 * S;                    // FP32 steps of the ending inner cycle
+    constexpr int NA = FROM_E ? S : 2 * S;       // FP32 steps of the ending inner cycle
+    constexpr int KH0 = FROM_E ? 0 : S;          // steps before its prolongation
     constexpr int NC = PRE ? S : 0;              // FP32 steps of the next one
     constexpr int WARM = NA + 1 + (PRE ? NC + 1 : 0);
     const int first = TR ? min(Nt, n1 - 1 + WARM) : max(0, n0 - WARM);
@@ -590,9 +592,11 @@ __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const Le
     double acc = 0.0;
 
     constexpr int KZ = HEAD == 1 ? 1 : K;
-    float rf[PF][K], rz[PF][KZ];
+    constexpr int KE = FROM_E ? K : 1;
+    float rf[PF][K], rz[PF][KZ], re[PF][KE];
     double ru[PF][K], rb[PF][K];
-    auto fetch = [&](int n, float (&ff)[K], float (&fz)[KZ], double (&fu)[K], double (&fb)[K]) {
+    auto fetch = [&](int n, float (&ff)[K], float (&fz)[KZ], float (&fe)[KE], double (&fu)[K],
+                     double (&fb)[K]) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             ff[j] = 0.0f;
@@ -600,12 +604,19 @@ __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const Le
             fb[j] = 0.0;
         }
 #pragma unroll
+        for (int j = 0; j < KE; ++j) fe[j] = 0.0f;
+#pragma unroll
         for (int j = 0; j < KZ; ++j) fz[j] = 0.0f;
         if (!lane_in) return;
         const int64_t ro = (int64_t)n * P + g;
         const float2 fv = *reinterpret_cast<const float2*>(a.f + ro);
         ff[0] = fv.x;
         ff[1] = fv.y;
+        if constexpr (FROM_E) {
+            const float2 ev = *reinterpret_cast<const float2*>(a.e + ro);
+            fe[0] = ev.x;
+            fe[1] = ev.y;
+        }
         if constexpr (HEAD == 1) {
             fz[0] = a.z[(int64_t)n * a.Pz + (g >> 1)];
         } else {
@@ -619,7 +630,7 @@ __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const Le
     auto row_of = [&](int it) { return TR ? first - it : first + it; };
 #pragma unroll
     for (int d = 0; d < PF; ++d)
-        if (d < count) fetch(row_of(d), rf[d], rz[d], ru[d], rb[d]);
+        if (d < count) fetch(row_of(d), rf[d], rz[d], re[d], ru[d], rb[d]);
 
     for (int it0 = 0; it0 < count; it0 += PF) {
 #pragma unroll
@@ -627,7 +638,7 @@ __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const Le
         const int it = it0 + d;
         if (it >= count) break;
         const int n = row_of(it);
-        float fr[K], zz[KZ];
+        float fr[K], zz[KZ], ee[KE];
         double uu[K], bb[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -637,7 +648,9 @@ __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const Le
         }
 #pragma unroll
         for (int j = 0; j < KZ; ++j) zz[j] = rz[d][j];
-        if (it + PF < count) fetch(row_of(it + PF), rf[d], rz[d], ru[d], rb[d]);
+#pragma unroll
+        for (int j = 0; j < KE; ++j) ee[j] = re[d][j];
+        if (it + PF < count) fetch(row_of(it + PF), rf[d], rz[d], re[d], ru[d], rb[d]);
         const bool out_row = (n >= n0) && (n < n1);
         const bool dir_row = (n == 0);
         const bool coupled = TR ? (n < Nt) : (n >= 2);
@@ -653,11 +666,16 @@ __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const Le
         float rc[K], fn[K];
         auto chain = [&](auto dir_tag) {
             constexpr bool DIR = decltype(dir_tag)::value;
-            // ending inner cycle: S steps from zero, prolongation, S steps
+            // ending inner cycle: S steps from zero (or its stored pre-smoothed iterate),
+            // prolongation, S steps
             float x[K] = {0.0f, 0.0f};
+            if constexpr (FROM_E) {
 #pragma unroll
-            for (int k = 0; k < NA; ++k) {
-                if (k == S) {
+                for (int j = 0; j < K; ++j) x[j] = ee[j];
+            }
+#pragma unroll
+            for (int k = 0; k <= NA; ++k) {
+                if (k == KH0) {
                     if constexpr (HEAD == 1) {
                         const float znext = shfl_dn1(zz[0]);
                         x[0] += zz[0];
@@ -669,6 +687,7 @@ __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const Le
 #pragma unroll
                     for (int j = 0; j < K; ++j) x[j] = valid[j] ? x[j] : 0.0f;
                 }
+                if (k == NA) break;
                 float y[K];
                 row_step<float, K, true, DIR>(L32, C32, x, pa[k], fr, y);
 #pragma unroll
@@ -758,10 +777,10 @@ __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const Le
     if (lane == 0) a.parts[wave] = acc;
 }
 
-template <int TR, int S, int HEAD, int PRE, int TAIL>
+template <int TR, int S, int HEAD, int PRE, int TAIL, int FROM_E>
 __global__ __launch_bounds__(256) void k_mixed_fine(LevelView<float> L32, LevelView<double> L64,
                                                     MixedArgs a) {
-    mixed_body<TR, S, HEAD, PRE, TAIL>(L32, L64, a, grid_wave());
+    mixed_body<TR, S, HEAD, PRE, TAIL, FROM_E>(L32, L64, a, grid_wave());
 }
 
 struct Geometry {
@@ -904,6 +923,28 @@ void dispatch_cycle(int S, int tail, const LevelView<double>& L, const FusedArgs
 #undef STMG_CYCLE
 }
 
+// Two V-cycles meet on a level that starts from zero: the post-smoothing of the first
+// (its pre-smoothing recomputed, the prolongation between), then the pre-smoothing of
+// the second from that iterate, which is stored, and its restricted residual.
+template <typename T, int TR>
+void dispatch_cycle_zero(int S, int tail, const LevelView<T>& L, const FusedArgs<T>& a,
+                         const LaunchCfg& lc, hipStream_t s) {
+#define STMG_CYCLE0(SS)                                                                        \
+    if (a.head == 1) {                                                                         \
+        if (tail == TAIL_RX) launch_one<T, TR, SS, 1, SS, 0, SS, TAIL_RX>(L, a, lc, s);        \
+        else launch_one<T, TR, SS, 1, SS, 0, SS, TAIL_RT>(L, a, lc, s);                        \
+    } else {                                                                                   \
+        if (tail == TAIL_RX) launch_one<T, TR, SS, 2, SS, 0, SS, TAIL_RX>(L, a, lc, s);        \
+        else launch_one<T, TR, SS, 2, SS, 0, SS, TAIL_RT>(L, a, lc, s);                        \
+    }
+    if (S == 1) {
+        STMG_CYCLE0(1)
+    } else {
+        STMG_CYCLE0(2)
+    }
+#undef STMG_CYCLE0
+}
+
 }  // namespace
 
 int fused_max_sweeps() { return kMaxFused; }
@@ -931,14 +972,19 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
     const int S1 = fp.pre_sweeps, S2 = fp.sweeps, S3 = fp.next_sweeps;
     if (S1 < 0 || S2 < 0 || S3 < 0 || S2 > kMaxFused) return -1;
     const int chain = S1 + S2 + S3;
-    const bool cyc = fp.mid != nullptr;
-    const bool recompute = S1 > 0;
-    if (cyc || recompute) {
-        // the chain passes: S1 = S2 (recompute) or S2 = S3 with MID (cycle), x / t head
+    const bool cyc = fp.mid_norm != 0;
+    const bool cyc0 = S1 > 0 && S3 > 0;    // two zero-start cycles meet (no MID)
+    const bool recompute = S1 > 0 && S3 == 0;
+    if (cyc || recompute || cyc0) {
+        // the chain passes: S1 = S2 (recompute), S2 = S3 with MID (cycle) or
+        // S1 = S2 = S3 (cycle from zero); x / t head
         if (chain > kMaxChain || (fp.prolong != 'x' && fp.prolong != 't')) return -1;
-        if (recompute && (cyc || S3 != 0 || S2 != S1 || fp.tail != 0 || !fp.zero_in)) return -1;
-        if (cyc && (S2 != S3 || S2 < 1 || (fp.tail != 'x' && fp.tail != 't') ||
+        if (recompute && (cyc || S2 != S1 || fp.tail != 0 || !fp.zero_in)) return -1;
+        if (cyc && (S1 != 0 || S2 != S3 || S2 < 1 || (fp.tail != 'x' && fp.tail != 't') ||
                     !std::is_same<T, double>::value))
+            return -1;
+        if (cyc0 && (cyc || S2 != S1 || S3 != S1 || S1 > 2 || !fp.zero_in ||
+                     (fp.tail != 'x' && fp.tail != 't')))
             return -1;
     } else if (S3 != 0) {
         return -1;
@@ -972,6 +1018,11 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
     if (recompute) {
         if (fp.trans) dispatch_recompute<T, 1>(S1, L, a, lc, s);
         else dispatch_recompute<T, 0>(S1, L, a, lc, s);
+        return G.nwaves;
+    }
+    if (cyc0) {
+        if (fp.trans) dispatch_cycle_zero<T, 1>(S1, tail, L, a, lc, s);
+        else dispatch_cycle_zero<T, 0>(S1, tail, L, a, lc, s);
         return G.nwaves;
     }
     if (cyc) {
@@ -1010,7 +1061,7 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
     return G.nwaves;
 }
 
-int mixed_chain_sweeps(int S) { return 3 * S + 2; }
+int mixed_chain_sweeps(int S, bool from_e) { return (from_e ? 2 : 3) * S + 2; }
 int mixed_max_sweeps() { return kMaxMixedSweeps; }
 
 int launch_mixed(const LevelView<float>& L32, const LevelView<double>& L64, const MixedPass& mp,
@@ -1018,8 +1069,10 @@ int launch_mixed(const LevelView<float>& L32, const LevelView<double>& L64, cons
     const int S = mp.sweeps;
     if (S < 1 || S > kMaxMixedSweeps || (mp.prolong != 'x' && mp.prolong != 't')) return -1;
     if (mp.pre && mp.tail != 'x' && mp.tail != 't') return -1;
-    const Geometry G = geometry<double>(L64.N, L64.Nt, mixed_chain_sweeps(S), true);
+    const bool from_e = mp.e != nullptr;
+    const Geometry G = geometry<double>(L64.N, L64.Nt, mixed_chain_sweeps(S, from_e), true);
     MixedArgs a;
+    a.e = mp.e;
     a.f = mp.f;
     a.z = mp.z;
     a.Pz = mp.Pz;
@@ -1042,14 +1095,19 @@ int launch_mixed(const LevelView<float>& L32, const LevelView<double>& L64, cons
     const dim3 grid(blocks), block(kWave * kWavesPerBlock);
     const int head = mp.prolong == 'x' ? 1 : 2;
     const int tail = mp.tail == 'x' ? TAIL_RX : TAIL_RT;
-#define STMG_MIXED_LAUNCH(TR_, S_, H_, P_, T_)                                                  \
+#define STMG_MIXED_LAUNCH1(TR_, S_, H_, P_, T_, E_)                                             \
     do {                                                                                       \
         if (mp.ev_start)                                                                       \
-            hipExtLaunchKernelGGL((k_mixed_fine<TR_, S_, H_, P_, T_>), grid, block, 0, s,      \
+            hipExtLaunchKernelGGL((k_mixed_fine<TR_, S_, H_, P_, T_, E_>), grid, block, 0, s,  \
                                   mp.ev_start, mp.ev_stop, 0, L32, L64, a);                     \
         else                                                                                   \
-            hipLaunchKernelGGL((k_mixed_fine<TR_, S_, H_, P_, T_>), grid, block, 0, s, L32,   \
-                               L64, a);                                                        \
+            hipLaunchKernelGGL((k_mixed_fine<TR_, S_, H_, P_, T_, E_>), grid, block, 0, s,     \
+                               L32, L64, a);                                                   \
+    } while (0)
+#define STMG_MIXED_LAUNCH(TR_, S_, H_, P_, T_)                                                  \
+    do {                                                                                       \
+        if (from_e) STMG_MIXED_LAUNCH1(TR_, S_, H_, P_, T_, 1);                                 \
+        else STMG_MIXED_LAUNCH1(TR_, S_, H_, P_, T_, 0);                                        \
     } while (0)
 #define STMG_MIXED_TAIL(TR_, S_, H_)                                                            \
     do {                                                                                       \
@@ -1072,6 +1130,7 @@ int launch_mixed(const LevelView<float>& L32, const LevelView<double>& L64, cons
 #undef STMG_MIXED_HEAD
 #undef STMG_MIXED_TAIL
 #undef STMG_MIXED_LAUNCH
+#undef STMG_MIXED_LAUNCH1
     return G.nwaves;
 }
 

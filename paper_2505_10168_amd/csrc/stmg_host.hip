@@ -271,6 +271,8 @@ int validate(const stmg_problem* p, const stmg_options* o) {
         return fail(STMG_EINVAL, "unknown interpolation");
     if (!(o->tol > 0) || !(o->diverge > 0)) return fail(STMG_EINVAL, "tol and diverge must be > 0");
     if (o->debug_poison != 0 && o->debug_poison != 1) return fail(STMG_EINVAL, "debug_poison must be 0 or 1");
+    if (o->precision == STMG_MIXED && (o->inner_cycles < 1 || o->inner_cycles > 8))
+        return fail(STMG_EINVAL, "inner_cycles must be in [1, 8]");
     if (p->field_kind == STMG_FIELD_CONDUCTIVITY &&
         (o->reassembly == STMG_REASSEMBLE_D || o->deff_mode == 1))
         return fail(STMG_EINVAL, "a conductivity field has no design densities: reassembly D and "
@@ -662,7 +664,8 @@ int build(stmg_ctx* h, const double* d_q) {
     int64_t need = 1024;
     for (int S = 0; S <= fused_max_sweeps(); ++S) need = std::max<int64_t>(need, fused_parts(fl.N, fl.Nt, S));
     for (int S = 1; S <= mixed_max_sweeps(); ++S)
-        need = std::max<int64_t>(need, fused_parts(fl.N, fl.Nt, mixed_chain_sweeps(S)));
+        for (bool e : {false, true})
+            need = std::max<int64_t>(need, fused_parts(fl.N, fl.Nt, mixed_chain_sweeps(S, e)));
     need = std::max<int64_t>(need, (int64_t)gradient_chunks(fl.Nt) * fl.N);
     CHK(h->alloc(&h->parts, need));
     h->nparts = need;
@@ -1165,20 +1168,22 @@ int vcycles_pipelined(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* cy
 // FP64 V-cycles with the finest level's post-smoothing of cycle k, the residual norm
 // of its iterate u_k and the pre-smoothing (with its restricted residual) of cycle
 // k + 1 in ONE streaming pass (a chain of 2 nu steps), so the finest level is read
-// and written once per cycle instead of twice.  The pass stores u_k (for the stopping
-// test) and the pre-smoothed iterate of cycle k + 1 in two of four rotating vectors:
-//   first pre-smoothing: u0 -> D
-//   odd k:  D -> mid B, out C      even k:  C -> mid A, out D
-// so u_k survives the speculative cycle k + 1 that runs while the host tests r_k (the
-// termination test stays one cycle behind, as in vcycles_pipelined).  Iterates are
-// those of the plain loop, bit for bit; the norm partials are summed in another order.
+// and written once per cycle instead of twice.  The termination test stays one cycle
+// behind (cycle k + 1 runs while the host tests r_k).  u_k itself is not stored: when
+// r_k stops the iteration, one post-smoothing pass recomputes it from the pass's input
+// and the coarse correction z_k, which are still intact (the inputs rotate over three
+// vectors, and the level below keeps its last two corrections in its two vectors).
+// Where z_k would not survive the speculative cycle (the level below is the coarsest
+// level, the single-workgroup tail or a Galerkin level) the pass stores u_k instead,
+// over four rotating vectors.  Iterates are those of the plain loop, bit for bit; the
+// norm partials are summed in another order.
 #ifndef STMG_CHAINED
 #define STMG_CHAINED 1
 #endif
 bool chained_options(const stmg_ctx* h) {
     const Level& f = h->L[0];
-    return STMG_CHAINED && h->o.fused && h->L.size() >= 2 && f.v && h->hscal_pinned && !f.sten && h->o.nu >= 1 &&
-           2 * h->o.nu <= fused_max_chain_sweeps() &&
+    return STMG_CHAINED && h->o.fused && h->L.size() >= 2 && f.v && h->hscal_pinned && !f.sten &&
+           h->o.nu >= 1 && 2 * h->o.nu <= fused_max_chain_sweeps() &&
            !(f.dir == 't' && h->o.interp == STMG_INTERP_B);
 }
 
@@ -1188,15 +1193,22 @@ int vcycles_chained(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats*
     Level& c = h->L[1];
     const int nu = h->o.nu, maxc = h->o.max_cycles;
     const auto V = view<double>(f, h->o.omega);
-    double* A = f.u;   // holds u0 (unless zero) and later u_k of even k
-    double* Bv = f.t;
-    double* Cv = f.w;
-    double* D = f.v;
-    double* in = A;
-    int nparts = 0;
+    // the coarse correction of cycle k survives cycle k + 1 when the level below is
+    // smoothed by one recomputing pass per cycle (it then alternates its two vectors)
+    const bool z_survives = h->L.size() > 2 && !c.sten && !(h->o.fused == 1 && h->tail_start == 1) &&
+                            recompute_pre<double>(h, 1, true, nu);
+    double* buf[4] = {f.u, f.t, f.w, f.v};
     int bconst = 0;
     const double* bb = level_b<double>(h, f, 0, &bconst);
     auto timed_now = [&]() { return h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0; };
+    // input of pass k (pre-smoothed iterate of cycle k) and its stored u_k; u0 is in
+    // buf[0] and the first pre-smoothing writes in_1:
+    //   recompute mode: in_k = buf[k % 3]; the pass writes buf[(k + 1) % 3]
+    //   store mode:     odd k: in buf[3], u_k -> buf[1], out buf[2];
+    //                   even k: in buf[2], u_k -> buf[0], out buf[3]
+    auto in_of = [&](int k) { return z_survives ? buf[k % 3] : buf[(k & 1) ? 3 : 2]; };
+    auto out_of = [&](int k) { return z_survives ? buf[(k + 1) % 3] : buf[(k & 1) ? 2 : 3]; };
+    auto mid_of = [&](int k) { return z_survives ? nullptr : buf[(k & 1) ? 1 : 0]; };
     // first pre-smoothing and restriction (from zero: u0 is not read)
     {
         FusedPass fp{};
@@ -1212,18 +1224,17 @@ int vcycles_chained(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats*
         fp.fine = 1;
         const bool timed = timed_now();
         timer_begin(h, timed, fp);
-        if (launch_fused<double>(V, fp, in, bb, D, h->s) < 0) return fail(STMG_EINVAL, "pre-smoothing pass rejected");
+        if (launch_fused<double>(V, fp, buf[0], bb, in_of(1), h->s) < 0)
+            return fail(STMG_EINVAL, "pre-smoothing pass rejected");
         timer_end(h, timed, (double)f.dofs() * 8 * ((zero_u0 ? 1 : 2) + (bconst ? 0 : 1)) +
                                 (double)c.dofs() * 8);
         HIPCHK(hipGetLastError());
     }
     double tags[2] = {0, 0};
-    double* mids[2] = {A, Bv};   // u_k of even / odd k
+    double* zs[2] = {nullptr, nullptr};   // coarse corrections of the last two cycles
     auto enqueue = [&](int k) -> int {
         CHK(vcycle<double>(h, 1, trans, true, false));
-        const bool odd = (k & 1) != 0;
-        double* src = odd ? D : Cv;
-        double* out = odd ? Cv : D;
+        zs[k & 1] = c.u;
         FusedPass fp{};
         fp.trans = trans;
         fp.b_const = bconst;
@@ -1233,7 +1244,8 @@ int vcycles_chained(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats*
         fp.Nc = c.N;
         fp.Ntc = c.Nt;
         fp.sweeps = nu;
-        fp.mid = mids[odd ? 1 : 0];
+        fp.mid = mid_of(k);
+        fp.mid_norm = 1;
         fp.next_sweeps = nu;
         fp.tail = f.dir;
         fp.bc = c.b;
@@ -1242,11 +1254,12 @@ int vcycles_chained(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats*
         fp.fine = 1;
         const bool timed = timed_now();
         timer_begin(h, timed, fp);
-        nparts = launch_fused<double>(V, fp, src, bb, out, h->s);
+        const int nparts = launch_fused<double>(V, fp, in_of(k), bb, out_of(k), h->s);
         if (nparts < 0) return fail(STMG_EINVAL, "cycle pass rejected");
-        // read: input, b (unless constant in time), coarse correction; written: u_k,
+        // read: input, b (unless constant in time), coarse correction; written: (u_k),
         // the next input, coarse b
-        timer_end(h, timed, (double)f.dofs() * 8 * (bconst ? 3 : 4) + 2.0 * (double)c.dofs() * 8);
+        timer_end(h, timed, (double)f.dofs() * 8 * (2 + (bconst ? 0 : 1) + (z_survives ? 0 : 1)) +
+                                2.0 * (double)c.dofs() * 8);
         HIPCHK(hipGetLastError());
         ++h->vcycles;
         h->norm_parts = nparts;
@@ -1266,13 +1279,31 @@ int vcycles_chained(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats*
         if (stop || cyc == maxc) break;
         ++cyc;
     }
+    if (rc == 0 && z_survives) {
+        // u_cyc: the post-smoothing of pass cyc again, from its input and z_cyc, into the
+        // vector the speculative pass cyc + 1 wrote
+        FusedPass fp{};
+        fp.trans = trans;
+        fp.b_const = bconst;
+        fp.prolong = f.dir;
+        fp.z = zs[cyc & 1];
+        fp.Pz = c.P;
+        fp.Nc = c.N;
+        fp.Ntc = c.Nt;
+        fp.sweeps = nu;
+        fp.fine = 1;
+        if (launch_fused<double>(V, fp, in_of(cyc), bb, out_of(cyc + 1), h->s) < 0)
+            rc = fail(STMG_EINVAL, "final post-smoothing pass rejected");
+        else if (hipGetLastError() != hipSuccess)
+            rc = fail(STMG_EHIP, "final post-smoothing launch failed");
+    }
     if (hipStreamSynchronize(h->s) != hipSuccess && rc == 0) rc = fail(STMG_EHIP, "stream synchronisation failed");
     if (rc != 0) return rc;
-    // u_cyc is the MID output of pass cyc; keep the four vectors, with f.u on the result
-    double* res = mids[cyc & 1];
+    // keep the four vectors, with f.u on the result
+    double* res = z_survives ? out_of(cyc + 1) : mid_of(cyc);
     double* others[3];
     int k = 0;
-    for (double* q : {A, Bv, Cv, D})
+    for (double* q : buf)
         if (q != res) others[k++] = q;
     f.u = res;
     f.t = others[0];
@@ -1372,21 +1403,31 @@ int defect_step(stmg_ctx* h, int trans, double s_e, double s_f, double* norm) {
     return norm64(h, f.t, f, norm);
 }
 
-// The fused mixed-precision pass of the finest level (launch_mixed) replaces, per
-// outer step, the FP32 post-smoothing pass, the FP64 defect pass and the next FP32
-// pre-smoothing pass: the FP32 correction is never stored.  Same bits as the unfused
-// loop below.
+// Mixed precision: FP64 defect correction around FP32 V-cycles.  Each outer step
+// applies u += s_e e (FP64), forms r = b - J u in FP64, writes the FP32 right-hand
+// side f = r / s_f of the next inner solve (s_f = RMS of the previous residual, so f
+// stays O(1) in FP32 range) and solves J e = f approximately by `inner_cycles` FP32
+// V-cycles from e = 0 (FP32 smoothers and transfers, FP64 coarsest solve).
+//
+// On the finest level with the fused kernels, one pass (launch_mixed) does the FP32
+// post-smoothing of the last inner cycle, the FP64 defect correction and the FP32
+// pre-smoothing of the next outer step's first inner cycle, so the FP32 correction is
+// stored only between inner cycles; with two inner cycles one FP32 pass joins the
+// first cycle's post-smoothing (its pre-smoothing recomputed) and the second's
+// pre-smoothing.  Same bits as the unfused loop.
 #ifndef STMG_MIXED_FUSED
 #define STMG_MIXED_FUSED 1
 #endif
 bool mixed_fused_options(const stmg_ctx* h) {
     const Level& f = h->L[0];
     return STMG_MIXED_FUSED && h->o.fused && h->L.size() >= 2 && !f.sten && h->o.nu >= 1 &&
-           h->o.nu <= mixed_max_sweeps() && !(f.dir == 't' && h->o.interp == STMG_INTERP_B);
+           h->o.nu <= mixed_max_sweeps() && h->o.inner_cycles <= 2 &&
+           !(f.dir == 't' && h->o.interp == STMG_INTERP_B);
 }
 
 int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) {
     Level& f = h->L[0];
+    const int m = h->o.inner_cycles, nu = h->o.nu;
     const double sq = std::sqrt((double)f.dofs());
     double s_f = nb / sq;   // scale of the right-hand side the next step writes
     double rn;
@@ -1398,18 +1439,49 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
     const bool fusedm = mixed_fused_options(h);
     int cyc = 0, code = STMG_NOT_CONVERGED;
     bool stop = false;
-    if (fusedm) CHK(pre_smooth_restrict<float>(h, 0, trans, true, h->o.nu, true));
+    auto timed_now = [&]() { return h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0; };
+    if (fusedm) CHK(pre_smooth_restrict<float>(h, 0, trans, true, nu, true));
     for (cyc = 1; cyc <= h->o.max_cycles; ++cyc) {
         const double s_e = s_f;
         s_f = rn > 0 ? rn / sq : 1.0;
         if (fusedm) {
             Level& c = h->L[1];
+            const float* e_in = nullptr;
+            if (m == 2) {
+                // inner cycle 1 ends, inner cycle 2 starts from its iterate
+                CHK(vcycle<float>(h, 1, trans, true, false));
+                FusedPass fp{};
+                fp.trans = trans;
+                fp.pre_sweeps = nu;
+                fp.sweeps = nu;
+                fp.next_sweeps = nu;
+                fp.zero_in = 1;
+                fp.prolong = f.dir;
+                fp.z = c.u32;
+                fp.Pz = c.P;
+                fp.Nc = c.N;
+                fp.Ntc = c.Nt;
+                fp.tail = f.dir;
+                fp.bc = c.b32;
+                fp.Pbc = c.P;
+                fp.fine = 1;
+                const bool tk = timed_now();
+                timer_begin(h, tk, fp);
+                if (launch_fused<float>(view<float>(f, h->o.omega), fp, nullptr, f.b32, f.u32, h->s) < 0)
+                    return fail(STMG_EINVAL, "inner cycle pass rejected");
+                // read f, z; written e, coarse b
+                timer_end(h, tk, (double)f.dofs() * 8 + 2.0 * (double)c.dofs() * 4);
+                HIPCHK(hipGetLastError());
+                ++h->vcycles;
+                e_in = f.u32;
+            }
             CHK(vcycle<float>(h, 1, trans, true, false));
             int bconst = 0;
             MixedPass mp{};
             mp.trans = trans;
-            mp.sweeps = h->o.nu;
+            mp.sweeps = nu;
             mp.prolong = f.dir;
+            mp.e = e_in;
             mp.f = f.b32;
             mp.z = c.u32;
             mp.Pz = c.P;
@@ -1426,7 +1498,7 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
             mp.s_e = s_e;
             mp.inv_s = 1.0 / s_f;
             mp.parts = h->parts;
-            const bool tk = h->o.time_kernels > 0 && h->vcycles % h->o.time_kernels == 0;
+            const bool tk = timed_now();
             FusedPass ev{};
             ev.fine = 1;
             timer_begin(h, tk, ev);
@@ -1434,8 +1506,8 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
             mp.ev_stop = ev.ev_stop;
             const int nw = launch_mixed(view<float>(f, h->o.omega), view<double>(f, h->o.omega), mp, h->s);
             if (nw < 0) return fail(STMG_EINVAL, "mixed pass rejected");
-            // read f, z, u, b; written u, f', bc
-            timer_end(h, tk, (double)f.dofs() * (4 + 8 + (bconst ? 0 : 8) + 8 + 4) +
+            // read (e), f, z, u, b; written u, f', bc
+            timer_end(h, tk, (double)f.dofs() * ((e_in ? 4 : 0) + 4 + 8 + (bconst ? 0 : 8) + 8 + 4) +
                                  2.0 * (double)c.dofs() * 4);
             HIPCHK(hipGetLastError());
             ++h->vcycles;
@@ -1443,7 +1515,7 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
             std::swap(f.b32, f.t32);
             CHK(finish_norm(h, nw, &rn));
         } else {
-            CHK(vcycle<float>(h, 0, trans, true, false));
+            for (int i = 0; i < m; ++i) CHK(vcycle<float>(h, 0, trans, i == 0, false));
             CHK(defect_step(h, trans, s_e, s_f, &rn));
         }
         r = rn / nb;
@@ -1457,7 +1529,7 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
         st->cycles = cyc;
         st->rel_residual = r;
         st->conv_factor = (r0 > 0 && cyc > 0) ? std::pow(r / r0, 1.0 / cyc) : NAN;
-        st->dof_updates = cyc * cycle_dof_updates(h);
+        st->dof_updates = (double)cyc * m * cycle_dof_updates(h);
     }
     *status = code;
     return 0;
@@ -1717,6 +1789,8 @@ int stmg_default_options(stmg_options* o) {
     o->fused = 1;
     o->time_kernels = 0;
     o->interp = STMG_INTERP_C;
+    o->debug_poison = 0;
+    o->inner_cycles = 2;
     return 0;
 }
 

@@ -178,15 +178,16 @@ void launch_stencil_coarsest_dense(const StencilView& S, const double* inv, int 
 // One streaming pass: pre_sweeps Jacobi steps, the prolongation head, `sweeps` steps,
 // optionally the MID stage (iterate stored to `mid`, its residual norm into parts),
 // next_sweeps steps, the result stored to `out` (unless null), the tail.  Besides the
-// plain passes (pre_sweeps = next_sweeps = 0, no mid) two chains are instantiated, for
+// plain passes (pre_sweeps = next_sweeps = 0, no MID) two chains are instantiated, for
 // 1..3 steps: recompute (zero_in, pre_sweeps = sweeps, x/t head, no tail) and cycle
-// (FP64, mid set, sweeps = next_sweeps, x/t head, x/t tail).
+// (FP64, mid_norm, sweeps = next_sweeps, x/t head, x/t tail).
 struct FusedPass {
     int trans;          // 0: J, 1: J^T (streams backwards in time)
     int sweeps;         // Jacobi steps after the head (0..fused_max_sweeps())
     int pre_sweeps;     // steps before the head
     int next_sweeps;    // steps after the MID stage
-    void* mid;          // MID output (type T), level pitch
+    int mid_norm;       // MID stage: residual norm of the iterate after `sweeps` steps
+    void* mid;          // and that iterate stored here (type T, level pitch) unless null
     int zero_in;        // input u is identically zero (not read)
     int b_const;        // b holds two rows: zeros (time level 0) and every later level
     char prolong;       // 0, 'x' or 't': add P z to the input first; 'c': u += s_old e32
@@ -218,6 +219,8 @@ struct MixedPass {
     int trans;
     int sweeps;           // steps per smoothing (1..mixed_max_sweeps())
     char prolong;         // 'x' / 't': direction of the finest coarsening
+    const float* e;       // non-null: the ending inner cycle's stored pre-smoothed iterate
+                          // (it started from a previous one); null: from zero, recomputed
     const float* f;
     const float* z;
     int64_t Pz;
@@ -239,7 +242,7 @@ struct MixedPass {
 };
 int launch_mixed(const LevelView<float>& L32, const LevelView<double>& L64, const MixedPass& mp,
                  hipStream_t s);
-int mixed_chain_sweeps(int S);   // chain length the pass's geometry is sized for
+int mixed_chain_sweeps(int S, bool from_e);   // chain length the pass's geometry is sized for
 int mixed_max_sweeps();
 // y = a (b null) or y = a + s b over n FP64 values (n even), 16-byte accesses;
 // -1 for an odd or too large n
