@@ -522,7 +522,9 @@ def main():
         "mixed_precision": mixed,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_fused_fine (the fine level's fused smoothing passes)",
+            "kernel": ("k_fused_fine<double, TR, 0, 1, 2, 1, 2, 1> (the finest level's "
+                       "cross-cycle pass)" if args.workload == "boxfilt_8192x65536" and nu == 2
+                       else "k_fused_fine (the finest level's fused passes)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -345,6 +345,7 @@ class Solver:
         self.options = make_options(**options)
         self.device = rho.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._event = torch.cuda.Event()      # reused: recorded, then waited on at once
         self._order()
         self.handle = stmg_create(problem.c_struct(), self.options, rho, q, self.stream)
 
@@ -352,7 +353,8 @@ class Solver:
         """Make the handle's stream wait for the caller's current stream."""
         cur = self._torch.cuda.current_stream(self.device)
         if cur != self.stream:
-            self.stream.wait_stream(cur)
+            self._event.record(cur)
+            self.stream.wait_event(self._event)
 
     def close(self):
         if getattr(self, "handle", None):

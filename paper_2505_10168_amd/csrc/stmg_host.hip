@@ -1222,12 +1222,10 @@ int vcycles_chained(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats*
         fp.Nc = c.N;
         fp.Ntc = c.Nt;
         fp.fine = 1;
-        const bool timed = timed_now();
-        timer_begin(h, timed, fp);
+        // the event timer samples the cross-cycle passes only (one kernel, one byte count)
+        timer_begin(h, false, fp);
         if (launch_fused<double>(V, fp, buf[0], bb, in_of(1), h->s) < 0)
             return fail(STMG_EINVAL, "pre-smoothing pass rejected");
-        timer_end(h, timed, (double)f.dofs() * 8 * ((zero_u0 ? 1 : 2) + (bconst ? 0 : 1)) +
-                                (double)c.dofs() * 8);
         HIPCHK(hipGetLastError());
     }
     double tags[2] = {0, 0};
