@@ -48,8 +48,10 @@ def test_mixed_precision_tracks_fp64(name, transpose, fused, inner, cuda):
 @pytest.mark.parametrize("name", ["uniform_64x64", "block_256x600"])
 @pytest.mark.parametrize("transpose", [0, 1])
 def test_mixed_tail_is_bit_identical(name, transpose, cuda):
-    """The FP32 V-cycle through the single-workgroup tail (fused = 1) and through
-    streaming launches on every level (fused = 2) give the same bits."""
+    """The mixed solve through the single-workgroup tail (fused = 1) and through
+    streaming launches on every level (fused = 2) gives the same bits.  (The reference
+    path, fused = 0, sums the residual norms in another order, so its scales of the FP32
+    right-hand sides, and with them the FP32 roundings, differ in the last bits.)"""
     from paper_2505_10168_amd import binding as B
     outs = []
     for fused in (1, 2):
@@ -57,7 +59,8 @@ def test_mixed_tail_is_bit_identical(name, transpose, cuda):
         assert (s.info()["tail_level"] > 0) == (fused == 1)
         u, st = (s.solve_adjoint if transpose else s.solve_forward)()
         outs.append((to_np(u), st.history))
-    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    for o in outs[1:]:
+        assert np.array_equal(outs[0][0], o[0]) and outs[0][1] == o[1]
 
 
 @pytest.mark.parametrize("name", list(CASES))
