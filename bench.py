@@ -368,6 +368,8 @@ def main():
                     help="run the Section 7 design loop on an N x N grid instead")
     ap.add_argument("--design-cycles", type=int, default=200)
     ap.add_argument("--cold", action="store_true", help="design loop with cold restarts")
+    ap.add_argument("--no-levels", action="store_true",
+                    help="skip the level-by-level timing of one forward solve")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -476,6 +478,19 @@ def main():
                  "dof_updates_per_s": mst[-1].dof_updates / (percentile(mms, 50) * 1e-3)}
         del mu
         msolver.close()
+    levels = None
+    if not args.no_levels:
+        # one more forward solve (outside the timed steps) with events at every level
+        # boundary of every cycle: where a cycle's device time goes
+        lsolver = B.Solver(prob, rho, **dict(opts, time_kernels=0, time_levels=1))
+        _, lst = lsolver.solve_forward(out=u)
+        li = lsolver.info()
+        levels = {"ms_per_cycle": [round(x, 5) for x in lst.level_ms],
+                  "n_el": li["n_el"], "n_t": li["n_t"], "tail_level": li["tail_level"],
+                  "cycles_timed": lst.level_cycles,
+                  "sum_ms_per_cycle": sum(lst.level_ms),
+                  "solve_ms_per_cycle": lst.solve_ms / max(lst.cycles, 1)}
+        lsolver.close()
     solver.close()
     if concurrent:
         adj_solver.close()
@@ -520,6 +535,7 @@ def main():
             "setup_ms": recs[-1]["fwd"].setup_ms,
         },
         "mixed_precision": mixed,
+        "level_breakdown": levels,
         "roofline": {
             "bound": "hbm",
             "kernel": ("k_fused_fine<double, TR, 0, 1, 2, 1, 2, 1> (the finest level's "

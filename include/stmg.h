@@ -94,7 +94,7 @@ typedef struct {
  * lambda_crit = 0.25, max_levels = 0, min_coarse_dofs = 1024, M_min_elems = 0,
  * reassembly = R, deff_mode = 0, tol = 1e-10, diverge = 1e9, max_cycles = 100,
  * precision = FP64, w_diri_override = 0, fused = 1, time_kernels = 0, interp = C,
- * debug_poison = 0, inner_cycles = 2. */
+ * debug_poison = 0, inner_cycles = 2, time_levels = 0. */
 typedef struct {
     int32_t nu;               /* smoothing steps before and after the coarse correction (Algorithm 1) */
     double  omega;            /* Jacobi damping (Section 3.1 uses 1/2)                       */
@@ -128,6 +128,11 @@ typedef struct {
                                     correction u += e solves J e = r approximately by that many
                                     cycles from e = 0; the history and `cycles` count
                                     corrections.                                              */
+    int32_t time_levels;      /* k > 0: time every k-th cycle of a solve (the first included)
+                                    level by level with HIP events recorded on the stream at
+                                    the level boundaries; the means land in
+                                    stmg_stats.level_ms.  The events sit between the passes,
+                                    so they add a little to the solve time; 0: off          */
 } stmg_options;
 
 typedef struct {
@@ -145,6 +150,17 @@ typedef struct {
     double  setup_ms;                /* wall time of the handle's last hierarchy build or
                                         re-assembly (stmg_create / stmg_set_field)     */
     char    path[128];               /* coarsening directions, 'x' / 't' per step       */
+    int32_t level_cycles;            /* time_levels: cycles that were timed level by level */
+    double  level_ms[64];            /* time_levels: mean device ms per cycle (V-cycle, or
+                                        outer correction of MIXED with all its inner
+                                        cycles) spent on level l: its smoothing passes,
+                                        transfers and norms; on the last level the
+                                        coarsest solve; with fused = 1 the
+                                        single-workgroup tail counts on its first level
+                                        (stmg_info.tail_level).  Finest level of the
+                                        cross-cycle form: one pass per cycle, the
+                                        post-smoothing of this cycle with the
+                                        pre-smoothing of the next.                      */
     double  history[STMG_MAX_HISTORY + 1];   /* r_0 .. r_cycles                       */
 } stmg_stats;
 

@@ -43,7 +43,7 @@ class stmg_options(C.Structure):
                 ("tol", C.c_double), ("diverge", C.c_double), ("max_cycles", C.c_int32),
                 ("precision", C.c_int32), ("w_diri_override", C.c_double), ("fused", C.c_int32),
                 ("time_kernels", C.c_int32), ("interp", C.c_int32), ("debug_poison", C.c_int32),
-                ("inner_cycles", C.c_int32)]
+                ("inner_cycles", C.c_int32), ("time_levels", C.c_int32)]
 
 
 class stmg_stats(C.Structure):
@@ -53,7 +53,9 @@ class stmg_stats(C.Structure):
                 ("fine_kernel_ms", C.c_double), ("fine_kernel_bytes", C.c_double),
                 ("fine_kernel_launches", C.c_int64), ("fine_passes", C.c_int64),
                 ("setup_ms", C.c_double),
-                ("path", C.c_char * 128), ("history", C.c_double * (STMG_MAX_HISTORY + 1))]
+                ("path", C.c_char * 128), ("level_cycles", C.c_int32),
+                ("level_ms", C.c_double * 64),
+                ("history", C.c_double * (STMG_MAX_HISTORY + 1))]
 
 
 class stmg_info(C.Structure):
@@ -318,6 +320,8 @@ class SolveStats:
     setup_ms: float = 0.0
     path: str = ""
     history: list = field(default_factory=list)
+    level_cycles: int = 0
+    level_ms: list = field(default_factory=list)   # per level, time_levels > 0
 
     @classmethod
     def from_c(cls, s: stmg_stats) -> "SolveStats":
@@ -325,7 +329,8 @@ class SolveStats:
         return cls(s.status, s.cycles, s.n_levels, s.rel_residual, s.conv_factor, s.solve_ms,
                    s.dof_updates, s.fine_kernel_ms, s.fine_kernel_bytes, s.fine_kernel_launches,
                    s.fine_passes, s.setup_ms, s.path.decode(),
-                   [s.history[i] for i in range(n + 1)])
+                   [s.history[i] for i in range(n + 1)], s.level_cycles,
+                   [s.level_ms[i] for i in range(s.n_levels)] if s.level_cycles else [])
 
 
 class Solver:

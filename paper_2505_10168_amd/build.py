@@ -53,8 +53,10 @@ def build(verbose: bool = True) -> Path:
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), 4)) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
     tmp = LIB.with_suffix(".so.tmp")
+    # roctx: the solver's marker ranges (collected by rocprofv3 --marker-trace)
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp),
-           *map(str, objs)]
+           *map(str, objs), "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib",
+           "-lrocprofiler-sdk-roctx"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

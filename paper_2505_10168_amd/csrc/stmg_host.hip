@@ -16,6 +16,8 @@
 #include <mutex>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "stmg.h"
 #include "stmg_launch.hpp"
 
@@ -174,6 +176,40 @@ struct KernelTimer {
     size_t used = 0;
 };
 
+// Level-by-level device time of the sampled cycles: an event is recorded on the stream
+// at every level boundary, tagged with the level whose work follows it (-1: none, the
+// end of a cycle); the interval up to the next event belongs to that level.
+struct LevelTimer {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> tag;
+    size_t used = 0;
+    bool on = false;       // the current cycle is sampled
+    int64_t seen = 0;      // cycles started in this solve
+    int cycles = 0;        // of them sampled
+};
+
+// roctx range names, one pair per level ("stmg L3 pre", "stmg L3 post")
+const char* level_range(int l, bool post) {
+    static const auto names = [] {
+        std::vector<std::string> v;
+        for (int i = 0; i < 64; ++i) {
+            v.push_back("stmg L" + std::to_string(i) + " pre");
+            v.push_back("stmg L" + std::to_string(i) + " post");
+        }
+        return v;
+    }();
+    if (l < 0 || l >= 64) return "stmg level";
+    return names[2 * l + (post ? 1 : 0)].c_str();
+}
+
+// a roctx range over a scope (a no-op unless a profiler collects markers)
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+
 }  // namespace
 
 struct stmg_ctx {
@@ -199,6 +235,7 @@ struct stmg_ctx {
     std::vector<void*> allocs;
     size_t bytes = 0;
     KernelTimer timer;
+    LevelTimer lt;
     int tail_start = -1;         // first level of the single-workgroup tail (-1: none)
     bool rotate_in = false;      // the next fine pass keeps its input in L[0].w
     uint64_t vcycles = 0;        // fine-level V-cycles started (sampled kernel timing)
@@ -216,6 +253,7 @@ struct stmg_ctx {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
+        for (hipEvent_t e : lt.ev) (void)hipEventDestroy(e);
     }
 
     template <typename T>
@@ -273,6 +311,7 @@ int validate(const stmg_problem* p, const stmg_options* o) {
     if (o->debug_poison != 0 && o->debug_poison != 1) return fail(STMG_EINVAL, "debug_poison must be 0 or 1");
     if (o->precision == STMG_MIXED && (o->inner_cycles < 1 || o->inner_cycles > 8))
         return fail(STMG_EINVAL, "inner_cycles must be in [1, 8]");
+    if (o->time_levels < 0) return fail(STMG_EINVAL, "time_levels must be >= 0");
     if (p->field_kind == STMG_FIELD_CONDUCTIVITY &&
         (o->reassembly == STMG_REASSEMBLE_D || o->deff_mode == 1))
         return fail(STMG_EINVAL, "a conductivity field has no design densities: reassembly D and "
@@ -702,6 +741,72 @@ void timer_end(stmg_ctx* h, bool on, double bytes) {
     ++T.used;
 }
 
+// The work enqueued from here to the next mark belongs to level l (-1: to no level).
+void level_mark(stmg_ctx* h, int l) {
+    LevelTimer& T = h->lt;
+    if (!T.on) return;
+    if (T.used == T.ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            T.on = false;   // no timing rather than a failed solve
+            return;
+        }
+        T.ev.push_back(e);
+        T.tag.push_back(0);
+    }
+    if (hipEventRecord(T.ev[T.used], h->s) != hipSuccess) {
+        (void)hipGetLastError();
+        T.on = false;
+        return;
+    }
+    T.tag[T.used++] = l;
+}
+
+// One cycle of a solve loop (a V-cycle, or an outer correction of the mixed form):
+// a roctx range, and the level marks when the cycle is sampled.
+void cycle_begin(stmg_ctx* h) {
+    roctxRangePushA("stmg cycle");
+    LevelTimer& T = h->lt;
+    T.on = h->o.time_levels > 0 && T.seen++ % h->o.time_levels == 0;
+    if (T.on) ++T.cycles;
+}
+
+void cycle_end(stmg_ctx* h) {
+    level_mark(h, -1);
+    h->lt.on = false;
+    roctxRangePop();
+}
+
+struct CycleScope {
+    stmg_ctx* h;
+    explicit CycleScope(stmg_ctx* c) : h(c) { cycle_begin(h); }
+    ~CycleScope() { cycle_end(h); }
+    CycleScope(const CycleScope&) = delete;
+    CycleScope& operator=(const CycleScope&) = delete;
+};
+
+// After the stream has drained: the marked intervals summed per level, as the mean
+// per sampled cycle.
+void collect_levels(stmg_ctx* h, stmg_stats* st) {
+    LevelTimer& T = h->lt;
+    if (st && T.cycles > 0) {
+        double acc[64] = {0};
+        for (size_t i = 0; i + 1 < T.used; ++i) {
+            if (T.tag[i] < 0 || T.tag[i] >= 64) continue;
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, T.ev[i], T.ev[i + 1]) == hipSuccess) acc[T.tag[i]] += ms;
+            else (void)hipGetLastError();
+        }
+        st->level_cycles = T.cycles;
+        for (int l = 0; l < 64; ++l) st->level_ms[l] = acc[l] / T.cycles;
+    }
+    T.used = 0;
+    T.on = false;
+    T.seen = 0;
+    T.cycles = 0;
+}
+
 // Sweep chunk sizes for nu steps: the fewest fused passes, of near-equal size.
 std::vector<int> chunks_of(int nu) {
     const int m = fused_max_sweeps();
@@ -1003,13 +1108,26 @@ int tail_vcycle(stmg_ctx* h, int l, int trans) {
 template <typename T>
 int vcycle(stmg_ctx* h, int l, int trans, bool zero_start, bool norm) {
     const int last = (int)h->L.size() - 1;
-    if (l == last) return coarsest_solve<T>(h, l, trans);
-    if (h->o.fused == 1 && l == h->tail_start && zero_start && !norm)
+    level_mark(h, l);
+    if (l == last) {
+        Range r(level_range(l, false));
+        return coarsest_solve<T>(h, l, trans);
+    }
+    if (h->o.fused == 1 && l == h->tail_start && zero_start && !norm) {
+        Range r(level_range(l, false));
         return tail_vcycle<T>(h, l, trans);
+    }
     const bool rec = recompute_pre<T>(h, l, zero_start, h->o.nu) && !norm;
-    CHK(pre_smooth_restrict<T>(h, l, trans, zero_start, h->o.nu, rec));
+    {
+        Range r(level_range(l, false));
+        CHK(pre_smooth_restrict<T>(h, l, trans, zero_start, h->o.nu, rec));
+    }
     CHK(vcycle<T>(h, l + 1, trans, true, false));
-    CHK(prolong_post_smooth<T>(h, l, trans, h->o.nu, norm, rec));
+    level_mark(h, l);
+    {
+        Range r(level_range(l, true));
+        CHK(prolong_post_smooth<T>(h, l, trans, h->o.nu, norm, rec));
+    }
     if (l == 0) ++h->vcycles;
     return 0;
 }
@@ -1137,7 +1255,10 @@ int vcycles_pipelined(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* cy
     const int maxc = h->o.max_cycles;
     double tags[2] = {0, 0};
     auto enqueue = [&](int k) -> int {
-        CHK(vcycle<double>(h, 0, trans, false, true));
+        {
+            CycleScope cs(h);
+            CHK(vcycle<double>(h, 0, trans, false, true));
+        }
         return post_norm_async(h, k & 1, &tags[k & 1]);
     };
     h->rotate_in = true;
@@ -1231,8 +1352,11 @@ int vcycles_chained(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats*
     double tags[2] = {0, 0};
     double* zs[2] = {nullptr, nullptr};   // coarse corrections of the last two cycles
     auto enqueue = [&](int k) -> int {
+        CycleScope cs(h);
         CHK(vcycle<double>(h, 1, trans, true, false));
         zs[k & 1] = c.u;
+        level_mark(h, 0);
+        Range r0(level_range(0, true));
         FusedPass fp{};
         fp.trans = trans;
         fp.b_const = bconst;
@@ -1261,6 +1385,7 @@ int vcycles_chained(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats*
         HIPCHK(hipGetLastError());
         ++h->vcycles;
         h->norm_parts = nparts;
+        level_mark(h, -1);   // the norm's copy to the host counts on no level
         return post_norm_async(h, k & 1, &tags[k & 1]);
     };
     int rc = enqueue(1);
@@ -1335,7 +1460,10 @@ int solve_fp64(stmg_ctx* h, int trans, bool zero_u0, double nb, stmg_stats* st, 
     } else {
         if (zero_u0) CHK(set_u0(h, nullptr));
         for (cyc = 1; cyc <= h->o.max_cycles; ++cyc) {
-            CHK(vcycle<double>(h, 0, trans, false, true));
+            {
+                CycleScope cs(h);
+                CHK(vcycle<double>(h, 0, trans, false, true));
+            }
             double ss;
             if (single)
                 CHK(residual_norm64(h, trans, &ss));
@@ -1442,12 +1570,15 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
     for (cyc = 1; cyc <= h->o.max_cycles; ++cyc) {
         const double s_e = s_f;
         s_f = rn > 0 ? rn / sq : 1.0;
+        CycleScope cs(h);
         if (fusedm) {
             Level& c = h->L[1];
             const float* e_in = nullptr;
             if (m == 2) {
                 // inner cycle 1 ends, inner cycle 2 starts from its iterate
                 CHK(vcycle<float>(h, 1, trans, true, false));
+                level_mark(h, 0);
+                Range r0(level_range(0, true));
                 FusedPass fp{};
                 fp.trans = trans;
                 fp.pre_sweeps = nu;
@@ -1474,6 +1605,8 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
                 e_in = f.u32;
             }
             CHK(vcycle<float>(h, 1, trans, true, false));
+            level_mark(h, 0);
+            Range r0(level_range(0, true));
             int bconst = 0;
             MixedPass mp{};
             mp.trans = trans;
@@ -1511,9 +1644,11 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
             ++h->vcycles;
             std::swap(f.u, f.t);
             std::swap(f.b32, f.t32);
+            level_mark(h, -1);
             CHK(finish_norm(h, nw, &rn));
         } else {
             for (int i = 0; i < m; ++i) CHK(vcycle<float>(h, 0, trans, i == 0, false));
+            level_mark(h, 0);
             CHK(defect_step(h, trans, s_e, s_f, &rn));
         }
         r = rn / nb;
@@ -1538,6 +1673,7 @@ int solve(stmg_ctx* h, int trans, const double* d_rhs, const double* d_u0, doubl
     if (!h) return fail(STMG_EINVAL, "null handle");
     if (!d_u) return fail(STMG_EINVAL, "null output");
     auto t0 = std::chrono::steady_clock::now();
+    Range range(trans ? "stmg_solve adjoint" : "stmg_solve forward");
     if (st) {
         std::memset(st, 0, sizeof(*st));
         st->n_levels = (int)h->L.size();
@@ -1545,6 +1681,10 @@ int solve(stmg_ctx* h, int trans, const double* d_rhs, const double* d_u0, doubl
         for (size_t i = 0; i + 1 < h->L.size() && i + 1 < sizeof(st->path); ++i) st->path[i] = h->L[i].dir;
     }
     h->timer.used = 0;
+    h->lt.used = 0;
+    h->lt.seen = 0;
+    h->lt.cycles = 0;
+    h->lt.on = false;
     h->fine_passes = 0;
     const bool zero_u0 = d_u0 == nullptr;
     Level& fl = h->L[0];
@@ -1580,6 +1720,7 @@ int solve(stmg_ctx* h, int trans, const double* d_rhs, const double* d_u0, doubl
     launch_copy2d<double, double>(f.u, f.P, d_u, f.N + 1, f.Nt + 1, f.N + 1, 1.0, h->s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->s));
+    collect_levels(h, st);
     if (st) {
         st->fine_passes = h->fine_passes;
         st->status = status;
@@ -1789,6 +1930,7 @@ int stmg_default_options(stmg_options* o) {
     o->interp = STMG_INTERP_C;
     o->debug_poison = 0;
     o->inner_cycles = 2;
+    o->time_levels = 0;
     return 0;
 }
 
@@ -1808,6 +1950,7 @@ int stmg_create(stmg_t* handle, const stmg_problem* p, const stmg_options* o,
     CHK(validate(p, o));
     if (!d_rho) return fail(STMG_EINVAL, "null density");
     const auto t0 = std::chrono::steady_clock::now();
+    Range range("stmg_create");
     auto* h = new stmg_ctx();
     h->p = *p;
     h->o = *o;
@@ -1852,6 +1995,7 @@ int stmg_create(stmg_t* handle, const stmg_problem* p, const stmg_options* o,
 int stmg_set_field(stmg_t h, const double* d_field) {
     if (!h || !d_field) return fail(STMG_EINVAL, "null argument");
     const auto t0 = std::chrono::steady_clock::now();
+    Range range("stmg_set_field");
     // keep the old field to restore the handle if the new one is rejected
     std::vector<double> old((size_t)h->p.n_el);
     HIPCHK(hipMemcpyAsync(old.data(), h->rho, old.size() * 8, hipMemcpyDeviceToHost, h->s));

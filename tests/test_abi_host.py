@@ -98,7 +98,8 @@ def test_create_rejects_bad_problem_without_device_work(field, value):
 @pytest.mark.parametrize("field,value", [("nu", -1), ("omega", 0.0), ("max_cycles", 0),
                                          ("max_cycles", 5000), ("precision", 7), ("reassembly", 9),
                                          ("min_coarse_dofs", 0), ("tol", -1.0), ("fused", 3),
-                                         ("fused", -1), ("time_kernels", -1), ("interp", 2)])
+                                         ("fused", -1), ("time_kernels", -1), ("interp", 2),
+                                         ("time_levels", -1)])
 def test_create_rejects_bad_options(field, value):
     p = B.Problem(8, 8).c_struct()
     o = B.make_options(**{field: value})
@@ -185,3 +186,36 @@ def test_header_compiles_as_c99_and_links(tmp_path):
                     f"-Wl,-rpath,{lib}", "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     assert out[0] == "diverged" and int(out[1]) > 0 and int(out[2]) == 2
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes mirror of a header struct has the C compiler's size and field
+    offsets, so a field added on one side only fails here rather than in a solve."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    mirrors = [B.stmg_problem, B.stmg_options, B.stmg_stats, B.stmg_info]
+    lines = []
+    for st in mirrors:
+        name = st.__name__
+        lines.append(f'printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "stmg.h"\n'
+                   "int main(void) {\n" + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", f"-I{HEADER.parent}", str(src),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        sname, fname, val = line.split()
+        got[sname, fname] = int(val)
+    for st in mirrors:
+        name = st.__name__
+        assert got[name, "sizeof"] == C.sizeof(st), name
+        for f, _ in st._fields_:
+            assert got[name, f] == getattr(st, f).offset, (name, f)

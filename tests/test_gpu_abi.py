@@ -1,7 +1,8 @@
 """GPU tests of the boundary's set-up forms against the oracle: the Algorithm 3 tie,
 hierarchies built from a conductivity field (Section 2: k(x), c(x)), the statistics a
-solve reports, the FP32 per-level components of a mixed-precision handle, and a mixed
-solve that follows a diverged one on the same handle."""
+solve reports (level-by-level timing included), the FP32 per-level components of a
+mixed-precision handle, and a mixed solve that follows a diverged one on the same
+handle."""
 from __future__ import annotations
 
 import numpy as np
@@ -191,3 +192,42 @@ def test_mixed_solve_after_a_diverged_one_matches_a_fresh_handle(cuda):
     assert np.array_equal(to_np(ua), to_np(ub))
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision,fused", [("fp64", 1), ("fp64", 2), ("fp64", 0),
+                                             ("mixed", 1), ("mixed", 0)])
+def test_level_timing_reports_every_level_and_changes_no_bit(precision, fused, cuda):
+    """time_levels records events between the passes only: the iterates and the
+    history are those of an untimed handle, bit for bit; every level that runs its own
+    passes reports time (levels inside the single-workgroup tail count on its first
+    level), and the per-cycle level times add up to less than the solve's wall time."""
+    from paper_2505_10168_amd import binding as B
+    rho = np.ones(512)
+    prob = B.Problem(512, 1024, k_ins=1e-3)
+    prec = B.STMG_FP64 if precision == "fp64" else B.STMG_MIXED
+    opts = dict(nu=2, precision=prec, fused=fused)
+    a = B.Solver(prob, to_dev(rho, cuda), time_levels=1, **opts)
+    b = B.Solver(prob, to_dev(rho, cuda), **opts)
+    ua, sa = a.solve_forward()
+    ub, sb = b.solve_forward()
+    assert sa.status == 0 and sa.history == sb.history
+    assert np.array_equal(to_np(ua), to_np(ub))
+    assert sb.level_cycles == 0 and sb.level_ms == []
+    # the pipelined loops enqueue one cycle beyond the last tested one
+    assert sa.cycles <= sa.level_cycles <= sa.cycles + 1
+    tail = a.info()["tail_level"]
+    n = sa.n_levels
+    own = range(n) if tail < 0 else range(tail + 1)
+    print(f"{precision} fused={fused}: levels {n}, tail {tail}, ms per cycle " +
+          " ".join(f"{x:.3f}" for x in sa.level_ms))
+    assert len(sa.level_ms) == n
+    assert all(sa.level_ms[l] > 0 for l in own)
+    assert all(sa.level_ms[l] == 0 for l in range(n) if l not in own)
+    assert sum(sa.level_ms) * sa.level_cycles < sa.solve_ms
+    # every third cycle, the first included
+    c = B.Solver(prob, to_dev(rho, cuda), time_levels=3, **opts)
+    _, sc = c.solve_forward()
+    assert sc.history == sb.history
+    assert sc.level_cycles == (sa.level_cycles + 2) // 3
+    for s in (a, b, c):
+        s.close()
