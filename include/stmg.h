@@ -94,7 +94,7 @@ typedef struct {
  * lambda_crit = 0.25, max_levels = 0, min_coarse_dofs = 1024, M_min_elems = 0,
  * reassembly = R, deff_mode = 0, tol = 1e-10, diverge = 1e9, max_cycles = 100,
  * precision = FP64, w_diri_override = 0, fused = 1, time_kernels = 0, interp = C,
- * debug_poison = 0, inner_cycles = 2, time_levels = 0. */
+ * debug_poison = 0, inner_cycles = 4, time_levels = 0. */
 typedef struct {
     int32_t nu;               /* smoothing steps before and after the coarse correction (Algorithm 1) */
     double  omega;            /* Jacobi damping (Section 3.1 uses 1/2)                       */

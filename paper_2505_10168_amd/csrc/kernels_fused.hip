@@ -945,6 +945,29 @@ void dispatch_cycle_zero(int S, int tail, const LevelView<T>& L, const FusedArgs
 #undef STMG_CYCLE0
 }
 
+// Two FP32 inner cycles meet on the finest level of a mixed-precision solve, the first
+// from a stored pre-smoothed iterate: its prolongation and S post-smoothing steps, then
+// the S pre-smoothing steps of the next inner cycle, which are stored, and their
+// restricted residual.
+template <int TR>
+void dispatch_join(int S, int tail, const LevelView<float>& L, const FusedArgs<float>& a,
+                   const LaunchCfg& lc, hipStream_t s) {
+#define STMG_JOIN(SS)                                                                          \
+    if (a.head == 1) {                                                                         \
+        if (tail == TAIL_RX) launch_one<float, TR, 0, 1, SS, 0, SS, TAIL_RX>(L, a, lc, s);     \
+        else launch_one<float, TR, 0, 1, SS, 0, SS, TAIL_RT>(L, a, lc, s);                     \
+    } else {                                                                                   \
+        if (tail == TAIL_RX) launch_one<float, TR, 0, 2, SS, 0, SS, TAIL_RX>(L, a, lc, s);     \
+        else launch_one<float, TR, 0, 2, SS, 0, SS, TAIL_RT>(L, a, lc, s);                     \
+    }
+    if (S == 1) {
+        STMG_JOIN(1)
+    } else {
+        STMG_JOIN(2)
+    }
+#undef STMG_JOIN
+}
+
 }  // namespace
 
 int fused_max_sweeps() { return kMaxFused; }
@@ -975,7 +998,12 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
     const bool cyc = fp.mid_norm != 0;
     const bool cyc0 = S1 > 0 && S3 > 0;    // two zero-start cycles meet (no MID)
     const bool recompute = S1 > 0 && S3 == 0;
-    if (cyc || recompute || cyc0) {
+    const bool join = S1 == 0 && S3 > 0 && !cyc;   // two FP32 inner cycles meet
+    if (join) {
+        if (!std::is_same<T, float>::value || S2 != S3 || S2 > kMaxMixedSweeps || fp.zero_in ||
+            (fp.prolong != 'x' && fp.prolong != 't') || (fp.tail != 'x' && fp.tail != 't'))
+            return -1;
+    } else if (cyc || recompute || cyc0) {
         // the chain passes: S1 = S2 (recompute), S2 = S3 with MID (cycle) or
         // S1 = S2 = S3 (cycle from zero); x / t head
         if (chain > kMaxChain || (fp.prolong != 'x' && fp.prolong != 't')) return -1;
@@ -1023,6 +1051,13 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
     if (cyc0) {
         if (fp.trans) dispatch_cycle_zero<T, 1>(S1, tail, L, a, lc, s);
         else dispatch_cycle_zero<T, 0>(S1, tail, L, a, lc, s);
+        return G.nwaves;
+    }
+    if (join) {
+        if constexpr (std::is_same<T, float>::value) {
+            if (fp.trans) dispatch_join<1>(S2, tail, L, a, lc, s);
+            else dispatch_join<0>(S2, tail, L, a, lc, s);
+        }
         return G.nwaves;
     }
     if (cyc) {

@@ -1538,17 +1538,18 @@ int defect_step(stmg_ctx* h, int trans, double s_e, double s_f, double* norm) {
 // On the finest level with the fused kernels, one pass (launch_mixed) does the FP32
 // post-smoothing of the last inner cycle, the FP64 defect correction and the FP32
 // pre-smoothing of the next outer step's first inner cycle, so the FP32 correction is
-// stored only between inner cycles; with two inner cycles one FP32 pass joins the
-// first cycle's post-smoothing (its pre-smoothing recomputed) and the second's
-// pre-smoothing.  Same bits as the unfused loop.
+// stored only between inner cycles.  Between two inner cycles one FP32 pass joins the
+// post-smoothing of the first and the pre-smoothing of the second: after the first
+// inner cycle its pre-smoothing is recomputed from zero, after a later one it is read
+// back (the pre-smoothed iterate alternates between two FP32 vectors).  Same bits as
+// the unfused loop.
 #ifndef STMG_MIXED_FUSED
 #define STMG_MIXED_FUSED 1
 #endif
 bool mixed_fused_options(const stmg_ctx* h) {
     const Level& f = h->L[0];
     return STMG_MIXED_FUSED && h->o.fused && h->L.size() >= 2 && !f.sten && h->o.nu >= 1 &&
-           h->o.nu <= mixed_max_sweeps() && h->o.inner_cycles <= 2 &&
-           !(f.dir == 't' && h->o.interp == STMG_INTERP_B);
+           h->o.nu <= mixed_max_sweeps() && !(f.dir == 't' && h->o.interp == STMG_INTERP_B);
 }
 
 int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) {
@@ -1573,18 +1574,20 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
         CycleScope cs(h);
         if (fusedm) {
             Level& c = h->L[1];
-            const float* e_in = nullptr;
-            if (m == 2) {
-                // inner cycle 1 ends, inner cycle 2 starts from its iterate
+            // the pre-smoothed iterate of the current inner cycle (none: the first,
+            // which starts from zero and is recomputed)
+            float* e_in = nullptr;
+            for (int i = 1; i < m; ++i) {
+                // inner cycle i ends, inner cycle i + 1 starts from its iterate
                 CHK(vcycle<float>(h, 1, trans, true, false));
                 level_mark(h, 0);
                 Range r0(level_range(0, true));
                 FusedPass fp{};
                 fp.trans = trans;
-                fp.pre_sweeps = nu;
+                fp.pre_sweeps = e_in ? 0 : nu;
                 fp.sweeps = nu;
                 fp.next_sweeps = nu;
-                fp.zero_in = 1;
+                fp.zero_in = e_in ? 0 : 1;
                 fp.prolong = f.dir;
                 fp.z = c.u32;
                 fp.Pz = c.P;
@@ -1594,15 +1597,16 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
                 fp.bc = c.b32;
                 fp.Pbc = c.P;
                 fp.fine = 1;
+                float* dst = e_in == f.u32 ? f.t32 : f.u32;
                 const bool tk = timed_now();
                 timer_begin(h, tk, fp);
-                if (launch_fused<float>(view<float>(f, h->o.omega), fp, nullptr, f.b32, f.u32, h->s) < 0)
+                if (launch_fused<float>(view<float>(f, h->o.omega), fp, e_in, f.b32, dst, h->s) < 0)
                     return fail(STMG_EINVAL, "inner cycle pass rejected");
-                // read f, z; written e, coarse b
-                timer_end(h, tk, (double)f.dofs() * 8 + 2.0 * (double)c.dofs() * 4);
+                // read (e), f, z; written e', coarse b
+                timer_end(h, tk, (double)f.dofs() * (e_in ? 12 : 8) + 2.0 * (double)c.dofs() * 4);
                 HIPCHK(hipGetLastError());
                 ++h->vcycles;
-                e_in = f.u32;
+                e_in = dst;
             }
             CHK(vcycle<float>(h, 1, trans, true, false));
             level_mark(h, 0);
@@ -1620,7 +1624,8 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
             mp.b = level_b<double>(h, f, 0, &bconst);
             mp.b_const = bconst;
             mp.u_out = f.t;
-            mp.f_out = f.t32;
+            // the next right-hand side goes to the FP32 vector that holds neither e nor f
+            mp.f_out = e_in == f.t32 ? f.u32 : f.t32;
             mp.pre = 1;
             mp.tail = f.dir;
             mp.bc = c.b32;
@@ -1643,7 +1648,10 @@ int solve_mixed(stmg_ctx* h, int trans, double nb, stmg_stats* st, int* status) 
             HIPCHK(hipGetLastError());
             ++h->vcycles;
             std::swap(f.u, f.t);
-            std::swap(f.b32, f.t32);
+            float* old_f = f.b32;
+            f.b32 = mp.f_out;
+            if (mp.f_out == f.t32) f.t32 = old_f;
+            else f.u32 = old_f;
             level_mark(h, -1);
             CHK(finish_norm(h, nw, &rn));
         } else {
@@ -1929,7 +1937,7 @@ int stmg_default_options(stmg_options* o) {
     o->time_kernels = 0;
     o->interp = STMG_INTERP_C;
     o->debug_poison = 0;
-    o->inner_cycles = 2;
+    o->inner_cycles = 4;
     o->time_levels = 0;
     return 0;
 }

@@ -15,14 +15,19 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("transpose", [0, 1])
 @pytest.mark.parametrize("fused", [1, 0])
-@pytest.mark.parametrize("inner", [1, 2])
-def test_mixed_precision_tracks_fp64(name, transpose, fused, inner, cuda):
+@pytest.mark.parametrize("inner", [1, 2, 4])
+@pytest.mark.parametrize("nu", [2, 5])
+def test_mixed_precision_tracks_fp64(name, transpose, fused, inner, nu, cuda):
     """FP32 smoothers and transfers inside an FP64 defect correction: with `inner` FP32
     V-cycles per correction, correction j has the residual of FP64 cycle inner * j (to
     FP32 accuracy per cycle) and the same cycle count, the 1e-10 FP64 residual when FP64
-    reaches it, and the solution error against the oracle's direct solve stated."""
+    reaches it, and the solution error against the oracle's direct solve stated.  With
+    nu = 2 and fused = 1 the finest level runs the fused mixed passes (the inner cycles
+    joined pairwise, the last one joined to the FP64 defect correction); nu = 5 takes
+    the per-level passes."""
     from paper_2505_10168_amd import binding as B
-    kw = dict(fused=fused, max_cycles=300, nu=5)
+    # ramp_300x256 needs about 450 V(2,2) cycles
+    kw = dict(fused=fused, max_cycles=600 if nu == 2 else 300, nu=nu)
     s64, _, lv, h = make_pair(name, cuda, **kw)
     s32, _, _, _ = make_pair(name, cuda, precision=B.STMG_MIXED, inner_cycles=inner, **kw)
     b = O.load_vector(lv, 1.0)
@@ -33,12 +38,18 @@ def test_mixed_precision_tracks_fp64(name, transpose, fused, inner, cuda):
     u32, m = solve32()
     exact = O.direct_solve(lv, rhs, bool(transpose))
     err = rel(to_np(u32), exact)
-    print(f"mixed {name} T={transpose} fused={fused}: cycles={m.cycles} (fp64 {a.cycles}) "
+    print(f"mixed {name} T={transpose} fused={fused} inner={inner} nu={nu}: cycles={m.cycles} (fp64 {a.cycles}) "
           f"r={m.rel_residual:.2e} err_vs_oracle_direct={err:.2e} (fp64 {rel(to_np(u64), exact):.2e})")
     assert m.status == a.status
     assert abs(inner * m.cycles - a.cycles) <= 2 * inner
     n = min(len(m.history), (len(a.history) - 1) // inner + 1, 30 // inner)
-    np.testing.assert_allclose(m.history[:n], a.history[: inner * n : inner], rtol=1e-3)
+    # a correction adds the FP32 floor of its inner solve, relative to the residual it
+    # starts from (FP32 rounding times the operator's amplification; 1.6e-5 seen after
+    # four nu = 5 inner cycles on 64 x 64), to the FP64 cycles' residual
+    got = np.array(m.history[:n])
+    want = np.array(a.history[: inner * n : inner])
+    start = np.concatenate([[0.0], got[:-1]])
+    assert np.all(np.abs(got - want) <= 1e-3 * want + 1e-4 * start), (got, want)
     if a.status == 0:
         assert m.rel_residual < 1e-10 and err < 1e-7
         r_or = np.linalg.norm(O.apply_J(lv, to_np(u32), bool(transpose)) - rhs) / np.linalg.norm(rhs)
@@ -47,15 +58,18 @@ def test_mixed_precision_tracks_fp64(name, transpose, fused, inner, cuda):
 
 @pytest.mark.parametrize("name", ["uniform_64x64", "block_256x600"])
 @pytest.mark.parametrize("transpose", [0, 1])
-def test_mixed_tail_is_bit_identical(name, transpose, cuda):
+@pytest.mark.parametrize("inner", [1, 2, 3])
+def test_mixed_tail_is_bit_identical(name, transpose, inner, cuda):
     """The mixed solve through the single-workgroup tail (fused = 1) and through
-    streaming launches on every level (fused = 2) gives the same bits.  (The reference
+    streaming launches on every level (fused = 2) gives the same bits, with 1, 2 or 3
+    inner cycles per correction (nu = 2: the fused finest-level passes).  (The reference
     path, fused = 0, sums the residual norms in another order, so its scales of the FP32
     right-hand sides, and with them the FP32 roundings, differ in the last bits.)"""
     from paper_2505_10168_amd import binding as B
     outs = []
     for fused in (1, 2):
-        s, _, lv, h = make_pair(name, cuda, fused=fused, precision=B.STMG_MIXED, max_cycles=5)
+        s, _, lv, h = make_pair(name, cuda, fused=fused, precision=B.STMG_MIXED, max_cycles=5,
+                                nu=2, inner_cycles=inner)
         assert (s.info()["tail_level"] > 0) == (fused == 1)
         u, st = (s.solve_adjoint if transpose else s.solve_forward)()
         outs.append((to_np(u), st.history))
