@@ -53,6 +53,9 @@ constexpr int kWavesPerBlock = 4;
 #ifndef STMG_BIG_LEVEL_BYTES
 #define STMG_BIG_LEVEL_BYTES 268435456.0
 #endif
+#ifndef STMG_SPLIT_LOOP
+#define STMG_SPLIT_LOOP 1   // 0: one copy of the streaming loop, with the row-0 tests
+#endif
 #ifndef STMG_MIN_SEGMENT
 #define STMG_MIN_SEGMENT 2
 #endif
@@ -305,180 +308,195 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
     for (int d = 0; d < PF; ++d)
         if (d < count) fetch(row_of(d), ru[d], rb[d], rz[d]);
 
-    for (int it0 = 0; it0 < count; it0 += PF) {
+    // Waves whose rows include the Dirichlet row 0 or a row without time coupling run
+    // the loop with those tests; every other wave runs a copy without them, whose rows
+    // then need no join of the two compiled chains (a join costs register moves).
+    auto stream = [&](auto special_tag) {
+        constexpr bool SPECIAL = decltype(special_tag)::value;
+        for (int it0 = 0; it0 < count; it0 += PF) {
 #pragma unroll
-    for (int d = 0; d < PF; ++d) {
-        const int it = it0 + d;
-        if (it >= count) break;
-        const int n = row_of(it);
-        T x[K], bb[K], zz[KZ];
+        for (int d = 0; d < PF; ++d) {
+            const int it = it0 + d;
+            if (it >= count) break;
+            const int n = row_of(it);
+            T x[K], bb[K], zz[KZ];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            x[j] = ru[d][j];
-            bb[j] = rb[d][j];
-        }
+            for (int j = 0; j < K; ++j) {
+                x[j] = ru[d][j];
+                bb[j] = rb[d][j];
+            }
 #pragma unroll
-        for (int j = 0; j < KZ; ++j) zz[j] = rz[d][j];
-        if (it + PF < count) fetch(row_of(it + PF), ru[d], rb[d], rz[d]);
-        const bool out_row = (n >= n0) && (n < n1);
-        const bool dir_row = (n == 0);
-        const bool coupled = TR ? (n < Nt) : (n >= 2);
-        if (!coupled) {
-            // first levels of J (last of J^T): no coupling, i.e. a zero coupled row
+            for (int j = 0; j < KZ; ++j) zz[j] = rz[d][j];
+            if (it + PF < count) fetch(row_of(it + PF), ru[d], rb[d], rz[d]);
+            const bool out_row = (n >= n0) && (n < n1);
+            const bool dir_row = SPECIAL && (n == 0);
+            const bool coupled = !SPECIAL || (TR ? (n < Nt) : (n >= 2));
+            if (SPECIAL && !coupled) {
+                // first levels of J (last of J^T): no coupling, i.e. a zero coupled row
 #pragma unroll
-            for (int k = 0; k < NST; ++k)
+                for (int k = 0; k < NST; ++k)
 #pragma unroll
-                for (int j = 0; j < K; ++j) prev[k][j] = T(0);
-        }
+                    for (int j = 0; j < K; ++j) prev[k][j] = T(0);
+            }
 
-        // The chain, compiled twice: for the Dirichlet row 0 and for every other row.
-        T r[K], rm[K];
-        auto chain = [&](auto dir_tag) {
-            constexpr bool DIR = decltype(dir_tag)::value;
-            auto steps = [&](auto k0_tag, auto k1_tag) {
-                constexpr int k0 = decltype(k0_tag)::value, k1 = decltype(k1_tag)::value;
+            // The chain, compiled twice: for the Dirichlet row 0 and for every other row.
+            T r[K], rm[K];
+            auto chain = [&](auto dir_tag) {
+                constexpr bool DIR = decltype(dir_tag)::value;
+                auto steps = [&](auto k0_tag, auto k1_tag) {
+                    constexpr int k0 = decltype(k0_tag)::value, k1 = decltype(k1_tag)::value;
 #pragma unroll
-                for (int k = k0; k < k1; ++k) {
-                    T y[K];
-                    row_step<T, K, true, DIR>(L, C, x, prev[k], bb, y);
+                    for (int k = k0; k < k1; ++k) {
+                        T y[K];
+                        row_step<T, K, true, DIR>(L, C, x, prev[k], bb, y);
+#pragma unroll
+                        for (int j = 0; j < K; ++j) {
+                            prev[k][j] = x[j];
+                            x[j] = y[j];
+                        }
+                    }
+                };
+                steps(std::integral_constant<int, 0>{}, std::integral_constant<int, S1>{});
+                // Prolongation head: x += P z.
+                if constexpr (HEAD == 1) {
+                    const T znext = shfl_dn1(zz[0]);   // first coarse value of the next lane
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
-                        prev[k][j] = x[j];
-                        x[j] = y[j];
+                        const T za = zz[j >> 1];
+                        if ((j & 1) == 0) {
+                            x[j] += za;
+                        } else {
+                            const T zb = ((j >> 1) + 1 < KH) ? zz[((j >> 1) + 1) % KZ] : znext;
+                            x[j] = fmaT(T(0.5), za + zb, x[j]);
+                        }
                     }
+                } else if constexpr (HEAD == 2) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) x[j] += zz[j];
+                } else if constexpr (HEAD == 3) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) x[j] = fmaT((T)a.s_old, zz[j], x[j]);
+                }
+                if constexpr (HASZ) {
+                    // the interpolation reaches past the last node and into the lane left of
+                    // column 0; those columns must stay zero (padding, eliminated neighbour)
+#pragma unroll
+                    for (int j = 0; j < K; ++j) x[j] = valid[j] ? x[j] : T(0);
+                }
+                steps(std::integral_constant<int, S1>{}, std::integral_constant<int, S1 + S2>{});
+                if constexpr (MID) {
+                    if (a.mid != nullptr && out_row && useful && lane_in) st(a.mid + (int64_t)n * P + g, x);
+                    row_step<T, K, false, DIR>(L, C, x, prev[IM], bb, rm);
+#pragma unroll
+                    for (int j = 0; j < K; ++j) prev[IM][j] = x[j];
+                }
+                steps(std::integral_constant<int, S1 + S2>{}, std::integral_constant<int, S>{});
+                if constexpr (TAIL != TAIL_NONE) {
+                    row_step<T, K, false, DIR>(L, C, x, prev[IT], bb, r);
+#pragma unroll
+                    for (int j = 0; j < K; ++j) prev[IT][j] = x[j];
                 }
             };
-            steps(std::integral_constant<int, 0>{}, std::integral_constant<int, S1>{});
-            // Prolongation head: x += P z.
-            if constexpr (HEAD == 1) {
-                const T znext = shfl_dn1(zz[0]);   // first coarse value of the next lane
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const T za = zz[j >> 1];
-                    if ((j & 1) == 0) {
-                        x[j] += za;
-                    } else {
-                        const T zb = ((j >> 1) + 1 < KH) ? zz[((j >> 1) + 1) % KZ] : znext;
-                        x[j] = fmaT(T(0.5), za + zb, x[j]);
-                    }
-                }
-            } else if constexpr (HEAD == 2) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) x[j] += zz[j];
-            } else if constexpr (HEAD == 3) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) x[j] = fmaT((T)a.s_old, zz[j], x[j]);
+            if constexpr (SPECIAL) {
+                if (dir_row)
+                    chain(std::true_type{});
+                else
+                    chain(std::false_type{});
+            } else {
+                chain(std::false_type{});
             }
-            if constexpr (HASZ) {
-                // the interpolation reaches past the last node and into the lane left of
-                // column 0; those columns must stay zero (padding, eliminated neighbour)
-#pragma unroll
-                for (int j = 0; j < K; ++j) x[j] = valid[j] ? x[j] : T(0);
-            }
-            steps(std::integral_constant<int, S1>{}, std::integral_constant<int, S1 + S2>{});
+
+            if (store_out && out_row && useful && lane_in) st(a.out + (int64_t)n * P + g, x);
+
             if constexpr (MID) {
-                if (a.mid != nullptr && out_row && useful && lane_in) st(a.mid + (int64_t)n * P + g, x);
-                row_step<T, K, false, DIR>(L, C, x, prev[IM], bb, rm);
-#pragma unroll
-                for (int j = 0; j < K; ++j) prev[IM][j] = x[j];
-            }
-            steps(std::integral_constant<int, S1 + S2>{}, std::integral_constant<int, S>{});
-            if constexpr (TAIL != TAIL_NONE) {
-                row_step<T, K, false, DIR>(L, C, x, prev[IT], bb, r);
-#pragma unroll
-                for (int j = 0; j < K; ++j) prev[IT][j] = x[j];
-            }
-        };
-        if (dir_row)
-            chain(std::true_type{});
-        else
-            chain(std::false_type{});
-
-        if (store_out && out_row && useful && lane_in) st(a.out + (int64_t)n * P + g, x);
-
-        if constexpr (MID) {
-            if (out_row && useful) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const double rv = (double)rm[j];
-                    acc = __builtin_fma(rv, rv, acc);
-                }
-            }
-        }
-        if constexpr (TAIL != TAIL_NONE) {
-            if constexpr (TAIL == TAIL_RX) {
-                // coarse node I = (g + j)/2 for even j: r_{2I} + 1/2 (r_{2I-1} + r_{2I+1})
-                const T rl = shfl_up1(r[K - 1]);
-                if (out_row && useful && lane_in) {
-                    const int I0 = g >> 1;
-                    T c[KH];
-#pragma unroll
-                    for (int q = 0; q < KH; ++q) {
-                        const T left = (q == 0) ? rl : r[2 * q - 1];
-                        c[q] = fmaT(T(0.5), left + r[2 * q + 1], r[2 * q]);
-                    }
-                    T* dst = a.bc + (int64_t)n * a.Pbc + I0;
-                    if (I0 + KH - 1 <= a.Nc) {
-                        sth(dst, c);
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < KH; ++q)
-                            if (I0 + q <= a.Nc) dst[q] = c[q];
-                    }
-                }
-            } else if constexpr (TAIL == TAIL_RT) {
-                if (out_row && useful && lane_in) {
-                    // pairs (2J, 2J+1) -> J; the transposed stream meets 2J+1 first
-                    const bool odd = (n & 1) != 0;
-                    T v[K];
-                    T* dst = a.bc + (int64_t)(n >> 1) * a.Pbc + g;
-                    if (!TR) {
-                        if (odd) {
-#pragma unroll
-                            for (int j = 0; j < K; ++j) v[j] = T(0.5) * (r_pair[j] + r[j]);
-                            st(dst, v);
-                        } else if (n == Nt) {
-#pragma unroll
-                            for (int j = 0; j < K; ++j) v[j] = T(0.5) * r[j];
-                            st(dst, v);
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < K; ++j) r_pair[j] = r[j];
-                        }
-                    } else {
-                        if (odd) {
-#pragma unroll
-                            for (int j = 0; j < K; ++j) r_pair[j] = r[j];
-                        } else if (n == Nt) {
-#pragma unroll
-                            for (int j = 0; j < K; ++j) v[j] = T(0.5) * r[j];
-                            st(dst, v);
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < K; ++j) v[j] = T(0.5) * (r[j] + r_pair[j]);
-                            st(dst, v);
-                        }
-                    }
-                }
-            } else if constexpr (TAIL == TAIL_NORM || TAIL == TAIL_DEFECT) {
                 if (out_row && useful) {
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
-                        const double rv = (double)r[j];
+                        const double rv = (double)rm[j];
                         acc = __builtin_fma(rv, rv, acc);
                     }
                 }
-                if constexpr (TAIL == TAIL_DEFECT && std::is_same<T, double>::value) {
+            }
+            if constexpr (TAIL != TAIL_NONE) {
+                if constexpr (TAIL == TAIL_RX) {
+                    // coarse node I = (g + j)/2 for even j: r_{2I} + 1/2 (r_{2I-1} + r_{2I+1})
+                    const T rl = shfl_up1(r[K - 1]);
                     if (out_row && useful && lane_in) {
-                        const float2 f = make_float2((float)(r[0] * a.inv_s_new),
-                                                     (float)(r[1] * a.inv_s_new));
-                        *reinterpret_cast<float2*>(a.f32 + (int64_t)n * P + g) = f;
+                        const int I0 = g >> 1;
+                        T c[KH];
+#pragma unroll
+                        for (int q = 0; q < KH; ++q) {
+                            const T left = (q == 0) ? rl : r[2 * q - 1];
+                            c[q] = fmaT(T(0.5), left + r[2 * q + 1], r[2 * q]);
+                        }
+                        T* dst = a.bc + (int64_t)n * a.Pbc + I0;
+                        if (I0 + KH - 1 <= a.Nc) {
+                            sth(dst, c);
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < KH; ++q)
+                                if (I0 + q <= a.Nc) dst[q] = c[q];
+                        }
+                    }
+                } else if constexpr (TAIL == TAIL_RT) {
+                    if (out_row && useful && lane_in) {
+                        // pairs (2J, 2J+1) -> J; the transposed stream meets 2J+1 first
+                        const bool odd = (n & 1) != 0;
+                        T v[K];
+                        T* dst = a.bc + (int64_t)(n >> 1) * a.Pbc + g;
+                        if (!TR) {
+                            if (odd) {
+#pragma unroll
+                                for (int j = 0; j < K; ++j) v[j] = T(0.5) * (r_pair[j] + r[j]);
+                                st(dst, v);
+                            } else if (n == Nt) {
+#pragma unroll
+                                for (int j = 0; j < K; ++j) v[j] = T(0.5) * r[j];
+                                st(dst, v);
+                            } else {
+#pragma unroll
+                                for (int j = 0; j < K; ++j) r_pair[j] = r[j];
+                            }
+                        } else {
+                            if (odd) {
+#pragma unroll
+                                for (int j = 0; j < K; ++j) r_pair[j] = r[j];
+                            } else if (n == Nt) {
+#pragma unroll
+                                for (int j = 0; j < K; ++j) v[j] = T(0.5) * r[j];
+                                st(dst, v);
+                            } else {
+#pragma unroll
+                                for (int j = 0; j < K; ++j) v[j] = T(0.5) * (r[j] + r_pair[j]);
+                                st(dst, v);
+                            }
+                        }
+                    }
+                } else if constexpr (TAIL == TAIL_NORM || TAIL == TAIL_DEFECT) {
+                    if (out_row && useful) {
+#pragma unroll
+                        for (int j = 0; j < K; ++j) {
+                            const double rv = (double)r[j];
+                            acc = __builtin_fma(rv, rv, acc);
+                        }
+                    }
+                    if constexpr (TAIL == TAIL_DEFECT && std::is_same<T, double>::value) {
+                        if (out_row && useful && lane_in) {
+                            const float2 f = make_float2((float)(r[0] * a.inv_s_new),
+                                                         (float)(r[1] * a.inv_s_new));
+                            *reinterpret_cast<float2*>(a.f32 + (int64_t)n * P + g) = f;
+                        }
                     }
                 }
             }
         }
-    }
-    }
+        }
+    };
+    const bool special = TR ? (first == Nt || n0 == 0) : (first <= 1);
+    if (!STMG_SPLIT_LOOP || special)
+        stream(std::true_type{});
+    else
+        stream(std::false_type{});
 
     if constexpr (MID || TAIL == TAIL_NORM || TAIL == TAIL_DEFECT) {
 #pragma unroll
@@ -632,146 +650,160 @@ __device__ __forceinline__ void mixed_body(const LevelView<float>& L32, const Le
     for (int d = 0; d < PF; ++d)
         if (d < count) fetch(row_of(d), rf[d], rz[d], re[d], ru[d], rb[d]);
 
-    for (int it0 = 0; it0 < count; it0 += PF) {
+    // the loop in two copies, as in fused_body: with and without the tests for the
+    // Dirichlet row and the rows without time coupling
+    auto stream = [&](auto special_tag) {
+        constexpr bool SPECIAL = decltype(special_tag)::value;
+        for (int it0 = 0; it0 < count; it0 += PF) {
 #pragma unroll
-    for (int d = 0; d < PF; ++d) {
-        const int it = it0 + d;
-        if (it >= count) break;
-        const int n = row_of(it);
-        float fr[K], zz[KZ], ee[KE];
-        double uu[K], bb[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            fr[j] = rf[d][j];
-            uu[j] = ru[d][j];
-            bb[j] = rb[d][j];
-        }
-#pragma unroll
-        for (int j = 0; j < KZ; ++j) zz[j] = rz[d][j];
-#pragma unroll
-        for (int j = 0; j < KE; ++j) ee[j] = re[d][j];
-        if (it + PF < count) fetch(row_of(it + PF), rf[d], rz[d], re[d], ru[d], rb[d]);
-        const bool out_row = (n >= n0) && (n < n1);
-        const bool dir_row = (n == 0);
-        const bool coupled = TR ? (n < Nt) : (n >= 2);
-        if (!coupled) {
-#pragma unroll
-            for (int k = 0; k < NS32; ++k)
-#pragma unroll
-                for (int j = 0; j < K; ++j) pa[k][j] = 0.0f;
-#pragma unroll
-            for (int j = 0; j < K; ++j) p64[j] = 0.0;
-        }
-        double r64[K];
-        float rc[K], fn[K];
-        auto chain = [&](auto dir_tag) {
-            constexpr bool DIR = decltype(dir_tag)::value;
-            // ending inner cycle: S steps from zero (or its stored pre-smoothed iterate),
-            // prolongation, S steps
-            float x[K] = {0.0f, 0.0f};
-            if constexpr (FROM_E) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) x[j] = ee[j];
-            }
-#pragma unroll
-            for (int k = 0; k <= NA; ++k) {
-                if (k == KH0) {
-                    if constexpr (HEAD == 1) {
-                        const float znext = shfl_dn1(zz[0]);
-                        x[0] += zz[0];
-                        x[1] = fmaT(0.5f, zz[0] + znext, x[1]);
-                    } else {
-                        x[0] += zz[0];
-                        x[1] += zz[1];
-                    }
-#pragma unroll
-                    for (int j = 0; j < K; ++j) x[j] = valid[j] ? x[j] : 0.0f;
-                }
-                if (k == NA) break;
-                float y[K];
-                row_step<float, K, true, DIR>(L32, C32, x, pa[k], fr, y);
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    pa[k][j] = x[j];
-                    x[j] = y[j];
-                }
-            }
-            // FP64 defect correction
-            double xu[K];
-#pragma unroll
-            for (int j = 0; j < K; ++j) xu[j] = valid[j] ? fmaT(a.s_e, (double)x[j], uu[j]) : 0.0;
-            if (out_row && useful && lane_in) st(a.u_out + (int64_t)n * P + g, xu);
-            row_step<double, K, false, DIR>(L64, C64, xu, p64, bb, r64);
+        for (int d = 0; d < PF; ++d) {
+            const int it = it0 + d;
+            if (it >= count) break;
+            const int n = row_of(it);
+            float fr[K], zz[KZ], ee[KE];
+            double uu[K], bb[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                p64[j] = xu[j];
-                fn[j] = (float)(r64[j] * a.inv_s);
+                fr[j] = rf[d][j];
+                uu[j] = ru[d][j];
+                bb[j] = rb[d][j];
             }
-            if constexpr (PRE) {
-                // next inner cycle: S steps from zero on f', residual
-                float w[K] = {0.0f, 0.0f};
 #pragma unroll
-                for (int k = NA; k < NA + NC; ++k) {
+            for (int j = 0; j < KZ; ++j) zz[j] = rz[d][j];
+#pragma unroll
+            for (int j = 0; j < KE; ++j) ee[j] = re[d][j];
+            if (it + PF < count) fetch(row_of(it + PF), rf[d], rz[d], re[d], ru[d], rb[d]);
+            const bool out_row = (n >= n0) && (n < n1);
+            const bool dir_row = SPECIAL && (n == 0);
+            const bool coupled = !SPECIAL || (TR ? (n < Nt) : (n >= 2));
+            if (SPECIAL && !coupled) {
+#pragma unroll
+                for (int k = 0; k < NS32; ++k)
+#pragma unroll
+                    for (int j = 0; j < K; ++j) pa[k][j] = 0.0f;
+#pragma unroll
+                for (int j = 0; j < K; ++j) p64[j] = 0.0;
+            }
+            double r64[K];
+            float rc[K], fn[K];
+            auto chain = [&](auto dir_tag) {
+                constexpr bool DIR = decltype(dir_tag)::value;
+                // ending inner cycle: S steps from zero (or its stored pre-smoothed iterate),
+                // prolongation, S steps
+                float x[K] = {0.0f, 0.0f};
+                if constexpr (FROM_E) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) x[j] = ee[j];
+                }
+#pragma unroll
+                for (int k = 0; k <= NA; ++k) {
+                    if (k == KH0) {
+                        if constexpr (HEAD == 1) {
+                            const float znext = shfl_dn1(zz[0]);
+                            x[0] += zz[0];
+                            x[1] = fmaT(0.5f, zz[0] + znext, x[1]);
+                        } else {
+                            x[0] += zz[0];
+                            x[1] += zz[1];
+                        }
+#pragma unroll
+                        for (int j = 0; j < K; ++j) x[j] = valid[j] ? x[j] : 0.0f;
+                    }
+                    if (k == NA) break;
                     float y[K];
-                    row_step<float, K, true, DIR>(L32, C32, w, pa[k], fn, y);
+                    row_step<float, K, true, DIR>(L32, C32, x, pa[k], fr, y);
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
-                        pa[k][j] = w[j];
-                        w[j] = y[j];
+                        pa[k][j] = x[j];
+                        x[j] = y[j];
                     }
                 }
-                row_step<float, K, false, DIR>(L32, C32, w, pa[NA + NC], fn, rc);
+                // FP64 defect correction
+                double xu[K];
 #pragma unroll
-                for (int j = 0; j < K; ++j) pa[NA + NC][j] = w[j];
-            }
-        };
-        if (dir_row)
-            chain(std::true_type{});
-        else
-            chain(std::false_type{});
-        if (out_row && useful) {
+                for (int j = 0; j < K; ++j) xu[j] = valid[j] ? fmaT(a.s_e, (double)x[j], uu[j]) : 0.0;
+                if (out_row && useful && lane_in) st(a.u_out + (int64_t)n * P + g, xu);
+                row_step<double, K, false, DIR>(L64, C64, xu, p64, bb, r64);
 #pragma unroll
-            for (int j = 0; j < K; ++j) acc = __builtin_fma(r64[j], r64[j], acc);
-        }
-        if (out_row && useful && lane_in)
-            *reinterpret_cast<float2*>(a.f_out + (int64_t)n * P + g) = make_float2(fn[0], fn[1]);
-        if constexpr (PRE && TAIL == TAIL_RX) {
-            // coarse node g/2: r_{2I} + 1/2 (r_{2I-1} + r_{2I+1})
-            const float rl = shfl_up1(rc[K - 1]);
-            if (out_row && useful && lane_in) {
-                const int I0 = g >> 1;
-                if (I0 <= a.Nc) a.bc[(int64_t)n * a.Pbc + I0] = fmaT(0.5f, rl + rc[1], rc[0]);
-            }
-        } else if constexpr (PRE && TAIL == TAIL_RT) {
-            if (out_row && useful && lane_in) {
-                const bool odd = (n & 1) != 0;
-                float* dst = a.bc + (int64_t)(n >> 1) * a.Pbc + g;
-                float v[K];
-                bool put = true;
-                if (!TR) {
-                    if (odd) {
-                        for (int j = 0; j < K; ++j) v[j] = 0.5f * (r_pair[j] + rc[j]);
-                    } else if (n == Nt) {
-                        for (int j = 0; j < K; ++j) v[j] = 0.5f * rc[j];
-                    } else {
-                        for (int j = 0; j < K; ++j) r_pair[j] = rc[j];
-                        put = false;
-                    }
-                } else {
-                    if (odd) {
-                        for (int j = 0; j < K; ++j) r_pair[j] = rc[j];
-                        put = false;
-                    } else if (n == Nt) {
-                        for (int j = 0; j < K; ++j) v[j] = 0.5f * rc[j];
-                    } else {
-                        for (int j = 0; j < K; ++j) v[j] = 0.5f * (rc[j] + r_pair[j]);
-                    }
+                for (int j = 0; j < K; ++j) {
+                    p64[j] = xu[j];
+                    fn[j] = (float)(r64[j] * a.inv_s);
                 }
-                if (put) *reinterpret_cast<float2*>(dst) = make_float2(v[0], v[1]);
+                if constexpr (PRE) {
+                    // next inner cycle: S steps from zero on f', residual
+                    float w[K] = {0.0f, 0.0f};
+#pragma unroll
+                    for (int k = NA; k < NA + NC; ++k) {
+                        float y[K];
+                        row_step<float, K, true, DIR>(L32, C32, w, pa[k], fn, y);
+#pragma unroll
+                        for (int j = 0; j < K; ++j) {
+                            pa[k][j] = w[j];
+                            w[j] = y[j];
+                        }
+                    }
+                    row_step<float, K, false, DIR>(L32, C32, w, pa[NA + NC], fn, rc);
+#pragma unroll
+                    for (int j = 0; j < K; ++j) pa[NA + NC][j] = w[j];
+                }
+            };
+            if constexpr (SPECIAL) {
+                if (dir_row)
+                    chain(std::true_type{});
+                else
+                    chain(std::false_type{});
+            } else {
+                chain(std::false_type{});
+            }
+            if (out_row && useful) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) acc = __builtin_fma(r64[j], r64[j], acc);
+            }
+            if (out_row && useful && lane_in)
+                *reinterpret_cast<float2*>(a.f_out + (int64_t)n * P + g) = make_float2(fn[0], fn[1]);
+            if constexpr (PRE && TAIL == TAIL_RX) {
+                // coarse node g/2: r_{2I} + 1/2 (r_{2I-1} + r_{2I+1})
+                const float rl = shfl_up1(rc[K - 1]);
+                if (out_row && useful && lane_in) {
+                    const int I0 = g >> 1;
+                    if (I0 <= a.Nc) a.bc[(int64_t)n * a.Pbc + I0] = fmaT(0.5f, rl + rc[1], rc[0]);
+                }
+            } else if constexpr (PRE && TAIL == TAIL_RT) {
+                if (out_row && useful && lane_in) {
+                    const bool odd = (n & 1) != 0;
+                    float* dst = a.bc + (int64_t)(n >> 1) * a.Pbc + g;
+                    float v[K];
+                    bool put = true;
+                    if (!TR) {
+                        if (odd) {
+                            for (int j = 0; j < K; ++j) v[j] = 0.5f * (r_pair[j] + rc[j]);
+                        } else if (n == Nt) {
+                            for (int j = 0; j < K; ++j) v[j] = 0.5f * rc[j];
+                        } else {
+                            for (int j = 0; j < K; ++j) r_pair[j] = rc[j];
+                            put = false;
+                        }
+                    } else {
+                        if (odd) {
+                            for (int j = 0; j < K; ++j) r_pair[j] = rc[j];
+                            put = false;
+                        } else if (n == Nt) {
+                            for (int j = 0; j < K; ++j) v[j] = 0.5f * rc[j];
+                        } else {
+                            for (int j = 0; j < K; ++j) v[j] = 0.5f * (rc[j] + r_pair[j]);
+                        }
+                    }
+                    if (put) *reinterpret_cast<float2*>(dst) = make_float2(v[0], v[1]);
+                }
             }
         }
-    }
-    }
+        }
+    };
+    const bool special = TR ? (first == Nt || n0 == 0) : (first <= 1);
+    if (!STMG_SPLIT_LOOP || special)
+        stream(std::true_type{});
+    else
+        stream(std::false_type{});
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
     if (lane == 0) a.parts[wave] = acc;
