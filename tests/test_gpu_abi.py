@@ -194,9 +194,11 @@ def test_mixed_solve_after_a_diverged_one_matches_a_fresh_handle(cuda):
     b.close()
 
 
-@pytest.mark.parametrize("precision,fused", [("fp64", 1), ("fp64", 2), ("fp64", 0),
-                                             ("mixed", 1), ("mixed", 0)])
-def test_level_timing_reports_every_level_and_changes_no_bit(precision, fused, cuda):
+@pytest.mark.parametrize("precision,fused,extra", [
+    ("fp64", 1, {}), ("fp64", 2, {}), ("fp64", 0, {}), ("mixed", 1, {}), ("mixed", 0, {}),
+    ("fp64", 1, {"reassembly": 3}), ("fp64", 1, {"interp": 1}), ("mixed", 1, {"reassembly": 3})],
+    ids=["fp64-1", "fp64-2", "fp64-0", "mixed-1", "mixed-0", "P", "B", "P-mixed"])
+def test_level_timing_reports_every_level_and_changes_no_bit(precision, fused, extra, cuda):
     """time_levels records events between the passes only: the iterates and the
     history are those of an untimed handle, bit for bit; every level that runs its own
     passes reports time (levels inside the single-workgroup tail count on its first
@@ -205,7 +207,7 @@ def test_level_timing_reports_every_level_and_changes_no_bit(precision, fused, c
     rho = np.ones(512)
     prob = B.Problem(512, 1024, k_ins=1e-3)
     prec = B.STMG_FP64 if precision == "fp64" else B.STMG_MIXED
-    opts = dict(nu=2, precision=prec, fused=fused)
+    opts = dict(nu=2, precision=prec, fused=fused, max_cycles=300, **extra)
     a = B.Solver(prob, to_dev(rho, cuda), time_levels=1, **opts)
     b = B.Solver(prob, to_dev(rho, cuda), **opts)
     ua, sa = a.solve_forward()
@@ -218,7 +220,7 @@ def test_level_timing_reports_every_level_and_changes_no_bit(precision, fused, c
     tail = a.info()["tail_level"]
     n = sa.n_levels
     own = range(n) if tail < 0 else range(tail + 1)
-    print(f"{precision} fused={fused}: levels {n}, tail {tail}, ms per cycle " +
+    print(f"{precision} fused={fused} {extra}: levels {n}, tail {tail}, ms per cycle " +
           " ".join(f"{x:.3f}" for x in sa.level_ms))
     assert len(sa.level_ms) == n
     assert all(sa.level_ms[l] > 0 for l in own)

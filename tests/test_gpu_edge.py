@@ -55,13 +55,16 @@ def test_edge_grids_match_oracle(case, fused, transpose, cuda):
 
 @pytest.mark.parametrize("case", EDGE, ids=[c[0] for c in EDGE])
 @pytest.mark.parametrize("transpose", [0, 1])
-def test_edge_grids_mixed_precision(case, transpose, cuda):
+@pytest.mark.parametrize("inner", [1, 4, 8])
+def test_edge_grids_mixed_precision(case, transpose, inner, cuda):
     """FP32 inner V-cycles in FP64 defect correction reach the same 1e-10 residual and
-    the direct solution on the same grids."""
+    the direct solution on the same grids, with 1, 4 (the default) or 8 inner cycles per
+    correction (the fused finest-level passes: nu = 2)."""
     from paper_2505_10168_amd import binding as B
     _, rho, n_t, kmin, extra = case
     prob = B.Problem(len(rho), n_t, k_ins=kmin)
-    s = B.Solver(prob, to_dev(rho, cuda), nu=2, precision=B.STMG_MIXED, max_cycles=400, **extra)
+    s = B.Solver(prob, to_dev(rho, cuda), nu=2, precision=B.STMG_MIXED, max_cycles=400,
+                 inner_cycles=inner, **extra)
     mat, lv, h = oracle_setup(rho, n_t, kmin, nu=2, **extra)
     b = O.load_vector(lv, 1.0)
     if transpose:
