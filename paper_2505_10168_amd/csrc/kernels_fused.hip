@@ -53,6 +53,9 @@ constexpr int kWavesPerBlock = 4;
 #ifndef STMG_BIG_LEVEL_BYTES
 #define STMG_BIG_LEVEL_BYTES 268435456.0
 #endif
+#ifndef STMG_ZERO_FIRST
+#define STMG_ZERO_FIRST 1   // first step of a zero-start chain as a scaled copy of b
+#endif
 #ifndef STMG_SPLIT_LOOP
 #define STMG_SPLIT_LOOP 1   // 0: one copy of the streaming loop, with the row-0 tests
 #endif
@@ -254,7 +257,12 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
     const int rows = Nt + 1;
     const int n0 = wt * a.seg;
     const int n1 = min(rows, n0 + a.seg);   // output rows [n0, n1)
-    constexpr int WCHAIN = S + (TAIL != TAIL_NONE ? 1 : 0);
+    // A chain with S1 > 0 starts from u = 0 (it redoes a smoothing from zero): its first
+    // step is y = (omega / J_ii) b, since with a zero iterate and a zero coupled row every
+    // stencil term is +0; the same value, no stencil work, and no previous row needed, so
+    // the segment starts one row later.
+    constexpr bool ZF = STMG_ZERO_FIRST && S1 > 0;
+    constexpr int WCHAIN = S + (TAIL != TAIL_NONE ? 1 : 0) - (ZF ? 1 : 0);
     constexpr int WMID = MID ? S1 + S2 + 1 : 0;
     constexpr int WARM = WCHAIN > WMID ? WCHAIN : WMID;
     const int first = TR ? min(Nt, n1 - 1 + WARM) : max(0, n0 - WARM);
@@ -348,7 +356,13 @@ __device__ __forceinline__ void fused_body(const LevelView<T>& L, const FusedArg
 #pragma unroll
                     for (int k = k0; k < k1; ++k) {
                         T y[K];
-                        row_step<T, K, true, DIR>(L, C, x, prev[k], bb, y);
+                        if (ZF && k == 0) {
+#pragma unroll
+                            for (int j = 0; j < K; ++j)
+                                y[j] = jacobi_update<T>(T(0), DIR ? L.wW : C.wd[j], bb[j]);
+                        } else {
+                            row_step<T, K, true, DIR>(L, C, x, prev[k], bb, y);
+                        }
 #pragma unroll
                         for (int j = 0; j < K; ++j) {
                             prev[k][j] = x[j];
@@ -916,6 +930,30 @@ void dispatch_sweeps(int S, int tail, const LevelView<T>& L, const FusedArgs<T>&
     }
 }
 
+// Pre-smoothing of a coarse level from a zero start, its residual and restriction: the S
+// steps run as a chain from zero (S1 = S), whose first step needs no stencil and no
+// previous row.  Coarse levels only (k_fused).
+template <typename T, int TR, int S>
+void launch_zero_pre(int tail, const LevelView<T>& L, const FusedArgs<T>& a, hipStream_t s) {
+    const dim3 grid((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock), block(kWave * kWavesPerBlock);
+    if (tail == TAIL_RX)
+        hipLaunchKernelGGL((k_fused<T, TR, S, 0, 0, 0, 0, TAIL_RX>), grid, block, 0, s, L, a);
+    else
+        hipLaunchKernelGGL((k_fused<T, TR, S, 0, 0, 0, 0, TAIL_RT>), grid, block, 0, s, L, a);
+}
+
+template <typename T, int TR>
+void dispatch_zero_pre(int S, int tail, const LevelView<T>& L, const FusedArgs<T>& a, hipStream_t s) {
+    switch (S) {
+        case 1: launch_zero_pre<T, TR, 1>(tail, L, a, s); break;
+        case 2: launch_zero_pre<T, TR, 2>(tail, L, a, s); break;
+        case 3: launch_zero_pre<T, TR, 3>(tail, L, a, s); break;
+        case 4: launch_zero_pre<T, TR, 4>(tail, L, a, s); break;
+        case 5: launch_zero_pre<T, TR, 5>(tail, L, a, s); break;
+        default: launch_zero_pre<T, TR, 6>(tail, L, a, s); break;
+    }
+}
+
 // Post-smoothing from a zero start that first redoes the S pre-smoothing steps (from
 // zero, on the level's own b) instead of reading their stored result.
 template <typename T, int TR>
@@ -1120,6 +1158,12 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
         } else {
             return -1;
         }
+    }
+    if (STMG_ZERO_FIRST && fp.zero_in && a.head == 0 && S2 > 0 && !fp.fine &&
+        (tail == TAIL_RX || tail == TAIL_RT)) {
+        if (fp.trans) dispatch_zero_pre<T, 1>(S2, tail, L, a, s);
+        else dispatch_zero_pre<T, 0>(S2, tail, L, a, s);
+        return G.nwaves;
     }
     if (fp.trans)
         dispatch_sweeps<T, 1>(S2, tail, L, a, lc, s);
