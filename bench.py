@@ -368,6 +368,8 @@ def main():
                     help="run the Section 7 design loop on an N x N grid instead")
     ap.add_argument("--design-cycles", type=int, default=200)
     ap.add_argument("--cold", action="store_true", help="design loop with cold restarts")
+    ap.add_argument("--timed-every", type=int, default=TIMED_EVERY,
+                    help="time the fine passes of every k-th V-cycle with HIP events")
     ap.add_argument("--no-levels", action="store_true",
                     help="skip the level-by-level timing of one forward solve")
     args = ap.parse_args()
@@ -401,7 +403,7 @@ def main():
     concurrent = (args.concurrent or (conc_default and not args.sequential)) and not args.no_adjoint
     s_fwd = torch.cuda.Stream(device=dev) if concurrent else None
     s_adj = torch.cuda.Stream(device=dev) if concurrent else None
-    opts = dict(nu=nu, precision=precision, fused=args.fused, time_kernels=TIMED_EVERY,
+    opts = dict(nu=nu, precision=precision, fused=args.fused, time_kernels=args.timed_every,
                 interp=B.STMG_INTERP_B if args.interp == "B" else B.STMG_INTERP_C,
                 reassembly="RKDP".index(args.reassembly))
     solver = B.Solver(prob, rho, stream=s_fwd, **opts)
@@ -551,7 +553,7 @@ def main():
             "avg_launch_us": avg_us,
             "bytes_per_launch": kern_bytes / launches if launches else None,
             "share_of_solve_time": fine_share,
-            "timed_every_nth_cycle": TIMED_EVERY,
+            "timed_every_nth_cycle": args.timed_every,
             "stream_GBs": rates,
             "copy_GBs": copy_gbs,
             "copy_frac": (achieved / copy_gbs) if achieved else None,
