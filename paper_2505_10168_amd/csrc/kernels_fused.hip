@@ -62,6 +62,9 @@ constexpr int kWavesPerBlock = 4;
 #ifndef STMG_MIN_SEGMENT
 #define STMG_MIN_SEGMENT 2
 #endif
+#ifndef STMG_SINGLE_ROW_MAX_WAVES
+#define STMG_SINGLE_ROW_MAX_WAVES 640   // 2-row segments giving at most this many waves: 1-row
+#endif
 constexpr int kPrefetchRows = STMG_PREFETCH_ROWS;   // rows in flight per wave (register ring)
 constexpr int kXcds = 8;     // accelerator complex dies of an MI355X
 constexpr int kMaxFused = 6; // Jacobi steps one pass can fuse
@@ -833,8 +836,12 @@ struct Geometry {
     int HL, U, xw, seg, nwaves;
 };
 
+// even_seg: segments of an even number of time levels (a t restriction pairs the levels
+// 2J, 2J+1 inside one wave's segment).  Other passes on levels small enough that even
+// the shortest even segments leave SIMDs idle take single-level segments: each wave then
+// walks one row fewer of its serial chain, which is what bounds those launches.
 template <typename T>
-Geometry geometry(int N, int Nt, int sweeps, bool fine) {
+Geometry geometry(int N, int Nt, int sweeps, bool fine, bool even_seg = true) {
     constexpr int K = Lanes<T>::K;
     Geometry G;
     // Halo lanes: ceil((S+2)/K), rounded up so that the useful strip of every wave is
@@ -861,6 +868,7 @@ Geometry geometry(int N, int Nt, int sweeps, bool fine) {
     if (seg < min_seg) seg = min_seg;
     if (seg > 1024) seg = 1024;
     if (seg & 1) ++seg;
+    if (!even_seg && seg == 2 && G.xw * ((rows + 1) / 2) <= STMG_SINGLE_ROW_MAX_WAVES) seg = 1;
     G.seg = (int)seg;
     G.nwaves = (int)(G.xw * ((rows + G.seg - 1) / G.seg));
     return G;
@@ -1055,8 +1063,9 @@ int fused_geometry(int N, int Nt, int sweeps, bool fp32, bool fine, int* strip_c
 }
 
 int fused_parts(int N, int Nt, int sweeps) {
-    // the FP32 geometry (wider lanes) never needs more waves than the FP64 one
-    return geometry<double>(N, Nt, sweeps, true).nwaves;
+    // the FP32 geometry (wider lanes) never needs more waves than the FP64 one, and
+    // odd segments never fewer
+    return geometry<double>(N, Nt, sweeps, true, false).nwaves;
 }
 
 template <typename T>
@@ -1087,7 +1096,7 @@ int launch_fused(const LevelView<T>& L, const FusedPass& fp, const T* u, const T
     } else if (S3 != 0) {
         return -1;
     }
-    Geometry G = geometry<T>(L.N, L.Nt, chain, fp.fine != 0);
+    Geometry G = geometry<T>(L.N, L.Nt, chain, fp.fine != 0, fp.tail == 't');
     FusedArgs<T> a;
     a.u = u;
     a.b = b;
