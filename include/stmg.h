@@ -329,8 +329,11 @@ int stmg_stream_calibrate(const double* d_a, const double* d_b, double s, double
 /* Launch geometry of one fused streaming pass of `sweeps` Jacobi steps (0..6) on an
  * n_el x n_t level (fp32: the FP32 kernels; fine: the finest level's kernels): each
  * wavefront owns a strip of *strip_cols columns and a segment of *seg_rows time levels
- * (*strips strips along x, *waves wavefronts).  Host-only; a testing aid, so that
- * sampled checks can be placed across the boundaries between wavefronts. */
+ * (*strips strips along x, *waves wavefronts).  This is the geometry of passes that end
+ * with a t restriction, and of every pass on a level whose segments are longer than two
+ * time levels; other passes on small levels (2-row segments giving at most 640
+ * wavefronts) take 1-row segments.  Host-only; a testing aid, so that sampled checks can
+ * be placed across the boundaries between wavefronts. */
 int stmg_pass_geometry(int n_el, int n_t, int sweeps, int fp32, int fine, int* strip_cols,
                        int* strips, int* seg_rows, int* waves);
 
