@@ -219,3 +219,23 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[name, "sizeof"] == C.sizeof(st), name
         for f, _ in st._fields_:
             assert got[name, f] == getattr(st, f).offset, (name, f)
+
+
+@pytest.mark.parametrize("n_el,n_t,sweeps,fp32,fine", [
+    (8192, 65536, 2, 0, 1), (8192, 65536, 4, 0, 1), (4096, 65536, 2, 1, 1), (1024, 4096, 5, 0, 1),
+    (512, 2048, 5, 0, 0), (64, 64, 5, 0, 0), (7, 128, 2, 0, 0), (3, 5, 6, 1, 0)])
+def test_pass_geometry_covers_the_level(n_el, n_t, sweeps, fp32, fine):
+    """The launch geometry of a fused pass (host-only): the useful strips cover every
+    node column, the halo is at least the chain's reach on each side and keeps the
+    useful strip a whole number of 128-byte lines, the time segments are even (a t
+    restriction pairs levels inside one segment) and cover every time level, and the
+    wavefront count is strips x segments."""
+    g = B.stmg_pass_geometry(n_el, n_t, sweeps, bool(fp32), bool(fine))
+    k = 4 if fp32 else 2                       # columns per lane (16 bytes)
+    u, xw, seg, waves = g["strip_cols"], g["strips"], g["seg_rows"], g["waves"]
+    halo_lanes = (64 - u // k) // 2
+    assert u % k == 0 and halo_lanes * k >= sweeps + 2
+    assert (u * (8 if not fp32 else 4)) % 128 == 0
+    assert xw * u >= n_el + 1 > (xw - 1) * u
+    assert seg >= 2 and seg % 2 == 0
+    assert waves == xw * -(-(n_t + 1) // seg)
